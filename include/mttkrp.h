@@ -1,0 +1,161 @@
+/*
+ * mttkrp.h -- C ABI of an MI355X (gfx950) sparse MTTKRP / CP-ALS library.
+ *
+ * The operation (Sec. II-A, Eq. (1) and the elementwise update after it):
+ * for an N-mode sparse tensor X with nonzeros (c_0..c_{N-1}, val) and dense
+ * factor matrices A_m (I_m x R), the MTTKRP along mode n is
+ *
+ *     M_n[i, r] = sum over nonzeros with c_n == i of  val * prod_{m != n} A_m[c_m, r].
+ *
+ * CP-ALS (Sec. II-A, CPD paragraph) computes it along every mode in turn and
+ * re-solves each factor from it.
+ *
+ * Following the paper's tensor format (Sec. III-C, "mode-specific copies"),
+ * mttkrp_layout_build keeps one copy of the nonzeros per output mode, each
+ * ordered by its output index and split into nonzero-balanced partitions
+ * (Sec. III-B, load-balancing scheme 2), and the per-mode kernel accumulates
+ * every output row on chip and writes it once (Sec. IV-B), with no global
+ * atomics.
+ *
+ * Conventions for every call:
+ *  - Indices are 0-based.  Matrices are row-major with R contiguous values per
+ *    row.  "host" pointers are CPU memory, "device" pointers are memory of the
+ *    current HIP device.
+ *  - Every call returns a status and never aborts.  Arguments are validated
+ *    on the host before anything is enqueued; mttkrp_last_error() then holds
+ *    a message (per calling thread).  Errors raised by the HIP runtime are
+ *    reported as MTTKRP_EHIP, at the latest by the next call.
+ *  - Device work is enqueued on `stream` (0 = the null stream) and is
+ *    asynchronous unless stated otherwise.  A handle owns scratch memory
+ *    (carry rows, CP-ALS workspace), so one handle must be used by one stream
+ *    at a time; different handles are independent.
+ *  - Results are reproducible bit for bit for a fixed handle, R and dtype:
+ *    no atomics, fixed summation order.
+ */
+#ifndef MTTKRP_H
+#define MTTKRP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mttkrp_layout* mttkrp_handle; /* opaque; owns all device copies and workspace */
+
+typedef enum {
+    MTTKRP_OK = 0,
+    MTTKRP_EINVAL = 1,        /* null pointer, bad N / mode / R / dims, or handle misuse */
+    MTTKRP_ERANGE = 2,        /* a coordinate is >= the dimension of its mode */
+    MTTKRP_ENOMEM = 3,        /* footprint over the budget (not a "small tensor"), or allocation failed */
+    MTTKRP_EUNSUPPORTED = 4,  /* N or R outside the compiled set */
+    MTTKRP_ENOTSPD = 5,       /* CP-ALS: a normal-equation matrix is not positive definite */
+    MTTKRP_EHIP = 6           /* HIP runtime error */
+} mttkrp_status;
+
+/* Factor storage used for the row gathers. */
+enum { MTTKRP_FP32 = 0, MTTKRP_BF16 = 1 };
+
+/* Limits: 3 <= N <= MTTKRP_MAX_MODES, every dim in [1, 2^31 - 1], nnz < 2^32,
+ * R in {16, 32, 64}. */
+#define MTTKRP_MAX_MODES 8
+
+typedef struct {
+    int parts_per_cu;          /* workgroup partitions per compute unit for the MTTKRP launch; 0 = default (8) */
+    int factor_dtype;          /* gather precision used inside cpd_als_iter: MTTKRP_FP32 or MTTKRP_BF16 */
+    int max_R;                 /* largest R the handle will run with (16, 32 or 64); sizes the workspace; 0 = 64 */
+    uint64_t hbm_budget_bytes; /* refuse to build (MTTKRP_ENOMEM) when the footprint exceeds this; 0 = no budget */
+    int host_only;             /* 1: build the host arrays only (for inspection); no device memory, runs refused */
+} mttkrp_opts;
+
+/* Fill `o` with the defaults listed above. */
+void mttkrp_opts_default(mttkrp_opts* o);
+
+/* Device bytes a handle for this tensor would hold: N mode copies (Sec. III-C:
+ * the paper's memory formula is N * nnz * bits-per-nonzero; here each copy
+ * stores N-1 uint32 input indices, one fp32 value, 1 bit of row-start flag
+ * and a 32-bit row index per 32 nonzeros, plus 4 bytes per output row) and
+ * the workspace sized by opts->max_R and opts->factor_dtype.  Host only; opts
+ * may be NULL.  Used for admission before anything is built. */
+mttkrp_status mttkrp_footprint(const uint32_t* dims /* host, N */, int N, uint64_t nnz,
+                               const mttkrp_opts* opts, uint64_t* bytes /* host, out */);
+
+/* Build the N mode-specific copies (Sec. III-B/III-C) of a COO tensor.
+ *   coo_idx: host, nnz x N uint32, row-major (nonzero k at coo_idx[k*N .. k*N+N-1])
+ *   vals:    host, nnz float
+ *   dims:    host, N
+ * The inputs are borrowed for the call only (validated and copied).  Duplicate
+ * coordinates are allowed and add up.  nnz == 0 is valid (all outputs zero).
+ * Sorting and partitioning run on the host; the copies are then uploaded on
+ * `stream` and the call returns after the upload has completed.
+ * On success *out receives a handle to release with mttkrp_layout_free. */
+mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, uint64_t nnz,
+                                  const uint32_t* dims, int N, const mttkrp_opts* opts,
+                                  hipStream_t stream, mttkrp_handle* out);
+
+/* Device bytes held by the handle (0 for a host-only handle). */
+uint64_t mttkrp_layout_bytes(mttkrp_handle h);
+
+/* MTTKRP along `mode` (Alg. 1's body for one mode; Alg. 2 per partition).
+ *   factors: host array of N device pointers; factors[m] is A_m, I_m x R fp32.
+ *            factors[mode] is not read and may be NULL.
+ *   out:     device, I_mode x R fp32, overwritten (rows without nonzeros get 0).
+ * R must be 16, 32 or 64 and <= the handle's max_R. */
+mttkrp_status mttkrp_run(mttkrp_handle h, int mode, const float* const* factors, float* out, int R,
+                         hipStream_t stream);
+
+/* Same, with bfloat16 factor rows (uint16 bit patterns, I_m x R) gathered and
+ * multiplied in FP32 with FP32 accumulation. */
+mttkrp_status mttkrp_run_bf16(mttkrp_handle h, int mode, const uint16_t* const* factors, float* out, int R,
+                              hipStream_t stream);
+
+/* Prepare CP-ALS state for `factors` (host array of N device pointers to
+ * I_m x R fp32): the FP64 Gram matrices A_m^T A_m, and the bf16 copies when
+ * opts->factor_dtype is MTTKRP_BF16.  Call before the first cpd_als_iter and
+ * again whenever the factors were changed by anything but cpd_als_iter. */
+mttkrp_status cpd_als_init(mttkrp_handle h, const float* const* factors, int R, hipStream_t stream);
+
+/* One CP-ALS sweep over all modes (textbook ALS, see Sec. II-A): for each
+ * mode n, V = Hadamard product of the other Gram matrices (FP64), M = MTTKRP
+ * along n, A_n = M V^{-1} by Cholesky (FP64 arithmetic, fp32 store), columns
+ * normalised to unit 2-norm with the norms in lambda, Gram of A_n updated.
+ *   factors: host array of N device pointers, updated in place
+ *   lambda:  device, R doubles (out: the norms of the last mode)
+ *   fit_out: device, 1 double (out: 1 - |X - Xhat| / |X|), may be NULL
+ * Returns MTTKRP_ENOTSPD if a V is not positive definite (detected on the
+ * device; reported by this call, which then synchronises the stream). */
+mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
+                           hipStream_t stream);
+
+/* Release a handle and all of its device memory (synchronises the device).
+ * NULL is ignored. */
+void mttkrp_layout_free(mttkrp_handle h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mttkrp_last_error(void);
+
+/* Host view of one mode copy of a host-only handle (for inspection and tests).
+ * All pointers stay valid until mttkrp_layout_free. */
+typedef struct {
+    uint64_t nnz;                 /* nonzeros */
+    uint64_t nnz_pad;             /* array length: nnz rounded up to a multiple of 32 */
+    uint64_t nrows_nz;            /* output rows with at least one nonzero */
+    uint64_t nempty;              /* output rows without nonzeros */
+    int n_in;                     /* N - 1 */
+    int in_modes[MTTKRP_MAX_MODES - 1];      /* the input modes, increasing */
+    const uint32_t* idx[MTTKRP_MAX_MODES - 1]; /* idx[j][k]: coordinate in mode in_modes[j] of nonzero k */
+    const float* val;             /* value of nonzero k */
+    const uint32_t* winfo;        /* 2 words per 32 nonzeros: row-start bits, row ordinal of the first */
+    const uint32_t* row_id;       /* output row of each nonempty row, increasing (nrows_nz) */
+    const uint32_t* empty_rows;   /* rows without nonzeros, increasing (nempty) */
+    const uint64_t* src_pos;      /* position in the caller's COO input of nonzero k */
+} mttkrp_mode_view;
+
+mttkrp_status mttkrp_layout_view(mttkrp_handle h, int mode, mttkrp_mode_view* v);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTTKRP_H */

@@ -1,0 +1,262 @@
+"""ctypes binding of the C ABI in ``include/mttkrp.h`` (argument marshalling only).
+
+Every function has the C name.  Device buffers are passed as ``torch.Tensor``
+objects on the current HIP device (only their pointers are used) and streams
+as ``torch.cuda.Stream`` objects or raw ``hipStream_t`` integers; host
+buffers are numpy arrays.  All computation happens in the HIP library; if it
+is not built, importing this module raises instead of falling back.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmttkrp_hip.so")
+
+MTTKRP_OK, MTTKRP_EINVAL, MTTKRP_ERANGE, MTTKRP_ENOMEM, MTTKRP_EUNSUPPORTED, MTTKRP_ENOTSPD, MTTKRP_EHIP = range(7)
+MTTKRP_FP32, MTTKRP_BF16 = 0, 1
+MTTKRP_MAX_MODES = 8
+STATUS_NAMES = {0: "MTTKRP_OK", 1: "MTTKRP_EINVAL", 2: "MTTKRP_ERANGE", 3: "MTTKRP_ENOMEM",
+                4: "MTTKRP_EUNSUPPORTED", 5: "MTTKRP_ENOTSPD", 6: "MTTKRP_EHIP"}
+
+# Every symbol the header declares.
+EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "mttkrp_layout_bytes", "mttkrp_run",
+            "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
+            "mttkrp_layout_view"]
+
+
+class MttkrpError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class mttkrp_opts(ctypes.Structure):
+    _fields_ = [("parts_per_cu", ctypes.c_int), ("factor_dtype", ctypes.c_int), ("max_R", ctypes.c_int),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int)]
+
+
+class mttkrp_mode_view(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_uint64), ("nnz_pad", ctypes.c_uint64), ("nrows_nz", ctypes.c_uint64),
+                ("nempty", ctypes.c_uint64), ("n_in", ctypes.c_int),
+                ("in_modes", ctypes.c_int * (MTTKRP_MAX_MODES - 1)),
+                ("idx", ctypes.POINTER(ctypes.c_uint32) * (MTTKRP_MAX_MODES - 1)),
+                ("val", ctypes.POINTER(ctypes.c_float)), ("winfo", ctypes.POINTER(ctypes.c_uint32)),
+                ("row_id", ctypes.POINTER(ctypes.c_uint32)), ("empty_rows", ctypes.POINTER(ctypes.c_uint32)),
+                ("src_pos", ctypes.POINTER(ctypes.c_uint64))]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2503_18198_amd.build.build() "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32p, f32p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)
+    lib.mttkrp_opts_default.argtypes = [ctypes.POINTER(mttkrp_opts)]
+    lib.mttkrp_opts_default.restype = None
+    lib.mttkrp_footprint.argtypes = [u32p, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(mttkrp_opts),
+                                     ctypes.POINTER(ctypes.c_uint64)]
+    lib.mttkrp_layout_build.argtypes = [u32p, f32p, ctypes.c_uint64, u32p, ctypes.c_int, ctypes.POINTER(mttkrp_opts),
+                                        vp, ctypes.POINTER(vp)]
+    lib.mttkrp_layout_bytes.argtypes = [vp]
+    lib.mttkrp_layout_bytes.restype = ctypes.c_uint64
+    lib.mttkrp_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
+    lib.mttkrp_run_bf16.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
+    lib.cpd_als_init.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.cpd_als_iter.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.c_int, vp, vp]
+    lib.mttkrp_layout_free.argtypes = [vp]
+    lib.mttkrp_layout_free.restype = None
+    lib.mttkrp_last_error.argtypes = []
+    lib.mttkrp_last_error.restype = ctypes.c_char_p
+    lib.mttkrp_layout_view.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mttkrp_mode_view)]
+    for name in ("mttkrp_footprint", "mttkrp_layout_build", "mttkrp_run", "mttkrp_run_bf16", "cpd_als_init",
+                 "cpd_als_iter", "mttkrp_layout_view"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int):
+    if status != MTTKRP_OK:
+        raise MttkrpError(status, _lib.mttkrp_last_error().decode(errors="replace"))
+
+
+def mttkrp_last_error() -> str:
+    return _lib.mttkrp_last_error().decode(errors="replace")
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream) if torch.cuda.is_available() else 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def mttkrp_opts_default(**overrides) -> mttkrp_opts:
+    o = mttkrp_opts()
+    _lib.mttkrp_opts_default(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def _opts(opts) -> Optional[mttkrp_opts]:
+    if opts is None or isinstance(opts, mttkrp_opts):
+        return opts
+    return mttkrp_opts_default(**opts)
+
+
+def _dims(dims) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(dims, dtype=np.uint32))
+
+
+def mttkrp_footprint(dims: Sequence[int], nnz: int, opts=None) -> int:
+    d = _dims(dims)
+    out = ctypes.c_uint64()
+    o = _opts(opts)
+    _check(_lib.mttkrp_footprint(d.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), d.shape[0], int(nnz),
+                                 ctypes.byref(o) if o is not None else None, ctypes.byref(out)))
+    return int(out.value)
+
+
+class Layout:
+    """Owns an ``mttkrp_handle``; released by ``mttkrp_layout_free`` or on collection."""
+
+    def __init__(self, ptr: int, dims, nnz: int, host_only: bool):
+        self._ptr = ptr
+        self.dims = tuple(int(x) for x in dims)
+        self.nnz = int(nnz)
+        self.host_only = host_only
+
+    @property
+    def ptr(self) -> int:
+        if not self._ptr:
+            raise MttkrpError(MTTKRP_EINVAL, "layout already freed")
+        return self._ptr
+
+    def free(self):
+        if self._ptr:
+            _lib.mttkrp_layout_free(ctypes.c_void_p(self._ptr))
+            self._ptr = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def mttkrp_layout_build(idx: np.ndarray, vals: np.ndarray, dims: Sequence[int], opts=None, stream=None) -> Layout:
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    vals = np.ascontiguousarray(vals, dtype=np.float32).reshape(-1)
+    d = _dims(dims)
+    if idx.ndim != 2 or idx.shape[1] != d.shape[0] or idx.shape[0] != vals.shape[0]:
+        raise MttkrpError(MTTKRP_EINVAL, "idx must be (nnz, N) with N = len(dims) and len(vals) = nnz")
+    o = _opts(opts)
+    host_only = bool(o.host_only) if o is not None else False
+    h = ctypes.c_void_p()
+    _check(_lib.mttkrp_layout_build(idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                    vals.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), idx.shape[0],
+                                    d.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), d.shape[0],
+                                    ctypes.byref(o) if o is not None else None,
+                                    ctypes.c_void_p(0 if host_only else _stream(stream)), ctypes.byref(h)))
+    return Layout(h.value, dims, idx.shape[0], host_only)
+
+
+def mttkrp_layout_bytes(h: Layout) -> int:
+    return int(_lib.mttkrp_layout_bytes(ctypes.c_void_p(h.ptr)))
+
+
+def mttkrp_layout_free(h: Layout):
+    h.free()
+
+
+def _ptr_array(tensors, n):
+    arr = (ctypes.c_void_p * n)()
+    for m, t in enumerate(tensors):
+        arr[m] = None if t is None else int(t.data_ptr())
+    return arr
+
+
+def _check_factor(t, rows, R, dtype_name, what):
+    import torch
+    want = torch.float32 if dtype_name == "fp32" else torch.bfloat16
+    if t.dtype != want or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (rows, R):
+        raise MttkrpError(MTTKRP_EINVAL, f"{what} must be a contiguous {want} device tensor of shape ({rows}, {R})")
+
+
+def mttkrp_run(h: Layout, mode: int, factors, out, R: Optional[int] = None, stream=None):
+    """out <- MTTKRP of the layout along ``mode`` with fp32 ``factors`` (list of N
+    device tensors; the entry at ``mode`` may be None)."""
+    _run(_lib.mttkrp_run, "fp32", h, mode, factors, out, R, stream)
+
+
+def mttkrp_run_bf16(h: Layout, mode: int, factors, out, R: Optional[int] = None, stream=None):
+    """As mttkrp_run, with bfloat16 factor tensors."""
+    _run(_lib.mttkrp_run_bf16, "bf16", h, mode, factors, out, R, stream)
+
+
+def _run(fn, dt, h, mode, factors, out, R, stream):
+    import torch
+    N = len(h.dims)
+    if not 0 <= int(mode) < N:
+        raise MttkrpError(MTTKRP_EINVAL, f"mode {mode} out of range for a {N}-mode tensor")
+    if len(factors) != N:
+        raise MttkrpError(MTTKRP_EINVAL, f"need {N} factors (entry {mode} may be None)")
+    if R is None:
+        R = int(out.shape[1])
+    for m, f in enumerate(factors):
+        if m != mode:
+            _check_factor(f, h.dims[m], R, dt, f"factor {m}")
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or tuple(out.shape) != (h.dims[mode], R):
+        raise MttkrpError(MTTKRP_EINVAL, f"out must be a contiguous float32 device tensor of shape ({h.dims[mode]}, {R})")
+    _check(fn(ctypes.c_void_p(h.ptr), int(mode), _ptr_array(factors, N), ctypes.c_void_p(out.data_ptr()), int(R),
+              ctypes.c_void_p(_stream(stream))))
+
+
+def cpd_als_init(h: Layout, factors, R: int, stream=None):
+    N = len(h.dims)
+    for m, f in enumerate(factors):
+        _check_factor(f, h.dims[m], R, "fp32", f"factor {m}")
+    _check(_lib.cpd_als_init(ctypes.c_void_p(h.ptr), _ptr_array(factors, N), int(R), ctypes.c_void_p(_stream(stream))))
+
+
+def cpd_als_iter(h: Layout, factors, lam, R: int, fit_out=None, stream=None):
+    import torch
+    N = len(h.dims)
+    for m, f in enumerate(factors):
+        _check_factor(f, h.dims[m], R, "fp32", f"factor {m}")
+    if lam.dtype != torch.float64 or not lam.is_cuda or lam.numel() < R:
+        raise MttkrpError(MTTKRP_EINVAL, "lambda must be a float64 device tensor with R entries")
+    if fit_out is not None and (fit_out.dtype != torch.float64 or not fit_out.is_cuda):
+        raise MttkrpError(MTTKRP_EINVAL, "fit_out must be a float64 device tensor")
+    _check(_lib.cpd_als_iter(ctypes.c_void_p(h.ptr), _ptr_array(factors, N), ctypes.c_void_p(lam.data_ptr()), int(R),
+                             ctypes.c_void_p(fit_out.data_ptr() if fit_out is not None else 0),
+                             ctypes.c_void_p(_stream(stream))))
+
+
+def mttkrp_layout_view(h: Layout, mode: int) -> dict:
+    """Copies of the host arrays of one mode copy (host-only layouts)."""
+    v = mttkrp_mode_view()
+    _check(_lib.mttkrp_layout_view(ctypes.c_void_p(h.ptr), int(mode), ctypes.byref(v)))
+
+    def arr(p, n, dt):
+        if n == 0:
+            return np.zeros(0, dtype=dt)
+        return np.ctypeslib.as_array(p, shape=(int(n),)).astype(dt, copy=True)
+
+    return dict(nnz=int(v.nnz), nnz_pad=int(v.nnz_pad), nrows_nz=int(v.nrows_nz), nempty=int(v.nempty),
+                in_modes=[int(v.in_modes[j]) for j in range(v.n_in)],
+                idx=[arr(v.idx[j], v.nnz_pad, np.uint32) for j in range(v.n_in)],
+                val=arr(v.val, v.nnz_pad, np.float32), winfo=arr(v.winfo, 2 * (v.nnz_pad // 32), np.uint32),
+                row_id=arr(v.row_id, v.nrows_nz, np.uint32), empty_rows=arr(v.empty_rows, v.nempty, np.uint32),
+                src_pos=arr(v.src_pos, v.nnz, np.uint64))

@@ -1,0 +1,322 @@
+// CP-ALS update kernels (FP64 arithmetic).
+//
+// The paper computes CPD by alternating least squares around the MTTKRP and
+// normalises the factors (Sec. II-A).  The least-squares step is the
+// textbook one: A_n = M V^{-1} with V the Hadamard product of the other
+// factors' Gram matrices.  R <= 64 here, so V is tiny: its Cholesky factor
+// and inverse come from one workgroup, and the I_n x R products are
+// memory-bound row passes.  Every reduction writes per-block partials that a
+// second kernel adds in block order, so results repeat bit for bit.
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace mk {
+namespace {
+
+constexpr int kRowsTile = 256 / 16;   // rows per LDS tile in the Gram kernel (R >= 16)
+
+// Block b of `nblk` covers rows [b * rpb, min((b+1) * rpb, I)).
+__device__ __forceinline__ void block_rows(uint32_t I, uint32_t rpb, uint32_t& r0, uint32_t& r1)
+{
+    r0 = min((uint64_t)blockIdx.x * rpb, (uint64_t)I);
+    r1 = min((uint64_t)r0 + rpb, (uint64_t)I);
+}
+
+// part[b][r*R + c] = sum over the block's rows i of A[i][r] * A[i][c].
+__global__ __launch_bounds__(kWG) void gram_partial_kernel(const float* __restrict__ A, uint32_t I, int R,
+                                                           uint32_t rpb, double* __restrict__ part)
+{
+    __shared__ double tile[kRowsTile * 64];
+    const int tid = threadIdx.x;
+    const int RR = R * R;
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    uint32_t r0, r1;
+    block_rows(I, rpb, r0, r1);
+    const int T = kWG / R > kRowsTile ? kRowsTile : kWG / R;  // rows loaded per tile, one element per thread
+    for (uint32_t i0 = r0; i0 < r1; i0 += T) {
+        const uint32_t nrow = min((uint32_t)T, r1 - i0);
+        __syncthreads();
+        if (tid < (int)nrow * R) tile[tid] = (double)A[(uint64_t)i0 * R + tid];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = tid + j * kWG;
+            if (e < RR) {
+                const int r = e / R, c = e % R;
+                double s = 0.0;
+                for (uint32_t t = 0; t < nrow; ++t) s += tile[t * R + r] * tile[t * R + c];
+                acc[j] += s;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = tid + j * kWG;
+        if (e < RR) part[(uint64_t)blockIdx.x * RR + e] = acc[j];
+    }
+}
+
+// out[e] = sum over blocks b (in order) of part[b * K + e].  op 1: out[e] =
+// sqrt(sum), with 1 in place of 0 (column norms).
+__global__ __launch_bounds__(kWG) void reduce_partials_kernel(const double* __restrict__ part, int nblk, int K,
+                                                              double* __restrict__ out, int op)
+{
+    const int e = blockIdx.x * kWG + threadIdx.x;
+    if (e >= K) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(uint64_t)b * K + e];
+    if (op == 1) s = s > 0.0 ? sqrt(s) : 1.0;
+    out[e] = s;
+}
+
+// V = Hadamard product of all Gram matrices except `skip` (skip = -1: all).
+// reset_flag: clear the not-positive-definite flag at the start of a sweep.
+__global__ __launch_bounds__(kWG) void hadamard_kernel(const double* __restrict__ grams, int N, int skip, int R,
+                                                       double* __restrict__ V, double* flag, int reset_flag)
+{
+    const int RR = R * R;
+    for (int e = threadIdx.x; e < RR; e += kWG) {
+        double v = 1.0;
+        for (int m = 0; m < N; ++m)
+            if (m != skip) v *= grams[(uint64_t)m * RR + e];
+        V[e] = v;
+    }
+    if (reset_flag && threadIdx.x == 0) *flag = 0.0;
+}
+
+// Cholesky factor V = L L^T (lower, in LDS), L^{-1} by forward substitution
+// (one column per thread, kept in `scratch`), then W = L^{-T} L^{-1} = V^{-1}.
+// A non-positive pivot sets *flag = 1 and fills W with NaN.
+__global__ __launch_bounds__(kWG) void cholesky_inverse_kernel(const double* __restrict__ V, int R,
+                                                               double* __restrict__ W, double* __restrict__ scratch,
+                                                               double* flag)
+{
+    __shared__ double L[64 * 64];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int RR = R * R;
+    for (int e = tid; e < RR; e += kWG) L[e] = V[e];
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < R; ++j) {
+        if (tid == 0) {
+            double d = L[j * R + j];
+            for (int k = 0; k < j; ++k) d -= L[j * R + k] * L[j * R + k];
+            if (!(d > 0.0) || !isfinite(d)) {
+                bad = 1;
+                d = 1.0;
+            }
+            L[j * R + j] = sqrt(d);
+        }
+        __syncthreads();
+        const double djj = L[j * R + j];
+        for (int i = j + 1 + tid; i < R; i += kWG) {
+            double s = L[i * R + j];
+            for (int k = 0; k < j; ++k) s -= L[i * R + k] * L[j * R + k];
+            L[i * R + j] = s / djj;
+        }
+        __syncthreads();
+    }
+    // Column c of L^{-1}: x_i = 0 (i < c), x_c = 1 / L_cc, x_i = -(sum_{c<=k<i} L_ik x_k) / L_ii.
+    if (tid < R) {
+        const int c = tid;
+        for (int i = 0; i < c; ++i) scratch[i * R + c] = 0.0;
+        scratch[c * R + c] = 1.0 / L[c * R + c];
+        for (int i = c + 1; i < R; ++i) {
+            double s = 0.0;
+            for (int k = c; k < i; ++k) s += L[i * R + k] * scratch[k * R + c];
+            scratch[i * R + c] = -s / L[i * R + i];
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    // W[i][j] = sum_k Linv[k][i] * Linv[k][j], k >= max(i, j).
+    for (int e = tid; e < RR; e += kWG) {
+        const int i = e / R, j = e % R;
+        double s = 0.0;
+        for (int k = max(i, j); k < R; ++k) s += scratch[k * R + i] * scratch[k * R + j];
+        W[e] = bad ? __longlong_as_double(0x7ff8000000000000ll) : s;
+    }
+    if (tid == 0 && bad) *flag = 1.0;
+}
+
+// Rows of M W (FP64).  op 0: per-block column sums of squares -> part[b][c].
+// op 1: A[i][c] = (M W)[i][c] / lam[c], stored as fp32.
+__global__ __launch_bounds__(kWG) void mw_kernel(const float* __restrict__ M, const double* __restrict__ W, uint32_t I,
+                                                 int R, uint32_t rpb, int op, const double* __restrict__ lam,
+                                                 float* __restrict__ A, double* __restrict__ part)
+{
+    __shared__ double sW[64 * 64];
+    __shared__ double sM[kWG];
+    __shared__ double sred[kWG];
+    const int tid = threadIdx.x;
+    const int RR = R * R;
+    for (int e = tid; e < RR; e += kWG) sW[e] = W[e];
+    const int rows_per_pass = kWG / R;
+    const int c = tid % R;
+    const int ri = tid / R;
+    const double inv = op == 1 ? 1.0 / lam[c] : 0.0;
+    double colsq = 0.0;
+    uint32_t r0, r1;
+    block_rows(I, rpb, r0, r1);
+    for (uint32_t i0 = r0; i0 < r1; i0 += rows_per_pass) {
+        const uint32_t i = i0 + ri;
+        __syncthreads();
+        sM[tid] = i < r1 ? (double)M[(uint64_t)i * R + c] : 0.0;
+        __syncthreads();
+        if (i < r1) {
+            double s = 0.0;
+            for (int k = 0; k < R; ++k) s += sM[ri * R + k] * sW[k * R + c];
+            if (op == 0) colsq += s * s;
+            else A[(uint64_t)i * R + c] = (float)(s * inv);
+        }
+    }
+    if (op == 0) {
+        sred[tid] = colsq;
+        __syncthreads();
+        if (tid < R) {
+            double t = 0.0;
+            for (int j = 0; j < rows_per_pass; ++j) t += sred[j * R + tid];
+            part[(uint64_t)blockIdx.x * R + tid] = t;
+        }
+    }
+}
+
+// part[b][c] = sum over the block's rows of M[i][c] * A[i][c].
+__global__ __launch_bounds__(kWG) void coldot_kernel(const float* __restrict__ M, const float* __restrict__ A,
+                                                     uint32_t I, int R, uint32_t rpb, double* __restrict__ part)
+{
+    __shared__ double sred[kWG];
+    const int tid = threadIdx.x;
+    const int rows_per_pass = kWG / R;
+    const int c = tid % R;
+    const int ri = tid / R;
+    double s = 0.0;
+    uint32_t r0, r1;
+    block_rows(I, rpb, r0, r1);
+    for (uint32_t i = r0 + ri; i < r1; i += rows_per_pass)
+        s += (double)M[(uint64_t)i * R + c] * (double)A[(uint64_t)i * R + c];
+    sred[tid] = s;
+    __syncthreads();
+    if (tid < R) {
+        double t = 0.0;
+        for (int j = 0; j < rows_per_pass; ++j) t += sred[j * R + tid];
+        part[(uint64_t)blockIdx.x * R + tid] = t;
+    }
+}
+
+// fit = 1 - sqrt(max(0, |X|^2 + lam^T (*G) lam - 2 sum_r lam_r dot_r)) / |X|.
+__global__ __launch_bounds__(kWG) void fit_kernel(const double* __restrict__ dot, const double* __restrict__ lam,
+                                                  const double* __restrict__ grams, int N, int R, double normX2,
+                                                  double* fit_out, double* lam_out)
+{
+    __shared__ double sx[kWG];
+    __shared__ double sd[kWG];
+    const int tid = threadIdx.x;
+    const int RR = R * R;
+    double x = 0.0;
+    for (int e = tid; e < RR; e += kWG) {
+        double v = 1.0;
+        for (int m = 0; m < N; ++m) v *= grams[(uint64_t)m * RR + e];
+        x += lam[e / R] * v * lam[e % R];
+    }
+    sx[tid] = x;
+    sd[tid] = tid < R ? lam[tid] * dot[tid] : 0.0;
+    if (lam_out && tid < R) lam_out[tid] = lam[tid];
+    __syncthreads();
+    if (tid == 0) {
+        double xh = 0.0, inner = 0.0;
+        for (int j = 0; j < kWG; ++j) xh += sx[j];
+        for (int j = 0; j < R; ++j) inner += sd[j];
+        const double res = normX2 + xh - 2.0 * inner;
+        if (fit_out) *fit_out = 1.0 - sqrt(res > 0.0 ? res : 0.0) / sqrt(normX2);
+    }
+}
+
+// Round fp32 to bfloat16, nearest-even on the bit pattern; NaN stays NaN.
+__global__ __launch_bounds__(kWG) void cast_bf16_kernel(const float* __restrict__ A, uint64_t n,
+                                                        uint16_t* __restrict__ out)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kWG) {
+        const uint32_t b = __float_as_uint(A[i]);
+        uint16_t h;
+        if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) h = (uint16_t)((b >> 16) | 0x0040u);
+        else h = (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+        out[i] = h;
+    }
+}
+
+uint32_t nblocks_for(uint32_t I, int max_blocks, uint32_t& rpb)
+{
+    uint32_t nb = (I + 63) / 64;
+    if (nb > (uint32_t)max_blocks) nb = (uint32_t)max_blocks;
+    if (nb < 1) nb = 1;
+    rpb = (I + nb - 1) / nb;
+    return nb;
+}
+
+}  // namespace
+
+hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w, hipStream_t s)
+{
+    uint32_t rpb;
+    const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
+    hipLaunchKernelGGL(gram_partial_kernel, dim3(nb), dim3(kWG), 0, s, A, I, R, rpb, w.part);
+    const int K = R * R;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((K + kWG - 1) / kWG), dim3(kWG), 0, s, w.part, (int)nb, K, G_out,
+                       0);
+    return hipGetLastError();
+}
+
+hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, double* flag, int reset_flag,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(hadamard_kernel, dim3(1), dim3(kWG), 0, s, grams, N, skip, R, V, flag, reset_flag);
+    return hipGetLastError();
+}
+
+hipError_t als_cholesky_inverse(const double* V, int R, double* W, double* scratch, double* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(cholesky_inverse_kernel, dim3(1), dim3(kWG), 0, s, V, R, W, scratch, flag);
+    return hipGetLastError();
+}
+
+hipError_t als_solve_normalize(const float* M, const double* W, uint32_t I, int R, float* A, double* lam,
+                               AlsWork& w, hipStream_t s)
+{
+    uint32_t rpb;
+    const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
+    hipLaunchKernelGGL(mw_kernel, dim3(nb), dim3(kWG), 0, s, M, W, I, R, rpb, 0, (const double*)nullptr,
+                       (float*)nullptr, w.part);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kWG), 0, s, w.part, (int)nb, R, lam, 1);
+    hipLaunchKernelGGL(mw_kernel, dim3(nb), dim3(kWG), 0, s, M, W, I, R, rpb, 1, (const double*)lam, A,
+                       (double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t als_fit(const float* M, const float* A, uint32_t I, const double* lam, const double* grams, int N, int R,
+                   double normX2, double* fit_out, double* lam_out, AlsWork& w, hipStream_t s)
+{
+    uint32_t rpb;
+    const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
+    hipLaunchKernelGGL(coldot_kernel, dim3(nb), dim3(kWG), 0, s, M, A, I, R, rpb, w.part);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kWG), 0, s, w.part, (int)nb, R, w.colsq, 0);
+    hipLaunchKernelGGL(fit_kernel, dim3(1), dim3(kWG), 0, s, (const double*)w.colsq, lam, grams, N, R, normX2,
+                       fit_out, lam_out);
+    return hipGetLastError();
+}
+
+hipError_t cast_bf16(const float* A, uint64_t n, uint16_t* out, hipStream_t s)
+{
+    uint64_t blocks = (n + kWG - 1) / kWG;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(cast_bf16_kernel, dim3((uint32_t)blocks), dim3(kWG), 0, s, A, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace mk

@@ -1,0 +1,435 @@
+// C ABI runtime: handles, validation, device memory, launches.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "layout.h"
+#include "mttkrp.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+mttkrp_status fail(mttkrp_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+mttkrp_status hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return MTTKRP_EHIP;
+}
+
+constexpr uint64_t kAlign = 256;
+constexpr uint32_t kMaxParts = 8192;    // partitions per launch at most (sizes the carry buffer)
+constexpr int kAlsBlocks = 512;         // row blocks of the CP-ALS reductions
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int host_threads()
+{
+    unsigned t = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(t, 32u));
+}
+
+bool r_supported(int R) { return R == 16 || R == 32 || R == 64; }
+
+struct Workspace {
+    uint64_t carry = 0, grams = 0, V = 0, W = 0, Linv = 0, part = 0, colsq = 0, lam = 0, scal = 0, M = 0, bf16 = 0;
+    uint64_t total = 0;
+};
+
+Workspace plan_workspace(const uint32_t* dims, int N, int maxR, int dtype)
+{
+    Workspace w;
+    uint64_t maxI = 0, sumI = 0;
+    for (int m = 0; m < N; ++m) {
+        maxI = std::max<uint64_t>(maxI, dims[m]);
+        sumI += dims[m];
+    }
+    const uint64_t R = (uint64_t)maxR;
+    w.carry = align_up(kMaxParts * 2ull * R * 4ull);
+    w.grams = align_up((uint64_t)N * R * R * 8ull);
+    w.V = align_up(R * R * 8ull);
+    w.W = align_up(R * R * 8ull);
+    w.Linv = align_up(R * R * 8ull);
+    w.part = align_up((uint64_t)kAlsBlocks * R * R * 8ull);
+    w.colsq = align_up(R * 8ull);
+    w.lam = align_up(R * 8ull);
+    w.scal = align_up(8 * 8ull);
+    w.M = align_up(maxI * R * 4ull);
+    w.bf16 = dtype == MTTKRP_BF16 ? (uint64_t)N * kAlign + sumI * R * 2ull : 0;
+    w.total = w.carry + w.grams + w.V + w.W + w.Linv + w.part + w.colsq + w.lam + w.scal + w.M + align_up(w.bf16);
+    return w;
+}
+
+uint64_t copies_bytes(const uint32_t* dims, int N, uint64_t nnz)
+{
+    uint64_t b = 0;
+    for (int n = 0; n < N; ++n) b += mk::mode_device_bytes(nnz, N, dims[n]) + (uint64_t)(N + 4) * kAlign;
+    return b;
+}
+
+}  // namespace
+
+struct mttkrp_layout {
+    int N = 0;
+    uint32_t dims[MTTKRP_MAX_MODES] = {};
+    uint64_t nnz = 0;
+    mttkrp_opts opts{};
+    int device = 0;
+    int cu_count = 256;
+    bool host_only = false;
+    std::vector<mk::HostMode> host;
+    mk::DevMode dev[MTTKRP_MAX_MODES];
+    void* dmem = nullptr;
+    uint64_t dbytes = 0;
+    float* carry = nullptr;
+    mk::AlsWork als;
+    double normX2 = 0.0;
+    int als_R = 0;
+};
+
+extern "C" {
+
+void mttkrp_opts_default(mttkrp_opts* o)
+{
+    if (!o) return;
+    o->parts_per_cu = 8;
+    o->factor_dtype = MTTKRP_FP32;
+    o->max_R = 64;
+    o->hbm_budget_bytes = 0;
+    o->host_only = 0;
+}
+
+const char* mttkrp_last_error(void) { return g_err.c_str(); }
+
+static mttkrp_status check_opts(const mttkrp_opts* in, mttkrp_opts* o)
+{
+    mttkrp_opts_default(o);
+    if (in) *o = *in;
+    if (o->parts_per_cu <= 0) o->parts_per_cu = 8;
+    if (o->max_R == 0) o->max_R = 64;
+    if (!r_supported(o->max_R)) return fail(MTTKRP_EUNSUPPORTED, "max_R must be 16, 32 or 64");
+    if (o->factor_dtype != MTTKRP_FP32 && o->factor_dtype != MTTKRP_BF16)
+        return fail(MTTKRP_EINVAL, "factor_dtype must be MTTKRP_FP32 or MTTKRP_BF16");
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts* opts, uint64_t* bytes)
+{
+    g_err.clear();
+    if (!dims || !bytes) return fail(MTTKRP_EINVAL, "dims and bytes must not be NULL");
+    if (N < 3 || N > MTTKRP_MAX_MODES) return fail(MTTKRP_EUNSUPPORTED, "N must be between 3 and 8");
+    for (int m = 0; m < N; ++m)
+        if (dims[m] == 0 || dims[m] > 0x7fffffffu) return fail(MTTKRP_EINVAL, "dims must be in [1, 2^31-1]");
+    mttkrp_opts o;
+    mttkrp_status s = check_opts(opts, &o);
+    if (s) return s;
+    *bytes = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, uint64_t nnz, const uint32_t* dims,
+                                  int N, const mttkrp_opts* opts, hipStream_t stream, mttkrp_handle* out)
+{
+    g_err.clear();
+    if (!out) return fail(MTTKRP_EINVAL, "out handle pointer is NULL");
+    *out = nullptr;
+    if (N < 3 || N > MTTKRP_MAX_MODES) return fail(MTTKRP_EUNSUPPORTED, "N must be between 3 and 8");
+    if (nnz && !vals) return fail(MTTKRP_EINVAL, "vals is NULL");
+    mttkrp_opts o;
+    mttkrp_status s = check_opts(opts, &o);
+    if (s) return s;
+    bool range_err = false;
+    std::string msg = mk::validate_coo(coo_idx, nnz, dims, N, &range_err);
+    if (!msg.empty()) return fail(range_err ? MTTKRP_ERANGE : MTTKRP_EINVAL, msg);
+
+    const uint64_t need = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total;
+    if (!o.host_only && o.hbm_budget_bytes && need > o.hbm_budget_bytes)
+        return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(need) + " B exceeds the budget of " +
+                                       std::to_string(o.hbm_budget_bytes) + " B");
+
+    auto* h = new mttkrp_layout();
+    h->N = N;
+    for (int m = 0; m < N; ++m) h->dims[m] = dims[m];
+    h->nnz = nnz;
+    h->opts = o;
+    h->host_only = o.host_only != 0;
+
+    const int threads = host_threads();
+    if (h->host_only) {
+        h->host.resize(N);
+        for (int n = 0; n < N; ++n) mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, true, threads, h->host[n]);
+        *out = h;
+        return MTTKRP_OK;
+    }
+
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDevice");
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
+        h->cu_count = cus;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b) {
+        delete h;
+        return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(need) + " B exceeds free device memory (" +
+                                       std::to_string(free_b) + " B)");
+    }
+    e = hipMalloc(&h->dmem, need);
+    if (e != hipSuccess) {
+        h->dmem = nullptr;
+        delete h;
+        (void)hipGetLastError();
+        return fail(MTTKRP_ENOMEM, "hipMalloc of " + std::to_string(need) + " B failed");
+    }
+    h->dbytes = need;
+    char* base = static_cast<char*>(h->dmem);
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) -> void* {
+        void* p = base + off;
+        off += align_up(bytes);
+        return p;
+    };
+    // Workspace.
+    const Workspace ws = plan_workspace(dims, N, o.max_R, o.factor_dtype);
+    h->carry = static_cast<float*>(take(ws.carry));
+    h->als.grams = static_cast<double*>(take(ws.grams));
+    h->als.V = static_cast<double*>(take(ws.V));
+    h->als.W = static_cast<double*>(take(ws.W));
+    h->als.Linv = static_cast<double*>(take(ws.Linv));
+    h->als.part = static_cast<double*>(take(ws.part));
+    h->als.colsq = static_cast<double*>(take(ws.colsq));
+    h->als.lam = static_cast<double*>(take(ws.lam));
+    h->als.scal = static_cast<double*>(take(ws.scal));
+    h->als.M = static_cast<float*>(take(ws.M));
+    h->als.max_blocks = kAlsBlocks;
+    if (o.factor_dtype == MTTKRP_BF16)
+        for (int m = 0; m < N; ++m) h->als.bf16[m] = static_cast<uint16_t*>(take((uint64_t)dims[m] * o.max_R * 2));
+
+    // Mode copies: build on the host one mode at a time, upload, release.
+    double normX2 = 0.0;
+    for (int n = 0; n < N && e == hipSuccess; ++n) {
+        mk::HostMode hm;
+        mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, false, threads, hm);
+        mk::DevMode& d = h->dev[n];
+        d.nnz = hm.nnz;
+        d.nnz_pad = hm.nnz_pad;
+        d.nrows_nz = hm.nrows_nz;
+        d.nempty = hm.nempty;
+        d.n_in = N - 1;
+        auto up = [&](const void* src, uint64_t bytes) -> void* {
+            void* dst = take(bytes ? bytes : 4);
+            if (bytes && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+            return dst;
+        };
+        for (int j = 0; j < N - 1; ++j) {
+            d.in_modes[j] = hm.in_modes[j];
+            d.idx[j] = static_cast<const uint32_t*>(up(hm.idx[j].data(), hm.nnz_pad * 4));
+        }
+        d.val = static_cast<const float*>(up(hm.val.data(), hm.nnz_pad * 4));
+        d.winfo = static_cast<const uint2*>(up(hm.winfo.data(), hm.winfo.size() * 4));
+        d.row_id = static_cast<const uint32_t*>(up(hm.row_id.data(), hm.row_id.size() * 4));
+        d.empty_rows = static_cast<const uint32_t*>(up(hm.empty_rows.data(), hm.empty_rows.size() * 4));
+        if (n == 0) {
+            // |X|^2 with duplicate coordinates merged: duplicates are adjacent in
+            // the sorted copy (no row start between them, same other indices).
+            uint64_t k = 0;
+            while (k < nnz) {
+                double v = hm.val[k];
+                uint64_t j = k + 1;
+                while (j < nnz && !((hm.winfo[2 * (j / 32)] >> (j % 32)) & 1u)) {
+                    bool same = true;
+                    for (int t = 0; t < N - 1 && same; ++t) same = hm.idx[t][j] == hm.idx[t][k];
+                    if (!same) break;
+                    v += hm.val[j];
+                    ++j;
+                }
+                normX2 += v * v;
+                k = j;
+            }
+        }
+        // The host arrays are released at the end of this iteration; wait for
+        // the copies that read them.
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
+    h->normX2 = normX2;
+    if (e != hipSuccess) {
+        mttkrp_status st = hip_fail(e, "uploading the mode copies");
+        (void)hipFree(h->dmem);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return MTTKRP_OK;
+}
+
+uint64_t mttkrp_layout_bytes(mttkrp_handle h) { return h ? h->dbytes : 0; }
+
+void mttkrp_layout_free(mttkrp_handle h)
+{
+    if (!h) return;
+    if (h->dmem) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(h->dmem);
+    }
+    delete h;
+}
+
+mttkrp_status mttkrp_layout_view(mttkrp_handle h, int mode, mttkrp_mode_view* v)
+{
+    g_err.clear();
+    if (!h || !v) return fail(MTTKRP_EINVAL, "NULL handle or view");
+    if (!h->host_only) return fail(MTTKRP_EINVAL, "views exist only for host-only handles");
+    if (mode < 0 || mode >= h->N) return fail(MTTKRP_EINVAL, "mode out of range");
+    const mk::HostMode& m = h->host[mode];
+    memset(v, 0, sizeof(*v));
+    v->nnz = m.nnz;
+    v->nnz_pad = m.nnz_pad;
+    v->nrows_nz = m.nrows_nz;
+    v->nempty = m.nempty;
+    v->n_in = (int)m.in_modes.size();
+    for (int j = 0; j < v->n_in; ++j) {
+        v->in_modes[j] = m.in_modes[j];
+        v->idx[j] = m.idx[j].data();
+    }
+    v->val = m.val.data();
+    v->winfo = m.winfo.data();
+    v->row_id = m.row_id.data();
+    v->empty_rows = m.empty_rows.data();
+    v->src_pos = m.src_pos.data();
+    return MTTKRP_OK;
+}
+
+static mttkrp_status check_run(mttkrp_handle h, int mode, const void* const* factors, const float* out, int R)
+{
+    if (!h) return fail(MTTKRP_EINVAL, "NULL handle");
+    if (h->host_only) return fail(MTTKRP_EINVAL, "host-only handle: build without host_only to run");
+    if (mode < 0 || mode >= h->N) return fail(MTTKRP_EINVAL, "mode out of range");
+    if (!r_supported(R)) return fail(MTTKRP_EUNSUPPORTED, "R must be 16, 32 or 64");
+    if (R > h->opts.max_R) return fail(MTTKRP_EINVAL, "R exceeds the handle's max_R");
+    if (!factors || !out) return fail(MTTKRP_EINVAL, "NULL factors or out");
+    if (reinterpret_cast<uintptr_t>(out) % 16) return fail(MTTKRP_EINVAL, "out must be 16-byte aligned");
+    for (int m = 0; m < h->N; ++m) {
+        if (m == mode) continue;
+        if (!factors[m]) return fail(MTTKRP_EINVAL, "factor " + std::to_string(m) + " is NULL");
+        if (reinterpret_cast<uintptr_t>(factors[m]) % 16)
+            return fail(MTTKRP_EINVAL, "factor " + std::to_string(m) + " must be 16-byte aligned");
+    }
+    return MTTKRP_OK;
+}
+
+static mttkrp_status run_mode(mttkrp_handle h, int mode, const void* const* factors, int dtype, float* out, int R,
+                              hipStream_t stream)
+{
+    const mk::DevMode& d = h->dev[mode];
+    const void* fac[mk::kMaxIn];
+    for (int j = 0; j < d.n_in; ++j) fac[j] = factors[d.in_modes[j]];
+    const mk::Geometry g = mk::plan_geometry(d.nnz, R, dtype, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+    hipError_t e = mk::launch_mttkrp(d, h->N, R, dtype, fac, out, h->carry, g, h->dims[mode], stream);
+    if (e != hipSuccess) return hip_fail(e, "MTTKRP launch");
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_run(mttkrp_handle h, int mode, const float* const* factors, float* out, int R,
+                         hipStream_t stream)
+{
+    g_err.clear();
+    mttkrp_status s = check_run(h, mode, reinterpret_cast<const void* const*>(factors), out, R);
+    if (s) return s;
+    return run_mode(h, mode, reinterpret_cast<const void* const*>(factors), MTTKRP_FP32, out, R, stream);
+}
+
+mttkrp_status mttkrp_run_bf16(mttkrp_handle h, int mode, const uint16_t* const* factors, float* out, int R,
+                              hipStream_t stream)
+{
+    g_err.clear();
+    mttkrp_status s = check_run(h, mode, reinterpret_cast<const void* const*>(factors), out, R);
+    if (s) return s;
+    return run_mode(h, mode, reinterpret_cast<const void* const*>(factors), MTTKRP_BF16, out, R, stream);
+}
+
+static mttkrp_status check_factors(mttkrp_handle h, const void* const* factors, int R)
+{
+    if (!h) return fail(MTTKRP_EINVAL, "NULL handle");
+    if (h->host_only) return fail(MTTKRP_EINVAL, "host-only handle: build without host_only to run");
+    if (!r_supported(R)) return fail(MTTKRP_EUNSUPPORTED, "R must be 16, 32 or 64");
+    if (R > h->opts.max_R) return fail(MTTKRP_EINVAL, "R exceeds the handle's max_R");
+    if (!factors) return fail(MTTKRP_EINVAL, "NULL factors");
+    for (int m = 0; m < h->N; ++m) {
+        if (!factors[m]) return fail(MTTKRP_EINVAL, "factor " + std::to_string(m) + " is NULL");
+        if (reinterpret_cast<uintptr_t>(factors[m]) % 16)
+            return fail(MTTKRP_EINVAL, "factor " + std::to_string(m) + " must be 16-byte aligned");
+    }
+    return MTTKRP_OK;
+}
+
+mttkrp_status cpd_als_init(mttkrp_handle h, const float* const* factors, int R, hipStream_t stream)
+{
+    g_err.clear();
+    mttkrp_status s = check_factors(h, reinterpret_cast<const void* const*>(factors), R);
+    if (s) return s;
+    hipError_t e = hipSuccess;
+    for (int m = 0; m < h->N && e == hipSuccess; ++m) {
+        e = mk::als_gram(factors[m], h->dims[m], R, h->als.grams + (uint64_t)m * R * R, h->als, stream);
+        if (e == hipSuccess && h->opts.factor_dtype == MTTKRP_BF16)
+            e = mk::cast_bf16(factors[m], (uint64_t)h->dims[m] * R, h->als.bf16[m], stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "cpd_als_init");
+    h->als_R = R;
+    return MTTKRP_OK;
+}
+
+mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
+                           hipStream_t stream)
+{
+    g_err.clear();
+    mttkrp_status s = check_factors(h, reinterpret_cast<const void* const*>(factors), R);
+    if (s) return s;
+    if (h->als_R != R) return fail(MTTKRP_EINVAL, "call cpd_als_init with this R first");
+    if (!lambda) return fail(MTTKRP_EINVAL, "NULL lambda");
+    mk::AlsWork& w = h->als;
+    const int N = h->N;
+    const bool bf16 = h->opts.factor_dtype == MTTKRP_BF16;
+    const int dtype = bf16 ? MTTKRP_BF16 : MTTKRP_FP32;
+    double* flag = w.scal + 1;
+    hipError_t e = hipSuccess;
+    for (int n = 0; n < N && e == hipSuccess; ++n) {
+        const uint32_t I = h->dims[n];
+        const uint64_t RR = (uint64_t)R * R;
+        e = mk::als_hadamard(w.grams, N, n, R, w.V, flag, n == 0, stream);
+        if (e == hipSuccess) e = mk::als_cholesky_inverse(w.V, R, w.W, w.Linv, flag, stream);
+        if (e == hipSuccess) {
+            const void* fac[MTTKRP_MAX_MODES];
+            for (int m = 0; m < N; ++m)
+                fac[m] = bf16 ? static_cast<const void*>(w.bf16[m]) : static_cast<const void*>(factors[m]);
+            mttkrp_status st = run_mode(h, n, fac, dtype, w.M, R, stream);
+            if (st) return st;
+        }
+        if (e == hipSuccess) e = mk::als_solve_normalize(w.M, w.W, I, R, factors[n], w.lam, w, stream);
+        if (e == hipSuccess) e = mk::als_gram(factors[n], I, R, w.grams + (uint64_t)n * RR, w, stream);
+        if (e == hipSuccess && bf16) e = mk::cast_bf16(factors[n], (uint64_t)I * R, w.bf16[n], stream);
+    }
+    if (e == hipSuccess)
+        e = mk::als_fit(w.M, factors[N - 1], h->dims[N - 1], w.lam, w.grams, N, R, h->normX2,
+                        fit_out ? fit_out : w.scal, lambda, w, stream);
+    if (e != hipSuccess) return hip_fail(e, "cpd_als_iter");
+    double f = 0.0;
+    e = hipMemcpyAsync(&f, flag, sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "cpd_als_iter");
+    if (f != 0.0) return fail(MTTKRP_ENOTSPD, "a normal-equation matrix V is not positive definite");
+    return MTTKRP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+#include "mttkrp.h"
+
+namespace mk {
+
+constexpr int kWG = 256;                       // threads per workgroup in every kernel here
+constexpr int kMaxIn = MTTKRP_MAX_MODES - 1;   // input modes per nonzero, at most
+
+// One mode-specific copy of the tensor in device memory (Sec. III-C).
+// Nonzeros are ordered by output row; arrays are padded to nnz_pad (a
+// multiple of 32) with zero entries that the kernels never use.
+struct DevMode {
+    uint64_t nnz = 0, nnz_pad = 0, nrows_nz = 0, nempty = 0;
+    int n_in = 0;
+    int in_modes[kMaxIn] = {};
+    const uint32_t* idx[kMaxIn] = {};  // SoA input-mode coordinates
+    const float* val = nullptr;
+    const uint2* winfo = nullptr;      // per 32 nonzeros: {row-start bits, ordinal of the row holding the first}
+    const uint32_t* row_id = nullptr;  // ordinal -> output row
+    const uint32_t* empty_rows = nullptr;
+};
+
+// Launch geometry of one MTTKRP call.
+struct Geometry {
+    int lanes;          // lanes per group: one 16-byte slice of a factor row per lane
+    int groups;         // lane groups per workgroup
+    uint32_t gsz;       // nonzeros per lane group (multiple of 32)
+    uint64_t wgc;       // nonzeros per workgroup partition = groups * gsz
+    uint32_t nparts;    // workgroups
+};
+
+Geometry plan_geometry(uint64_t nnz, int R, int dtype, int parts_per_cu, uint32_t max_parts);
+
+// Enqueue the per-mode MTTKRP: partition kernel then fix-up kernel.
+// `fac` holds the N-1 input factors in the order of m.in_modes.
+hipError_t launch_mttkrp(const DevMode& m, int N, int R, int dtype, const void* const* fac, float* out,
+                         float* carry, const Geometry& g, uint32_t rows_out, hipStream_t s);
+
+// CP-ALS helpers (als_kernels.hip).  All FP64 unless noted.
+struct AlsWork {
+    double* grams = nullptr;     // N x R x R
+    double* V = nullptr;         // R x R
+    double* W = nullptr;         // R x R (V^{-1})
+    double* Linv = nullptr;      // R x R (inverse Cholesky factor)
+    double* part = nullptr;      // per-block partial sums: max_blocks x (R x R)
+    double* colsq = nullptr;     // R
+    double* lam = nullptr;       // R
+    double* scal = nullptr;      // small scalars: [0] fit, [1] not-positive-definite flag
+    float* M = nullptr;          // max_I x R fp32 (MTTKRP output)
+    uint16_t* bf16[MTTKRP_MAX_MODES] = {};  // bf16 copies of the factors (optional)
+    int max_blocks = 0;
+};
+
+hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w, hipStream_t s);
+hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, double* flag, int reset_flag,
+                        hipStream_t s);
+hipError_t als_cholesky_inverse(const double* V, int R, double* W, double* scratch, double* flag, hipStream_t s);
+hipError_t als_solve_normalize(const float* M, const double* W, uint32_t I, int R, float* A, double* lam,
+                               AlsWork& w, hipStream_t s);
+hipError_t als_fit(const float* M, const float* A, uint32_t I, const double* lam, const double* grams, int N, int R,
+                   double normX2, double* fit_out, double* lam_out, AlsWork& w, hipStream_t s);
+hipError_t cast_bf16(const float* A, uint64_t n, uint16_t* out, hipStream_t s);
+
+}  // namespace mk

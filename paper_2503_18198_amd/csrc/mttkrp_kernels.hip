@@ -1,0 +1,173 @@
+// Per-mode sparse MTTKRP for gfx950 (CDNA4, wave64).
+//
+// The paper's per-partition thread block (Alg. 2) gives each nonzero a
+// column of R threads: load the nonzero, gather the N-1 input factor rows,
+// multiply them element by element with the value, add the product into the
+// output row (Sec. IV-B).  Here the same per-nonzero work is mapped onto
+// CDNA4 as follows.
+//
+//  * A lane group of L = R*sizeof(T)/16 lanes owns one factor row per
+//    gather: each lane loads one 16-byte slice, so a row is one coalesced
+//    128-byte (fp32, R=32) access.  A wave runs 64/L groups side by side.
+//  * Every lane group walks its own contiguous run of `gsz` nonzeros of the
+//    mode copy (nonzero-balanced partitions, Sec. III-B scheme 2).  It
+//    streams indices and values 32 nonzeros at a time with full-line loads,
+//    shares them inside the group with ds_swizzle, keeps up to U nonzeros'
+//    row gathers in flight, and accumulates the current output row in
+//    registers.  A row that ends inside the group's run is stored once with
+//    a plain store.
+//  * A workgroup is G consecutive lane groups (one partition).  The partial
+//    first/last rows of every group are combined in LDS in group order; rows
+//    complete inside the workgroup are stored once.  A row cut by a
+//    workgroup boundary leaves one partial per workgroup in `carry`, and the
+//    fix-up kernel adds those in workgroup order.  No global atomics, a fixed
+//    summation order, so results repeat bit for bit.
+//  * Row boundaries come from one bit per nonzero ("starts a new output
+//    row") plus, per 32 nonzeros, the ordinal of the row holding the first
+//    one; ordinals map to output rows through the list of nonempty rows.
+#include "internal.h"
+
+namespace mk {
+
+template <int NIN>
+hipError_t launch_part_nin(const DevMode& m, int R, int dtype, const void* const* fac, float* out, float* carry,
+                           const Geometry& g, hipStream_t s);
+
+namespace {
+
+struct FixArgs {
+    const uint2* winfo;
+    const uint32_t* row_id;
+    const uint32_t* empty_rows;
+    const float* carry;
+    float* out;
+    uint64_t wgc;          // nonzeros per workgroup partition
+    uint32_t nparts;
+    uint32_t nbound;       // workgroups of this grid that handle partition boundaries
+    uint64_t nempty;
+    int R;
+};
+
+constexpr int kEmptyPerBlock = 64;
+
+// Rows cut by partition boundaries: add the partials of every partition that
+// holds part of the row, in partition order, in FP64.  Then zero the rows
+// without nonzeros.
+__global__ __launch_bounds__(kWG) void mttkrp_fixup_kernel(FixArgs a)
+{
+    __shared__ double s_part[kWG];
+    const int tid = threadIdx.x;
+    const int R = a.R;
+    if (blockIdx.x < a.nbound) {
+        const uint32_t q = blockIdx.x + 1;           // partition q begins at q * wgc
+        const uint2 wq = a.winfo[(q * a.wgc) >> 5];
+        if (wq.x & 1u) return;                        // a row starts at the boundary: nothing is cut
+        const uint32_t r = wq.y;                      // ordinal of the cut row
+        if (q >= 2) {
+            const uint2 wp = a.winfo[((uint64_t)(q - 1) * a.wgc) >> 5];
+            if (!(wp.x & 1u) && wp.y == r) return;   // the row was already cut at boundary q-1
+        }
+        const uint32_t pa = q - 1;
+        const int slot_a = (a.winfo[((uint64_t)pa * a.wgc) >> 5].y == r) ? 0 : 1;
+        // Partitions q, q+1, ..., pb hold the rest of the row; each starts inside it.
+        uint32_t pb = q;
+        for (;;) {
+            const uint32_t p = pb + 1 + tid;
+            const int inside = (p < a.nparts) && (a.winfo[((uint64_t)p * a.wgc) >> 5].y == r);
+            const int cnt = __syncthreads_count(inside);
+            pb += cnt;
+            if (cnt < kWG) break;
+        }
+        const int S = kWG / R;                        // partial streams
+        const int col = tid % R;
+        const int s = tid / R;
+        const uint32_t ncontrib = pb - q + 2;
+        double t = 0.0;
+        for (uint32_t j = s; j < ncontrib; j += S) {
+            const uint32_t p = (j == 0) ? pa : (q + j - 1);
+            const int slot = (j == 0) ? slot_a : 0;
+            t += (double)a.carry[((uint64_t)p * 2 + slot) * R + col];
+        }
+        s_part[tid] = t;
+        __syncthreads();
+        if (s == 0) {
+            double tot = 0.0;
+            for (int j = 0; j < S; ++j) tot += s_part[j * R + col];
+            a.out[(uint64_t)a.row_id[r] * R + col] = (float)tot;
+        }
+    } else {
+        const uint64_t e0 = (uint64_t)(blockIdx.x - a.nbound) * kEmptyPerBlock;
+        const uint64_t e1 = min(e0 + kEmptyPerBlock, a.nempty);
+        const uint64_t n = (e1 - e0) * (uint64_t)R;
+        for (uint64_t t = tid; t < n; t += kWG) {
+            const uint64_t e = e0 + t / R;
+            a.out[(uint64_t)a.empty_rows[e] * R + (t % R)] = 0.0f;
+        }
+    }
+}
+
+}  // namespace
+
+Geometry plan_geometry(uint64_t nnz, int R, int dtype, int target_parts, uint32_t max_parts)
+{
+    Geometry g;
+    const int elem = dtype == MTTKRP_FP32 ? 4 : 2;
+    g.lanes = R * elem / 16;
+    g.groups = kWG / g.lanes;
+    if (target_parts < 1) target_parts = 1;
+    uint64_t per_group = (nnz + (uint64_t)target_parts * g.groups - 1) / ((uint64_t)target_parts * g.groups);
+    uint64_t gsz = (per_group + 31) / 32 * 32;
+    if (gsz < 32) gsz = 32;
+    uint64_t wgc = gsz * g.groups;
+    uint64_t parts = (nnz + wgc - 1) / wgc;
+    if (parts > max_parts) {
+        const uint64_t pg = (nnz + (uint64_t)max_parts * g.groups - 1) / ((uint64_t)max_parts * g.groups);
+        gsz = (pg + 31) / 32 * 32;
+        wgc = gsz * g.groups;
+        parts = (nnz + wgc - 1) / wgc;
+    }
+    g.gsz = (uint32_t)gsz;
+    g.wgc = wgc;
+    g.nparts = (uint32_t)parts;
+    return g;
+}
+
+hipError_t launch_mttkrp(const DevMode& m, int N, int R, int dtype, const void* const* fac, float* out,
+                         float* carry, const Geometry& g, uint32_t rows_out, hipStream_t s)
+{
+    (void)N;
+    (void)rows_out;
+    hipError_t e = hipSuccess;
+    if (m.nnz > 0) {
+        switch (m.n_in) {
+            case 2: e = launch_part_nin<2>(m, R, dtype, fac, out, carry, g, s); break;
+            case 3: e = launch_part_nin<3>(m, R, dtype, fac, out, carry, g, s); break;
+            case 4: e = launch_part_nin<4>(m, R, dtype, fac, out, carry, g, s); break;
+            case 5: e = launch_part_nin<5>(m, R, dtype, fac, out, carry, g, s); break;
+            case 6: e = launch_part_nin<6>(m, R, dtype, fac, out, carry, g, s); break;
+            case 7: e = launch_part_nin<7>(m, R, dtype, fac, out, carry, g, s); break;
+            default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    }
+    FixArgs f;
+    f.winfo = m.winfo;
+    f.row_id = m.row_id;
+    f.empty_rows = m.empty_rows;
+    f.carry = carry;
+    f.out = out;
+    f.wgc = g.wgc;
+    f.nparts = m.nnz > 0 ? g.nparts : 0;
+    f.nbound = f.nparts > 1 ? f.nparts - 1 : 0;
+    f.nempty = m.nempty;
+    f.R = R;
+    const uint64_t eblocks = (m.nempty + kEmptyPerBlock - 1) / kEmptyPerBlock;
+    const uint64_t blocks = f.nbound + eblocks;
+    if (blocks > 0) {
+        hipLaunchKernelGGL(mttkrp_fixup_kernel, dim3((uint32_t)blocks), dim3(kWG), 0, s, f);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace mk

@@ -1,0 +1,7 @@
+// Partition kernels for 4-mode tensors (3 input modes per nonzero).
+#include "part_kernel.h"
+
+namespace mk {
+template hipError_t launch_part_nin<3>(const DevMode&, int, int, const void* const*, float*, float*,
+                                         const Geometry&, hipStream_t);
+}  // namespace mk

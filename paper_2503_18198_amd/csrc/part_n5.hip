@@ -1,0 +1,7 @@
+// Partition kernels for 5-mode tensors (4 input modes per nonzero).
+#include "part_kernel.h"
+
+namespace mk {
+template hipError_t launch_part_nin<4>(const DevMode&, int, int, const void* const*, float*, float*,
+                                         const Geometry&, hipStream_t);
+}  // namespace mk

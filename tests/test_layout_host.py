@@ -1,0 +1,187 @@
+"""Host logic of the library, no GPU: the mode copies built by
+``mttkrp_layout_build`` (host-only handles), argument validation, the
+footprint, and the exported C symbols."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_18198_amd import capi
+from tests import pins
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mttkrp.h")
+
+
+def host_layout(idx, val, dims):
+    return capi.mttkrp_layout_build(idx, val, dims, opts=dict(host_only=1))
+
+
+def row_of_each_nonzero(v):
+    """Output row of each nonzero of a view, decoded from its row-start bits
+    and per-word row ordinals."""
+    nnz = v["nnz"]
+    w = v["winfo"].reshape(-1, 2) if nnz else np.zeros((0, 2), np.uint32)
+    k = np.arange(nnz)
+    bits = (w[k // 32, 0] >> (k % 32).astype(np.uint32)) & 1
+    # ordinal: ordinal of the word's first nonzero plus row starts after it within the word
+    ordinal = np.empty(nnz, dtype=np.int64)
+    for i in range(nnz):
+        if i % 32 == 0:
+            o = int(w[i // 32, 1])
+        elif bits[i]:
+            o += 1
+        ordinal[i] = o
+    return v["row_id"][ordinal].astype(np.int64), bits, ordinal
+
+
+def check_view(idx, val, dims, v, n):
+    N = len(dims)
+    nnz = idx.shape[0]
+    assert v["nnz"] == nnz and v["nnz_pad"] == (nnz + 31) // 32 * 32
+    assert v["in_modes"] == [m for m in range(N) if m != n]
+    src = v["src_pos"].astype(np.int64)
+    # a permutation of the input, carrying every coordinate and value
+    assert np.array_equal(np.sort(src), np.arange(nnz))
+    for j, m in enumerate(v["in_modes"]):
+        assert np.array_equal(v["idx"][j][:nnz], idx[src, m])
+        assert not v["idx"][j][nnz:].any()
+    assert np.array_equal(v["val"][:nnz], val[src])
+    assert not v["val"][nnz:].any()
+    rows, bits, ordinal = row_of_each_nonzero(v)
+    assert np.array_equal(rows, idx[src, n].astype(np.int64))
+    # order: output row, then the other modes cyclically, then input position
+    cyc = [(n + j) % N for j in range(1, N)]
+    keys = [idx[src, n].astype(np.int64)] + [idx[src, m].astype(np.int64) for m in cyc] + [src]
+    order = np.lexsort(keys[::-1])
+    assert np.array_equal(order, np.arange(nnz))
+    # nonempty / empty rows partition [0, I_n)
+    counts = np.bincount(idx[:, n].astype(np.int64), minlength=dims[n])
+    assert np.array_equal(v["row_id"], np.nonzero(counts)[0])
+    assert np.array_equal(v["empty_rows"], np.nonzero(counts == 0)[0])
+    assert v["nrows_nz"] + v["nempty"] == dims[n]
+    # a start bit exactly where a new row begins
+    if nnz:
+        starts = np.ones(nnz, dtype=bool)
+        starts[1:] = rows[1:] != rows[:-1]
+        assert np.array_equal(bits.astype(bool), starts)
+        # padding bits are zero
+        last = v["winfo"].reshape(-1, 2)[-1, 0]
+        tail = nnz % 32
+        if tail:
+            assert (int(last) >> tail) == 0
+
+
+CASES = {
+    "random3": ((30, 20, 10), 500, 0),
+    "random4_dups": ((9, 7, 5, 4), 300, 40),
+    "random5": ((6, 5, 4, 3, 2), 200, 0),
+    "tiny": ((3, 3, 3), 5, 0),
+    "single_nnz": ((4, 5, 6), 1, 0),
+    "exactly32": ((40, 40, 40), 32, 0),
+    "dim_one": ((1, 50, 7), 120, 0),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_layout_invariants(case):
+    dims, nnz, dup = CASES[case]
+    rng = np.random.default_rng(hash(case) % 2 ** 32)
+    idx, val = pins.rand_coo(rng, dims, nnz, dup=dup)
+    val = val.astype(np.float32)
+    h = host_layout(idx, val, dims)
+    for n in range(len(dims)):
+        check_view(idx, val, dims, capi.mttkrp_layout_view(h, n), n)
+    h.free()
+
+
+def test_layout_one_heavy_row_and_empty_edges():
+    """All nonzeros in one output row; leading and trailing empty rows."""
+    rng = np.random.default_rng(3)
+    dims = (100, 60, 50)
+    nnz = 2000
+    idx = np.stack([np.full(nnz, 57), rng.integers(0, 60, nnz), rng.integers(0, 50, nnz)], axis=1).astype(np.uint32)
+    val = rng.random(nnz).astype(np.float32)
+    h = host_layout(idx, val, dims)
+    v = capi.mttkrp_layout_view(h, 0)
+    check_view(idx, val, dims, v, 0)
+    assert v["nrows_nz"] == 1 and list(v["row_id"]) == [57]
+    assert v["nempty"] == 99
+    for n in (1, 2):
+        check_view(idx, val, dims, capi.mttkrp_layout_view(h, n), n)
+
+
+def test_layout_empty_tensor():
+    dims = (5, 6, 7)
+    h = host_layout(np.zeros((0, 3), np.uint32), np.zeros(0, np.float32), dims)
+    for n in range(3):
+        v = capi.mttkrp_layout_view(h, n)
+        assert v["nnz"] == 0 and v["nnz_pad"] == 0 and v["nrows_nz"] == 0
+        assert np.array_equal(v["empty_rows"], np.arange(dims[n]))
+
+
+def test_layout_wide_keys():
+    """Other-mode indices wider than 64 bits in total: the generic comparison path."""
+    rng = np.random.default_rng(4)
+    dims = (50, 100_000, 100_000, 100_000, 100_000)  # 4 x 17 bits > 64
+    nnz = 400
+    idx = np.stack([rng.integers(0, d, nnz) for d in dims], axis=1).astype(np.uint32)
+    idx[::7, 1] = idx[0, 1]  # ties in the first comparison key
+    val = rng.random(nnz).astype(np.float32)
+    h = host_layout(idx, val, dims)
+    for n in range(5):
+        check_view(idx, val, dims, capi.mttkrp_layout_view(h, n), n)
+
+
+def test_errors():
+    idx = np.array([[0, 1, 2]], dtype=np.uint32)
+    val = np.ones(1, np.float32)
+    with pytest.raises(capi.MttkrpError) as e:
+        host_layout(idx, val, (1, 1, 3))
+    assert e.value.status == capi.MTTKRP_ERANGE
+    with pytest.raises(capi.MttkrpError) as e:
+        host_layout(np.zeros((1, 2), np.uint32), val, (3, 3))
+    assert e.value.status == capi.MTTKRP_EUNSUPPORTED
+    with pytest.raises(capi.MttkrpError) as e:
+        host_layout(np.zeros((1, 3), np.uint32), val, (0, 3, 3))
+    assert e.value.status == capi.MTTKRP_EINVAL
+    with pytest.raises(capi.MttkrpError) as e:
+        capi.mttkrp_footprint((3, 3, 3), 10, opts=dict(max_R=48))
+    assert e.value.status == capi.MTTKRP_EUNSUPPORTED
+    # runs are refused on host-only handles, before any device call
+    h = host_layout(idx, val, (1, 2, 3))
+    with pytest.raises(capi.MttkrpError) as e:
+        capi._check(capi._lib.mttkrp_run(ctypes.c_void_p(h.ptr), 0, (ctypes.c_void_p * 3)(), ctypes.c_void_p(0), 16,
+                                         ctypes.c_void_p(0)))
+    assert e.value.status == capi.MTTKRP_EINVAL
+    # over-budget footprint is refused before anything is allocated
+    with pytest.raises(capi.MttkrpError) as e:
+        capi.mttkrp_layout_build(idx, val, (1, 2, 3), opts=dict(hbm_budget_bytes=1024))
+    assert e.value.status == capi.MTTKRP_ENOMEM
+
+
+def test_footprint_formula():
+    dims = (1000, 800, 600)
+    nnz = 100_000
+    fp = capi.mttkrp_footprint(dims, nnz, opts=dict(max_R=16))
+    pad = (nnz + 31) // 32 * 32
+    copies = sum(pad * (4 * 2 + 4) + pad // 32 * 8 + 4 * d for d in dims)
+    assert copies <= fp <= copies + 16 * 1024 * 1024
+    # the paper's memory model: N copies of nnz elements of sum(log2 dims) + 32 bits
+    bits = sum(math.ceil(math.log2(d)) for d in dims) + 32
+    assert 3 * nnz * bits / 8 <= copies
+    fp64 = capi.mttkrp_footprint(dims, nnz, opts=dict(max_R=64))
+    fpbf = capi.mttkrp_footprint(dims, nnz, opts=dict(max_R=64, factor_dtype=capi.MTTKRP_BF16))
+    assert fp < fp64 < fpbf
+
+
+def test_header_symbols_exported():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(mttkrp_\w+|cpd_als_\w+)\s*\(", text, re.M))
+    assert declared == set(capi.EXPORTED), declared ^ set(capi.EXPORTED)
+    lib = ctypes.CDLL(capi.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name

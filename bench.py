@@ -1,0 +1,237 @@
+"""All-mode sparse MTTKRP benchmark on one MI355X.
+
+Workload (default): 3-mode 200000 x 150000 x 100000 tensor, 20M distinct
+nonzeros with Zipf(1.2) index skew per mode, values U(0,1) fp32, rank 32, fp32
+factors.  One step = the MTTKRP along every mode in turn (the paper's total
+execution time sums the per-mode MTTKRP times), with the mode copies and
+factors resident in HBM before timing starts.  The CP-ALS sweep (MTTKRPs plus
+the FP64 normal-equation updates) and the host layout build are timed
+separately and reported in the same JSON line.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one
+GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "all-mode spMTTKRP GFLOP/s & HBM % peak; batched req/s + p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "zipf1.2-20M-R32": dict(config=2, R=32),
+    "uniform-100k-R16": dict(config=1, R=16),
+}
+
+
+def algorithmic_bytes(dims, nnz, R, factor_bytes=4):
+    """Bytes a mode's MTTKRP must move: the mode copy's indices and values, a
+    4-byte row pointer per output row, each input factor read once, the
+    output written once."""
+    N = len(dims)
+    per_mode = []
+    for n in range(N):
+        b = nnz * (4 * (N - 1) + 4) + 4 * (dims[n] + 1)
+        b += sum(dims[m] * R * factor_bytes for m in range(N) if m != n)
+        b += dims[n] * R * 4
+        per_mode.append(b)
+    return per_mode
+
+
+def cpu_baseline(t, R, F, budget_s=20.0):
+    """The FP64 oracle on the host, all modes, on a bounded leading sample of
+    the nonzeros sized to take about ``budget_s`` seconds."""
+    import oracle
+
+    threads = max(1, min(os.cpu_count() or 1, 64))
+    N = len(t.dims)
+    F64 = [f.astype(np.float64) for f in F]
+    val = t.val.astype(np.float64)
+    probe = min(t.nnz, 500_000)
+    t0 = time.perf_counter()
+    for n in range(N):
+        oracle.mttkrp(t.idx[:probe], val[:probe], t.dims, F64, n, threads=threads)
+    dt = time.perf_counter() - t0
+    sample = int(min(t.nnz, max(probe, probe * budget_s / max(dt, 1e-3) / 2)))
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        for n in range(N):
+            oracle.mttkrp(t.idx[:sample], val[:sample], t.dims, F64, n, threads=threads)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 2 or reps >= 20:
+            break
+    flops = N * R * sample * N * reps
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} of {t.nnz} nonzeros, all {N} modes, R={R}, FP64 C oracle, "
+                      f"{threads} OpenMP threads, {reps} repetition(s) in {dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="zipf1.2-20M-R32", choices=sorted(WORKLOADS))
+    ap.add_argument("--parts-per-cu", type=int, default=0)
+    ap.add_argument("--hot-rows", type=int, default=-1, help="rows per input factor cached in LDS (-1: as many as fit)")
+    ap.add_argument("--als-iters", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB, 5 times (to calibrate "
+                         "the HBM byte counters against a kernel of known traffic)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: sharding across GPUs is not part of this build "
+              "(see the design notes on how the path would shard).", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import workloads
+    from paper_2503_18198_amd import capi
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * 2 ** 20 // 4
+        a = torch.rand(n, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
+        return 0
+    wl = WORKLOADS[args.workload]
+    R = wl["R"]
+    t_gen = time.perf_counter()
+    t = workloads.config_tensor(wl["config"])
+    F = workloads.random_factors(t.dims, R, seed=wl["config"])
+    gen_s = time.perf_counter() - t_gen
+    N = len(t.dims)
+    print(f"[bench] generated {t.dims} nnz={t.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    opts = dict(max_R=R, hot_rows=args.hot_rows)
+    if args.parts_per_cu:
+        opts["parts_per_cu"] = args.parts_per_cu
+    stream = torch.cuda.current_stream()
+    t_b = time.perf_counter()
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=opts, stream=stream)
+    build_s = time.perf_counter() - t_b
+    print(f"[bench] layout built in {build_s:.1f}s ({capi.mttkrp_layout_bytes(h) / 2**30:.2f} GiB)",
+          file=sys.stderr, flush=True)
+    dF = [torch.from_numpy(f).cuda() for f in F]
+    outs = [torch.empty((d, R), dtype=torch.float32, device="cuda") for d in t.dims]
+
+    def all_modes(ev=None):
+        for n in range(N):
+            if ev is not None:
+                ev[n][0].record(stream)
+            capi.mttkrp_run(h, n, dF, outs[n], R, stream=stream)
+            if ev is not None:
+                ev[n][1].record(stream)
+
+    for _ in range(args.warmup):
+        all_modes()
+    torch.cuda.synchronize()
+    K = args.steps
+    events = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(N)]
+              for _ in range(K)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for k in range(K):
+        all_modes(events[k])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    ms_step = total_ms / K
+    mode_ms = [float(np.mean([events[k][n][0].elapsed_time(events[k][n][1]) for k in range(K)])) for n in range(N)]
+
+    flops = N * R * t.nnz * N
+    gflops = flops / (ms_step / 1e3) / 1e9
+    bytes_mode = algorithmic_bytes(t.dims, t.nnz, R)
+    achieved = sum(bytes_mode) / (sum(mode_ms) / 1e3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N}-mode {'x'.join(map(str, t.dims))}, {t.nnz} distinct nonzeros "
+                               f"({'Zipf(%s)' % workloads.CONFIGS[wl['config']]['s'] if workloads.CONFIGS[wl['config']]['dist'] == 'zipf' else 'uniform'}), "
+                               f"R={R}, fp32 factors, all-mode MTTKRP per step",
+                   "nnz": t.nnz, "dims": list(t.dims), "R": R},
+        "hbm_pct_peak": round(100.0 * sum(bytes_mode) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
+        "per_mode_ms": [round(x, 4) for x in mode_ms],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "per-mode MTTKRP (partition + fix-up kernels), algorithmic bytes / event time",
+                     "bytes_per_mode": bytes_mode},
+        "build_s": round(build_s, 2),
+        "launch": capi.mttkrp_layout_info(h),
+    }
+
+    # CP-ALS sweeps (MTTKRP plus the FP64 update), timed separately.
+    if args.als_iters > 0:
+        lam = torch.empty(R, dtype=torch.float64, device="cuda")
+        fit = torch.empty(1, dtype=torch.float64, device="cuda")
+        Fa = [f.clone() for f in dF]
+        capi.cpd_als_init(h, Fa, R, stream=stream)
+        capi.cpd_als_iter(h, Fa, lam, R, fit, stream=stream)
+        torch.cuda.synchronize()
+        fits = []
+        t0 = time.perf_counter()
+        for _ in range(args.als_iters):
+            capi.cpd_als_iter(h, Fa, lam, R, fit, stream=stream)
+            fits.append(float(fit.item()))
+        torch.cuda.synchronize()
+        result["als"] = {"ms_per_iter": round((time.perf_counter() - t0) * 1e3 / args.als_iters, 3),
+                         "iters": args.als_iters, "fit_last": fits[-1]}
+
+    if not args.no_parity:
+        import oracle
+        rng = np.random.default_rng(0)
+        worst = 0.0
+        for n in range(N):
+            counts = np.bincount(t.idx[:, n].astype(np.int64), minlength=t.dims[n])
+            heavy = np.argsort(counts)[-50:]
+            rows = np.unique(np.concatenate([heavy, rng.integers(0, t.dims[n], 200)])).astype(np.uint32)
+            ref = oracle.mttkrp_rows(t.idx, t.val.astype(np.float64), t.dims, [f.astype(np.float64) for f in F],
+                                     n, rows)
+            got = outs[n].cpu().numpy()[rows.astype(np.int64)]
+            worst = max(worst, float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)))
+        result["parity_sampled_rows_rel_err"] = worst
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(t, R, F)
+    h.free()
+    print(json.dumps(result))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -62,11 +62,13 @@ enum { MTTKRP_FP32 = 0, MTTKRP_BF16 = 1 };
 #define MTTKRP_MAX_MODES 8
 
 typedef struct {
-    int parts_per_cu;          /* workgroup partitions per compute unit for the MTTKRP launch; 0 = default (8) */
+    int parts_per_cu;          /* workgroup partitions per compute unit for the MTTKRP launch; 0 = default (2) */
     int factor_dtype;          /* gather precision used inside cpd_als_iter: MTTKRP_FP32 or MTTKRP_BF16 */
     int max_R;                 /* largest R the handle will run with (16, 32 or 64); sizes the workspace; 0 = 64 */
     uint64_t hbm_budget_bytes; /* refuse to build (MTTKRP_ENOMEM) when the footprint exceeds this; 0 = no budget */
     int host_only;             /* 1: build the host arrays only (for inspection); no device memory, runs refused */
+    int hot_rows;              /* rows of each input factor kept in LDS during a run: the most frequently
+                                  gathered ones.  -1 = as many as fit (default), 0 = none, k > 0 = at most k */
 } mttkrp_opts;
 
 /* Fill `o` with the defaults listed above. */
@@ -128,6 +130,17 @@ mttkrp_status cpd_als_init(mttkrp_handle h, const float* const* factors, int R, 
 mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
                            hipStream_t stream);
 
+/* Launch facts of a handle, for tuning and reports. */
+typedef struct {
+    uint32_t cu_count;            /* compute units of the handle's device */
+    uint32_t lds_per_workgroup;   /* LDS bytes a workgroup may allocate on that device */
+    uint32_t hot_rows;            /* rows per input factor the MTTKRP kernel keeps in LDS */
+    uint32_t wg_threads;          /* threads per MTTKRP workgroup */
+    uint32_t parts_per_cu;        /* MTTKRP workgroups launched per compute unit */
+} mttkrp_info;
+
+mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
+
 /* Release a handle and all of its device memory (synchronises the device).
  * NULL is ignored. */
 void mttkrp_layout_free(mttkrp_handle h);
@@ -144,12 +157,15 @@ typedef struct {
     uint64_t nempty;              /* output rows without nonzeros */
     int n_in;                     /* N - 1 */
     int in_modes[MTTKRP_MAX_MODES - 1];      /* the input modes, increasing */
-    const uint32_t* idx[MTTKRP_MAX_MODES - 1]; /* idx[j][k]: coordinate in mode in_modes[j] of nonzero k */
+    const uint32_t* idx[MTTKRP_MAX_MODES - 1]; /* idx[j][k]: coordinate in mode in_modes[j] of nonzero k,
+                                                   or 0x80000000 | s for the row in hot slot s */
     const float* val;             /* value of nonzero k */
     const uint32_t* winfo;        /* 2 words per 32 nonzeros: row-start bits, row ordinal of the first */
     const uint32_t* row_id;       /* output row of each nonempty row, increasing (nrows_nz) */
     const uint32_t* empty_rows;   /* rows without nonzeros, increasing (nempty) */
     const uint64_t* src_pos;      /* position in the caller's COO input of nonzero k */
+    uint64_t nhot;                /* rows per input mode served from LDS */
+    const uint32_t* hot_rows[MTTKRP_MAX_MODES - 1]; /* hot_rows[j][s]: row of mode in_modes[j] in slot s */
 } mttkrp_mode_view;
 
 mttkrp_status mttkrp_layout_view(mttkrp_handle h, int mode, mttkrp_mode_view* v);

@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmttkrp_hip.so")
+LIB_PATH = os.environ.get("MTTKRP_HIP_LIB") or os.path.join(_HERE, "libmttkrp_hip.so")
 
 MTTKRP_OK, MTTKRP_EINVAL, MTTKRP_ERANGE, MTTKRP_ENOMEM, MTTKRP_EUNSUPPORTED, MTTKRP_ENOTSPD, MTTKRP_EHIP = range(7)
 MTTKRP_FP32, MTTKRP_BF16 = 0, 1
@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "MTTKRP_OK", 1: "MTTKRP_EINVAL", 2: "MTTKRP_ERANGE", 3: "MTTK
 # Every symbol the header declares.
 EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "mttkrp_layout_bytes", "mttkrp_run",
             "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
-            "mttkrp_layout_view"]
+            "mttkrp_layout_view", "mttkrp_layout_info"]
 
 
 class MttkrpError(RuntimeError):
@@ -38,7 +38,7 @@ class MttkrpError(RuntimeError):
 
 class mttkrp_opts(ctypes.Structure):
     _fields_ = [("parts_per_cu", ctypes.c_int), ("factor_dtype", ctypes.c_int), ("max_R", ctypes.c_int),
-                ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int)]
+                ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int), ("hot_rows", ctypes.c_int)]
 
 
 class mttkrp_mode_view(ctypes.Structure):
@@ -48,7 +48,13 @@ class mttkrp_mode_view(ctypes.Structure):
                 ("idx", ctypes.POINTER(ctypes.c_uint32) * (MTTKRP_MAX_MODES - 1)),
                 ("val", ctypes.POINTER(ctypes.c_float)), ("winfo", ctypes.POINTER(ctypes.c_uint32)),
                 ("row_id", ctypes.POINTER(ctypes.c_uint32)), ("empty_rows", ctypes.POINTER(ctypes.c_uint32)),
-                ("src_pos", ctypes.POINTER(ctypes.c_uint64))]
+                ("src_pos", ctypes.POINTER(ctypes.c_uint64)), ("nhot", ctypes.c_uint64),
+                ("hot_rows", ctypes.POINTER(ctypes.c_uint32) * (MTTKRP_MAX_MODES - 1))]
+
+
+class mttkrp_info(ctypes.Structure):
+    _fields_ = [("cu_count", ctypes.c_uint32), ("lds_per_workgroup", ctypes.c_uint32), ("hot_rows", ctypes.c_uint32),
+                ("wg_threads", ctypes.c_uint32), ("parts_per_cu", ctypes.c_uint32)]
 
 
 def _load():
@@ -74,8 +80,9 @@ def _load():
     lib.mttkrp_last_error.argtypes = []
     lib.mttkrp_last_error.restype = ctypes.c_char_p
     lib.mttkrp_layout_view.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mttkrp_mode_view)]
+    lib.mttkrp_layout_info.argtypes = [vp, ctypes.POINTER(mttkrp_info)]
     for name in ("mttkrp_footprint", "mttkrp_layout_build", "mttkrp_run", "mttkrp_run_bf16", "cpd_als_init",
-                 "cpd_als_iter", "mttkrp_layout_view"):
+                 "cpd_als_iter", "mttkrp_layout_view", "mttkrp_layout_info"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -176,6 +183,12 @@ def mttkrp_layout_bytes(h: Layout) -> int:
     return int(_lib.mttkrp_layout_bytes(ctypes.c_void_p(h.ptr)))
 
 
+def mttkrp_layout_info(h: Layout) -> dict:
+    i = mttkrp_info()
+    _check(_lib.mttkrp_layout_info(ctypes.c_void_p(h.ptr), ctypes.byref(i)))
+    return {k: int(getattr(i, k)) for k, _ in mttkrp_info._fields_}
+
+
 def mttkrp_layout_free(h: Layout):
     h.free()
 
@@ -259,4 +272,5 @@ def mttkrp_layout_view(h: Layout, mode: int) -> dict:
                 idx=[arr(v.idx[j], v.nnz_pad, np.uint32) for j in range(v.n_in)],
                 val=arr(v.val, v.nnz_pad, np.float32), winfo=arr(v.winfo, 2 * (v.nnz_pad // 32), np.uint32),
                 row_id=arr(v.row_id, v.nrows_nz, np.uint32), empty_rows=arr(v.empty_rows, v.nempty, np.uint32),
-                src_pos=arr(v.src_pos, v.nnz, np.uint64))
+                src_pos=arr(v.src_pos, v.nnz, np.uint64), nhot=int(v.nhot),
+                hot_rows=[arr(v.hot_rows[j], v.nhot, np.uint32) for j in range(v.n_in)])

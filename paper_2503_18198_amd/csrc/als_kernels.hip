@@ -15,7 +15,7 @@
 namespace mk {
 namespace {
 
-constexpr int kRowsTile = 256 / 16;   // rows per LDS tile in the Gram kernel (R >= 16)
+constexpr int kRowsTile = 16;   // rows staged in LDS per step of the row passes
 
 // Block b of `nblk` covers rows [b * rpb, min((b+1) * rpb, I)).
 __device__ __forceinline__ void block_rows(uint32_t I, uint32_t rpb, uint32_t& r0, uint32_t& r1)
@@ -25,52 +25,66 @@ __device__ __forceinline__ void block_rows(uint32_t I, uint32_t rpb, uint32_t& r
 }
 
 // part[b][r*R + c] = sum over the block's rows i of A[i][r] * A[i][c].
-__global__ __launch_bounds__(kWG) void gram_partial_kernel(const float* __restrict__ A, uint32_t I, int R,
-                                                           uint32_t rpb, double* __restrict__ part)
+// Thread (bi, bj) of a 16 x 16 grid owns the B x B entry block (B = R/16)
+// with rows bi*B.. and columns bj*B..; rows are staged 16 at a time in LDS.
+template <int R>
+__global__ __launch_bounds__(kWG) void gram_partial_kernel(const float* __restrict__ A, uint32_t I, uint32_t rpb,
+                                                           double* __restrict__ part)
 {
-    __shared__ double tile[kRowsTile * 64];
+    constexpr int B = R / 16;
+    __shared__ double tile[kRowsTile * R];
     const int tid = threadIdx.x;
-    const int RR = R * R;
-    double acc[16];
+    const int bi = tid / 16, bj = tid % 16;
+    double acc[B][B];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+        for (int j = 0; j < B; ++j) acc[i][j] = 0.0;
     uint32_t r0, r1;
     block_rows(I, rpb, r0, r1);
-    const int T = kWG / R > kRowsTile ? kRowsTile : kWG / R;  // rows loaded per tile, one element per thread
-    for (uint32_t i0 = r0; i0 < r1; i0 += T) {
-        const uint32_t nrow = min((uint32_t)T, r1 - i0);
+    for (uint32_t i0 = r0; i0 < r1; i0 += kRowsTile) {
+        const uint32_t nrow = min((uint32_t)kRowsTile, r1 - i0);
         __syncthreads();
-        if (tid < (int)nrow * R) tile[tid] = (double)A[(uint64_t)i0 * R + tid];
+        for (int e = tid; e < kRowsTile * R; e += kWG)
+            tile[e] = e < (int)(nrow * R) ? (double)A[(uint64_t)i0 * R + e] : 0.0;
         __syncthreads();
+#pragma unroll 4
+        for (int t = 0; t < kRowsTile; ++t) {
+            double x[B], y[B];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int e = tid + j * kWG;
-            if (e < RR) {
-                const int r = e / R, c = e % R;
-                double s = 0.0;
-                for (uint32_t t = 0; t < nrow; ++t) s += tile[t * R + r] * tile[t * R + c];
-                acc[j] += s;
+            for (int i = 0; i < B; ++i) {
+                x[i] = tile[t * R + bi * B + i];
+                y[i] = tile[t * R + bj * B + i];
             }
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc[i][j] += x[i] * y[j];
         }
     }
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int e = tid + j * kWG;
-        if (e < RR) part[(uint64_t)blockIdx.x * RR + e] = acc[j];
-    }
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+        for (int j = 0; j < B; ++j) part[(uint64_t)blockIdx.x * R * R + (bi * B + i) * R + bj * B + j] = acc[i][j];
 }
 
-// out[e] = sum over blocks b (in order) of part[b * K + e].  op 1: out[e] =
-// sqrt(sum), with 1 in place of 0 (column norms).
+// out[e] = sum over blocks b of part[b * K + e], one wave per entry: lane j
+// adds blocks j, j+64, ... in order, then a fixed butterfly adds the 64 lane
+// sums.  op 1: out[e] = sqrt(sum), with 1 in place of 0 (column norms).
 __global__ __launch_bounds__(kWG) void reduce_partials_kernel(const double* __restrict__ part, int nblk, int K,
                                                               double* __restrict__ out, int op)
 {
-    const int e = blockIdx.x * kWG + threadIdx.x;
+    const int e = blockIdx.x * (kWG / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
     if (e >= K) return;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(uint64_t)b * K + e];
-    if (op == 1) s = s > 0.0 ? sqrt(s) : 1.0;
-    out[e] = s;
+    for (int b = lane; b < nblk; b += 64) s += part[(uint64_t)b * K + e];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        if (op == 1) s = s > 0.0 ? sqrt(s) : 1.0;
+        out[e] = s;
+    }
 }
 
 // V = Hadamard product of all Gram matrices except `skip` (skip = -1: all).
@@ -89,13 +103,14 @@ __global__ __launch_bounds__(kWG) void hadamard_kernel(const double* __restrict_
 }
 
 // Cholesky factor V = L L^T (lower, in LDS), L^{-1} by forward substitution
-// (one column per thread, kept in `scratch`), then W = L^{-T} L^{-1} = V^{-1}.
-// A non-positive pivot sets *flag = 1 and fills W with NaN.
+// (one column per thread, also in LDS), then W = L^{-T} L^{-1} = V^{-1}.
+// A pivot that is not positive beyond rounding sets *flag = 1 and fills W
+// with NaN.
 __global__ __launch_bounds__(kWG) void cholesky_inverse_kernel(const double* __restrict__ V, int R,
-                                                               double* __restrict__ W, double* __restrict__ scratch,
-                                                               double* flag)
+                                                               double* __restrict__ W, double* flag)
 {
     __shared__ double L[64 * 64];
+    __shared__ double Li[64 * 64];
     __shared__ int bad;
     const int tid = threadIdx.x;
     const int RR = R * R;
@@ -104,9 +119,12 @@ __global__ __launch_bounds__(kWG) void cholesky_inverse_kernel(const double* __r
     __syncthreads();
     for (int j = 0; j < R; ++j) {
         if (tid == 0) {
-            double d = L[j * R + j];
+            // A pivot at rounding level relative to V_jj means V is singular to
+            // working precision: report it instead of dividing by noise.
+            const double vjj = L[j * R + j];
+            double d = vjj;
             for (int k = 0; k < j; ++k) d -= L[j * R + k] * L[j * R + k];
-            if (!(d > 0.0) || !isfinite(d)) {
+            if (!(d > 0.0) || d <= 64.0 * 2.220446049250313e-16 * fabs(vjj) || !isfinite(d)) {
                 bad = 1;
                 d = 1.0;
             }
@@ -124,63 +142,82 @@ __global__ __launch_bounds__(kWG) void cholesky_inverse_kernel(const double* __r
     // Column c of L^{-1}: x_i = 0 (i < c), x_c = 1 / L_cc, x_i = -(sum_{c<=k<i} L_ik x_k) / L_ii.
     if (tid < R) {
         const int c = tid;
-        for (int i = 0; i < c; ++i) scratch[i * R + c] = 0.0;
-        scratch[c * R + c] = 1.0 / L[c * R + c];
+        for (int i = 0; i < c; ++i) Li[i * R + c] = 0.0;
+        Li[c * R + c] = 1.0 / L[c * R + c];
         for (int i = c + 1; i < R; ++i) {
             double s = 0.0;
-            for (int k = c; k < i; ++k) s += L[i * R + k] * scratch[k * R + c];
-            scratch[i * R + c] = -s / L[i * R + i];
+            for (int k = c; k < i; ++k) s += L[i * R + k] * Li[k * R + c];
+            Li[i * R + c] = -s / L[i * R + i];
         }
     }
-    __threadfence_block();
     __syncthreads();
     // W[i][j] = sum_k Linv[k][i] * Linv[k][j], k >= max(i, j).
     for (int e = tid; e < RR; e += kWG) {
         const int i = e / R, j = e % R;
         double s = 0.0;
-        for (int k = max(i, j); k < R; ++k) s += scratch[k * R + i] * scratch[k * R + j];
+        for (int k = max(i, j); k < R; ++k) s += Li[k * R + i] * Li[k * R + j];
         W[e] = bad ? __longlong_as_double(0x7ff8000000000000ll) : s;
     }
     if (tid == 0 && bad) *flag = 1.0;
 }
 
-// Rows of M W (FP64).  op 0: per-block column sums of squares -> part[b][c].
-// op 1: A[i][c] = (M W)[i][c] / lam[c], stored as fp32.
+// Rows of M W (FP64).  Thread (row ri of 32, column group cg of 8) computes
+// the B = R/8 columns cg*B.. of its row.  op 0: per-block column sums of
+// squares -> part[b][c].  op 1: A[i][c] = (M W)[i][c] / lam[c], stored as fp32.
+template <int R>
 __global__ __launch_bounds__(kWG) void mw_kernel(const float* __restrict__ M, const double* __restrict__ W, uint32_t I,
-                                                 int R, uint32_t rpb, int op, const double* __restrict__ lam,
+                                                 uint32_t rpb, int op, const double* __restrict__ lam,
                                                  float* __restrict__ A, double* __restrict__ part)
 {
-    __shared__ double sW[64 * 64];
-    __shared__ double sM[kWG];
-    __shared__ double sred[kWG];
+    constexpr int B = R / 8;
+    constexpr int kRows = kWG / 8;
+    __shared__ double sW[R * R];
+    __shared__ double sM[kRows * R];
+    __shared__ double sred[kWG * B];
     const int tid = threadIdx.x;
-    const int RR = R * R;
-    for (int e = tid; e < RR; e += kWG) sW[e] = W[e];
-    const int rows_per_pass = kWG / R;
-    const int c = tid % R;
-    const int ri = tid / R;
-    const double inv = op == 1 ? 1.0 / lam[c] : 0.0;
-    double colsq = 0.0;
+    for (int e = tid; e < R * R; e += kWG) sW[e] = W[e];
+    const int ri = tid / 8;
+    const int cg = tid % 8;
+    double inv[B];
+    double colsq[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+        inv[j] = op == 1 ? 1.0 / lam[cg * B + j] : 0.0;
+        colsq[j] = 0.0;
+    }
     uint32_t r0, r1;
     block_rows(I, rpb, r0, r1);
-    for (uint32_t i0 = r0; i0 < r1; i0 += rows_per_pass) {
-        const uint32_t i = i0 + ri;
+    for (uint32_t i0 = r0; i0 < r1; i0 += kRows) {
+        const uint32_t nrow = min((uint32_t)kRows, r1 - i0);
         __syncthreads();
-        sM[tid] = i < r1 ? (double)M[(uint64_t)i * R + c] : 0.0;
+        for (int e = tid; e < kRows * R; e += kWG)
+            sM[e] = e < (int)(nrow * R) ? (double)M[(uint64_t)i0 * R + e] : 0.0;
         __syncthreads();
-        if (i < r1) {
-            double s = 0.0;
-            for (int k = 0; k < R; ++k) s += sM[ri * R + k] * sW[k * R + c];
-            if (op == 0) colsq += s * s;
-            else A[(uint64_t)i * R + c] = (float)(s * inv);
+        if ((uint32_t)ri < nrow) {
+            double acc[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) acc[j] = 0.0;
+#pragma unroll 8
+            for (int k = 0; k < R; ++k) {
+                const double m = sM[ri * R + k];
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc[j] += m * sW[k * R + cg * B + j];
+            }
+            const uint64_t row = i0 + ri;
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                if (op == 0) colsq[j] += acc[j] * acc[j];
+                else A[row * R + cg * B + j] = (float)(acc[j] * inv[j]);
+            }
         }
     }
     if (op == 0) {
-        sred[tid] = colsq;
+#pragma unroll
+        for (int j = 0; j < B; ++j) sred[(cg * B + j) * kRows + ri] = colsq[j];
         __syncthreads();
         if (tid < R) {
             double t = 0.0;
-            for (int j = 0; j < rows_per_pass; ++j) t += sred[j * R + tid];
+            for (int r = 0; r < kRows; ++r) t += sred[tid * kRows + r];
             part[(uint64_t)blockIdx.x * R + tid] = t;
         }
     }
@@ -265,10 +302,14 @@ hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w
 {
     uint32_t rpb;
     const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
-    hipLaunchKernelGGL(gram_partial_kernel, dim3(nb), dim3(kWG), 0, s, A, I, R, rpb, w.part);
+    switch (R) {
+        case 16: hipLaunchKernelGGL(gram_partial_kernel<16>, dim3(nb), dim3(kWG), 0, s, A, I, rpb, w.part); break;
+        case 32: hipLaunchKernelGGL(gram_partial_kernel<32>, dim3(nb), dim3(kWG), 0, s, A, I, rpb, w.part); break;
+        case 64: hipLaunchKernelGGL(gram_partial_kernel<64>, dim3(nb), dim3(kWG), 0, s, A, I, rpb, w.part); break;
+        default: return hipErrorInvalidValue;
+    }
     const int K = R * R;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((K + kWG - 1) / kWG), dim3(kWG), 0, s, w.part, (int)nb, K, G_out,
-                       0);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((K + 3) / 4), dim3(kWG), 0, s, w.part, (int)nb, K, G_out, 0);
     return hipGetLastError();
 }
 
@@ -281,7 +322,8 @@ hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, 
 
 hipError_t als_cholesky_inverse(const double* V, int R, double* W, double* scratch, double* flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(cholesky_inverse_kernel, dim3(1), dim3(kWG), 0, s, V, R, W, scratch, flag);
+    (void)scratch;
+    hipLaunchKernelGGL(cholesky_inverse_kernel, dim3(1), dim3(kWG), 0, s, V, R, W, flag);
     return hipGetLastError();
 }
 
@@ -290,11 +332,21 @@ hipError_t als_solve_normalize(const float* M, const double* W, uint32_t I, int 
 {
     uint32_t rpb;
     const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
-    hipLaunchKernelGGL(mw_kernel, dim3(nb), dim3(kWG), 0, s, M, W, I, R, rpb, 0, (const double*)nullptr,
-                       (float*)nullptr, w.part);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kWG), 0, s, w.part, (int)nb, R, lam, 1);
-    hipLaunchKernelGGL(mw_kernel, dim3(nb), dim3(kWG), 0, s, M, W, I, R, rpb, 1, (const double*)lam, A,
-                       (double*)nullptr);
+    auto pass = [&](int op) {
+        const double* lp = op == 1 ? lam : nullptr;
+        float* Ap = op == 1 ? A : nullptr;
+        double* pp = op == 0 ? w.part : nullptr;
+        switch (R) {
+            case 16: hipLaunchKernelGGL(mw_kernel<16>, dim3(nb), dim3(kWG), 0, s, M, W, I, rpb, op, lp, Ap, pp); break;
+            case 32: hipLaunchKernelGGL(mw_kernel<32>, dim3(nb), dim3(kWG), 0, s, M, W, I, rpb, op, lp, Ap, pp); break;
+            case 64: hipLaunchKernelGGL(mw_kernel<64>, dim3(nb), dim3(kWG), 0, s, M, W, I, rpb, op, lp, Ap, pp); break;
+            default: break;
+        }
+    };
+    if (R != 16 && R != 32 && R != 64) return hipErrorInvalidValue;
+    pass(0);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((R + 3) / 4), dim3(kWG), 0, s, w.part, (int)nb, R, lam, 1);
+    pass(1);
     return hipGetLastError();
 }
 
@@ -304,7 +356,7 @@ hipError_t als_fit(const float* M, const float* A, uint32_t I, const double* lam
     uint32_t rpb;
     const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
     hipLaunchKernelGGL(coldot_kernel, dim3(nb), dim3(kWG), 0, s, M, A, I, R, rpb, w.part);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kWG), 0, s, w.part, (int)nb, R, w.colsq, 0);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((R + 3) / 4), dim3(kWG), 0, s, w.part, (int)nb, R, w.colsq, 0);
     hipLaunchKernelGGL(fit_kernel, dim3(1), dim3(kWG), 0, s, (const double*)w.colsq, lam, grams, N, R, normX2,
                        fit_out, lam_out);
     return hipGetLastError();

@@ -70,11 +70,36 @@ Workspace plan_workspace(const uint32_t* dims, int N, int maxR, int dtype)
     return w;
 }
 
+constexpr uint32_t kAssumedLds = 160 * 1024;   // gfx950 LDS per workgroup, for host-only layouts
+
+// Rows per input mode that the partition kernel can keep in LDS: the hot rows
+// of the N-1 input modes, at max_R fp32 values each, must fit next to the
+// kernel's bookkeeping.
+uint32_t hot_rows_for(int N, int maxR, uint32_t lds_limit, int requested)
+{
+    if (requested == 0) return 0;
+    // Workgroups of 512 threads or more run one to a CU (registers) and own
+    // its whole LDS; 256-thread ones (4+ modes) run four to a CU and get a
+    // quarter each.
+    const uint32_t budget = mk::partition_wg_threads(N - 1) >= 512 ? lds_limit : lds_limit / 4;
+    const uint32_t fixed = mk::partition_lds_bytes(N - 1, 16, MTTKRP_FP32, 0);     // slots + bookkeeping
+    const uint32_t meta = fixed - 2u * (uint32_t)(mk::partition_wg_threads(N - 1) / 4) * 16u * 4u;
+    if (budget <= fixed) return 0;
+    uint32_t k = (budget - meta) / ((uint32_t)(N - 1) * (uint32_t)maxR * 4u);
+    if (requested > 0 && (uint32_t)requested < k) k = (uint32_t)requested;
+    return k;
+}
+
 uint64_t copies_bytes(const uint32_t* dims, int N, uint64_t nnz)
 {
     uint64_t b = 0;
     for (int n = 0; n < N; ++n) b += mk::mode_device_bytes(nnz, N, dims[n]) + (uint64_t)(N + 4) * kAlign;
     return b;
+}
+
+uint64_t hot_bytes(int N, uint32_t nhot)
+{
+    return (uint64_t)N * (align_up((uint64_t)nhot * 4ull) + kAlign);
 }
 
 }  // namespace
@@ -88,6 +113,10 @@ struct mttkrp_layout {
     int cu_count = 256;
     bool host_only = false;
     std::vector<mk::HostMode> host;
+    std::vector<mk::HotSet> hot;                       // host-only handles
+    uint32_t nhot = 0;                                 // hot rows per input mode
+    uint32_t lds_limit = 0;                            // LDS bytes per workgroup on the device
+    const uint32_t* hot_rows[MTTKRP_MAX_MODES] = {};   // device tables, slot -> row, per mode
     mk::DevMode dev[MTTKRP_MAX_MODES];
     void* dmem = nullptr;
     uint64_t dbytes = 0;
@@ -102,11 +131,12 @@ extern "C" {
 void mttkrp_opts_default(mttkrp_opts* o)
 {
     if (!o) return;
-    o->parts_per_cu = 8;
+    o->parts_per_cu = 2;
     o->factor_dtype = MTTKRP_FP32;
     o->max_R = 64;
     o->hbm_budget_bytes = 0;
     o->host_only = 0;
+    o->hot_rows = -1;
 }
 
 const char* mttkrp_last_error(void) { return g_err.c_str(); }
@@ -115,7 +145,7 @@ static mttkrp_status check_opts(const mttkrp_opts* in, mttkrp_opts* o)
 {
     mttkrp_opts_default(o);
     if (in) *o = *in;
-    if (o->parts_per_cu <= 0) o->parts_per_cu = 8;
+    if (o->parts_per_cu <= 0) o->parts_per_cu = 2;
     if (o->max_R == 0) o->max_R = 64;
     if (!r_supported(o->max_R)) return fail(MTTKRP_EUNSUPPORTED, "max_R must be 16, 32 or 64");
     if (o->factor_dtype != MTTKRP_FP32 && o->factor_dtype != MTTKRP_BF16)
@@ -133,7 +163,8 @@ mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const 
     mttkrp_opts o;
     mttkrp_status s = check_opts(opts, &o);
     if (s) return s;
-    *bytes = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total;
+    *bytes = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total +
+             hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows));
     return MTTKRP_OK;
 }
 
@@ -152,10 +183,27 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     std::string msg = mk::validate_coo(coo_idx, nnz, dims, N, &range_err);
     if (!msg.empty()) return fail(range_err ? MTTKRP_ERANGE : MTTKRP_EINVAL, msg);
 
-    const uint64_t need = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total;
-    if (!o.host_only && o.hbm_budget_bytes && need > o.hbm_budget_bytes)
-        return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(need) + " B exceeds the budget of " +
-                                       std::to_string(o.hbm_budget_bytes) + " B");
+    // Admission first, before any device call (the hot tables are sized for the
+    // largest LDS, an upper bound).
+    {
+        const uint64_t bound = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total +
+                               hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows));
+        if (!o.host_only && o.hbm_budget_bytes && bound > o.hbm_budget_bytes)
+            return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(bound) + " B exceeds the budget of " +
+                                           std::to_string(o.hbm_budget_bytes) + " B");
+    }
+    uint32_t lds_limit = kAssumedLds;
+    int dev_id = 0;
+    if (!o.host_only) {
+        hipError_t e0 = hipGetDevice(&dev_id);
+        if (e0 != hipSuccess) return hip_fail(e0, "hipGetDevice");
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id) == hipSuccess && v > 0)
+            lds_limit = (uint32_t)v;
+    }
+    const uint32_t nhot = hot_rows_for(N, o.max_R, lds_limit, o.hot_rows);
+    const uint64_t need = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total +
+                          hot_bytes(N, nhot);
 
     auto* h = new mttkrp_layout();
     h->N = N;
@@ -163,20 +211,23 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     h->nnz = nnz;
     h->opts = o;
     h->host_only = o.host_only != 0;
+    h->nhot = nhot;
+    h->lds_limit = lds_limit;
+    h->device = dev_id;
 
     const int threads = host_threads();
+    std::vector<mk::HotSet> hot = mk::select_hot_rows(coo_idx, nnz, dims, N, nhot);
     if (h->host_only) {
         h->host.resize(N);
-        for (int n = 0; n < N; ++n) mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, true, threads, h->host[n]);
+        for (int n = 0; n < N; ++n)
+            mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, true, threads, &hot, h->host[n]);
+        for (auto& hs : hot) hs.rows.resize(nhot, 0u);
+        h->hot = std::move(hot);
         *out = h;
         return MTTKRP_OK;
     }
 
-    hipError_t e = hipGetDevice(&h->device);
-    if (e != hipSuccess) {
-        delete h;
-        return hip_fail(e, "hipGetDevice");
-    }
+    hipError_t e = hipSuccess;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
         h->cu_count = cus;
@@ -217,11 +268,21 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     if (o.factor_dtype == MTTKRP_BF16)
         for (int m = 0; m < N; ++m) h->als.bf16[m] = static_cast<uint16_t*>(take((uint64_t)dims[m] * o.max_R * 2));
 
+    // Hot-row tables (padded to nhot entries; unused slots name row 0).
+    for (int m = 0; m < N; ++m) {
+        std::vector<uint32_t>& rows = hot[m].rows;
+        rows.resize(nhot, 0u);
+        void* dst = take(nhot ? (uint64_t)nhot * 4 : 4);
+        if (nhot && e == hipSuccess) e = hipMemcpyAsync(dst, rows.data(), (uint64_t)nhot * 4, hipMemcpyHostToDevice, stream);
+        h->hot_rows[m] = static_cast<const uint32_t*>(dst);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+
     // Mode copies: build on the host one mode at a time, upload, release.
     double normX2 = 0.0;
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         mk::HostMode hm;
-        mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, false, threads, hm);
+        mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, false, threads, &hot, hm);
         mk::DevMode& d = h->dev[n];
         d.nnz = hm.nnz;
         d.nnz_pad = hm.nnz_pad;
@@ -235,6 +296,7 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
         };
         for (int j = 0; j < N - 1; ++j) {
             d.in_modes[j] = hm.in_modes[j];
+            d.in_dims[j] = dims[hm.in_modes[j]];
             d.idx[j] = static_cast<const uint32_t*>(up(hm.idx[j].data(), hm.nnz_pad * 4));
         }
         d.val = static_cast<const float*>(up(hm.val.data(), hm.nnz_pad * 4));
@@ -276,6 +338,18 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
 
 uint64_t mttkrp_layout_bytes(mttkrp_handle h) { return h ? h->dbytes : 0; }
 
+mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info)
+{
+    g_err.clear();
+    if (!h || !info) return fail(MTTKRP_EINVAL, "NULL handle or info");
+    info->cu_count = (uint32_t)h->cu_count;
+    info->lds_per_workgroup = h->lds_limit;
+    info->hot_rows = h->nhot;
+    info->wg_threads = (uint32_t)mk::partition_wg_threads(h->N - 1);
+    info->parts_per_cu = (uint32_t)h->opts.parts_per_cu;
+    return MTTKRP_OK;
+}
+
 void mttkrp_layout_free(mttkrp_handle h)
 {
     if (!h) return;
@@ -308,6 +382,8 @@ mttkrp_status mttkrp_layout_view(mttkrp_handle h, int mode, mttkrp_mode_view* v)
     v->row_id = m.row_id.data();
     v->empty_rows = m.empty_rows.data();
     v->src_pos = m.src_pos.data();
+    v->nhot = h->nhot;
+    for (int j = 0; j < v->n_in; ++j) v->hot_rows[j] = h->hot[m.in_modes[j]].rows.data();
     return MTTKRP_OK;
 }
 
@@ -320,6 +396,9 @@ static mttkrp_status check_run(mttkrp_handle h, int mode, const void* const* fac
     if (R > h->opts.max_R) return fail(MTTKRP_EINVAL, "R exceeds the handle's max_R");
     if (!factors || !out) return fail(MTTKRP_EINVAL, "NULL factors or out");
     if (reinterpret_cast<uintptr_t>(out) % 16) return fail(MTTKRP_EINVAL, "out must be 16-byte aligned");
+    for (int m = 0; m < h->N; ++m)
+        if ((uint64_t)h->dims[m] * (uint64_t)R * 4ull >= 0xFFFFFFF0ull)
+            return fail(MTTKRP_EUNSUPPORTED, "factor " + std::to_string(m) + " is 4 GiB or larger");
     for (int m = 0; m < h->N; ++m) {
         if (m == mode) continue;
         if (!factors[m]) return fail(MTTKRP_EINVAL, "factor " + std::to_string(m) + " is NULL");
@@ -334,9 +413,13 @@ static mttkrp_status run_mode(mttkrp_handle h, int mode, const void* const* fact
 {
     const mk::DevMode& d = h->dev[mode];
     const void* fac[mk::kMaxIn];
-    for (int j = 0; j < d.n_in; ++j) fac[j] = factors[d.in_modes[j]];
-    const mk::Geometry g = mk::plan_geometry(d.nnz, R, dtype, h->opts.parts_per_cu * h->cu_count, kMaxParts);
-    hipError_t e = mk::launch_mttkrp(d, h->N, R, dtype, fac, out, h->carry, g, h->dims[mode], stream);
+    const uint32_t* hot[mk::kMaxIn];
+    for (int j = 0; j < d.n_in; ++j) {
+        fac[j] = factors[d.in_modes[j]];
+        hot[j] = h->hot_rows[d.in_modes[j]];
+    }
+    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+    hipError_t e = mk::launch_mttkrp(d, R, dtype, fac, hot, h->nhot, out, h->carry, g, stream);
     if (e != hipSuccess) return hip_fail(e, "MTTKRP launch");
     return MTTKRP_OK;
 }

@@ -18,6 +18,7 @@ struct DevMode {
     uint64_t nnz = 0, nnz_pad = 0, nrows_nz = 0, nempty = 0;
     int n_in = 0;
     int in_modes[kMaxIn] = {};
+    uint32_t in_dims[kMaxIn] = {};     // I_m of each input mode
     const uint32_t* idx[kMaxIn] = {};  // SoA input-mode coordinates
     const float* val = nullptr;
     const uint2* winfo = nullptr;      // per 32 nonzeros: {row-start bits, ordinal of the row holding the first}
@@ -27,19 +28,27 @@ struct DevMode {
 
 // Launch geometry of one MTTKRP call.
 struct Geometry {
-    int lanes;          // lanes per group: one 16-byte slice of a factor row per lane
+    int lanes;          // lanes per group: four factor values per lane
     int groups;         // lane groups per workgroup
     uint32_t gsz;       // nonzeros per lane group (multiple of 32)
     uint64_t wgc;       // nonzeros per workgroup partition = groups * gsz
     uint32_t nparts;    // workgroups
 };
 
-Geometry plan_geometry(uint64_t nnz, int R, int dtype, int parts_per_cu, uint32_t max_parts);
+Geometry plan_geometry(uint64_t nnz, int n_in, int R, int target_parts, uint32_t max_parts);
+
+// Threads per partition workgroup for n_in input modes.
+int partition_wg_threads(int n_in);
+
+// Dynamic LDS of the partition kernel for n_in input modes and nhot cached rows per mode.
+uint32_t partition_lds_bytes(int n_in, int R, int dtype, uint32_t nhot);
 
 // Enqueue the per-mode MTTKRP: partition kernel then fix-up kernel.
-// `fac` holds the N-1 input factors in the order of m.in_modes.
-hipError_t launch_mttkrp(const DevMode& m, int N, int R, int dtype, const void* const* fac, float* out,
-                         float* carry, const Geometry& g, uint32_t rows_out, hipStream_t s);
+// `fac` and `hot_rows` hold the N-1 input factors and their hot-row tables in
+// the order of m.in_modes; nhot rows of each are cached in LDS.
+hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* fac,
+                         const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry,
+                         const Geometry& g, hipStream_t s);
 
 // CP-ALS helpers (als_kernels.hip).  All FP64 unless noted.
 struct AlsWork {

@@ -88,8 +88,28 @@ uint64_t mode_device_bytes(uint64_t nnz, int N, uint64_t I_mode)
     return pad * (4ull * (N - 1) + 4ull) + (pad / 32) * 8ull + 4ull * I_mode;
 }
 
+std::vector<HotSet> select_hot_rows(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N, uint32_t k)
+{
+    std::vector<HotSet> hs(N);
+    for (int m = 0; m < N; ++m) {
+        std::vector<uint64_t> deg(dims[m], 0);
+        for (uint64_t e = 0; e < nnz; ++e) deg[coo[e * N + m]]++;
+        std::vector<uint32_t> cand;
+        for (uint32_t i = 0; i < dims[m]; ++i)
+            if (deg[i] >= 2) cand.push_back(i);
+        const size_t take = std::min<size_t>(k, cand.size());
+        std::partial_sort(cand.begin(), cand.begin() + take, cand.end(), [&](uint32_t a, uint32_t b) {
+            return deg[a] != deg[b] ? deg[a] > deg[b] : a < b;
+        });
+        hs[m].rows.assign(cand.begin(), cand.begin() + take);
+        hs[m].slot.assign(dims[m], -1);
+        for (size_t j = 0; j < take; ++j) hs[m].slot[hs[m].rows[j]] = (int32_t)j;
+    }
+    return hs;
+}
+
 void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const uint32_t* dims, int N, int mode,
-                     bool keep_src_pos, int threads, HostMode& out)
+                     bool keep_src_pos, int threads, const std::vector<HotSet>* hot, HostMode& out)
 {
     const int n = mode;
     const uint64_t I = dims[n];
@@ -158,7 +178,12 @@ void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const
     parallel_for(nnz, threads, [&](uint64_t lo, uint64_t hi) {
         for (uint64_t k = lo; k < hi; ++k) {
             const uint64_t p = perm[k];
-            for (int j = 0; j < n_in; ++j) out.idx[j][k] = coo[p * N + out.in_modes[j]];
+            for (int j = 0; j < n_in; ++j) {
+                const int m = out.in_modes[j];
+                const uint32_t v = coo[p * N + m];
+                const int32_t sl = hot ? (*hot)[m].slot[v] : -1;
+                out.idx[j][k] = sl >= 0 ? (kHotBit | (uint32_t)sl) : v;
+            }
             out.val[k] = vals[p];
             if (keep_src_pos) out.src_pos[k] = p;
         }

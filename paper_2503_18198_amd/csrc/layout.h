@@ -25,13 +25,26 @@ struct HostMode {
     std::vector<uint64_t> src_pos;             // [nnz] (kept only on request)
 };
 
+// Coordinates of rows served from the on-chip cache are stored as
+// kHotBit | slot; slot indexes the hot-row table of that input mode.
+constexpr uint32_t kHotBit = 0x80000000u;
+
+// Per mode: the rows gathered most often (highest degree, at least 2, ties by
+// row index), at most k of them, and for every row its slot or -1.
+struct HotSet {
+    std::vector<uint32_t> rows;   // slot -> row
+    std::vector<int32_t> slot;    // row -> slot or -1
+};
+
+std::vector<HotSet> select_hot_rows(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N, uint32_t k);
+
 // Validate a COO tensor.  Returns an empty string when valid, else a message;
 // *range_error is set when the failure is a coordinate out of range.
 std::string validate_coo(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N, bool* range_error);
 
 // Build the copy for output mode `mode`.  `threads` host threads are used.
 void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const uint32_t* dims, int N, int mode,
-                     bool keep_src_pos, int threads, HostMode& out);
+                     bool keep_src_pos, int threads, const std::vector<HotSet>* hot, HostMode& out);
 
 // Bytes of one mode copy on the device (arrays only, without alignment padding).
 uint64_t mode_device_bytes(uint64_t nnz, int N, uint64_t I_mode);

@@ -26,12 +26,23 @@
 //    row") plus, per 32 nonzeros, the ordinal of the row holding the first
 //    one; ordinals map to output rows through the list of nonempty rows.
 #include "internal.h"
+#include "part_kernel.h"
 
 namespace mk {
 
-template <int NIN>
-hipError_t launch_part_nin(const DevMode& m, int R, int dtype, const void* const* fac, float* out, float* carry,
-                           const Geometry& g, hipStream_t s);
+// Instantiated in part_n3.hip .. part_n8.hip.
+extern template hipError_t launch_part_nin<2>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+extern template hipError_t launch_part_nin<3>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+extern template hipError_t launch_part_nin<4>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+extern template hipError_t launch_part_nin<5>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+extern template hipError_t launch_part_nin<6>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+extern template hipError_t launch_part_nin<7>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
 
 namespace {
 
@@ -108,12 +119,11 @@ __global__ __launch_bounds__(kWG) void mttkrp_fixup_kernel(FixArgs a)
 
 }  // namespace
 
-Geometry plan_geometry(uint64_t nnz, int R, int dtype, int target_parts, uint32_t max_parts)
+Geometry plan_geometry(uint64_t nnz, int n_in, int R, int target_parts, uint32_t max_parts)
 {
     Geometry g;
-    const int elem = dtype == MTTKRP_FP32 ? 4 : 2;
-    g.lanes = R * elem / 16;
-    g.groups = kWG / g.lanes;
+    g.lanes = R / 4;
+    g.groups = part_wg(n_in) / g.lanes;
     if (target_parts < 1) target_parts = 1;
     uint64_t per_group = (nnz + (uint64_t)target_parts * g.groups - 1) / ((uint64_t)target_parts * g.groups);
     uint64_t gsz = (per_group + 31) / 32 * 32;
@@ -132,20 +142,23 @@ Geometry plan_geometry(uint64_t nnz, int R, int dtype, int target_parts, uint32_
     return g;
 }
 
-hipError_t launch_mttkrp(const DevMode& m, int N, int R, int dtype, const void* const* fac, float* out,
-                         float* carry, const Geometry& g, uint32_t rows_out, hipStream_t s)
+uint32_t partition_lds_bytes(int n_in, int R, int dtype, uint32_t nhot) { return part_lds_bytes(n_in, R, dtype, nhot); }
+
+int partition_wg_threads(int n_in) { return part_wg(n_in); }
+
+hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* fac,
+                         const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry,
+                         const Geometry& g, hipStream_t s)
 {
-    (void)N;
-    (void)rows_out;
     hipError_t e = hipSuccess;
     if (m.nnz > 0) {
         switch (m.n_in) {
-            case 2: e = launch_part_nin<2>(m, R, dtype, fac, out, carry, g, s); break;
-            case 3: e = launch_part_nin<3>(m, R, dtype, fac, out, carry, g, s); break;
-            case 4: e = launch_part_nin<4>(m, R, dtype, fac, out, carry, g, s); break;
-            case 5: e = launch_part_nin<5>(m, R, dtype, fac, out, carry, g, s); break;
-            case 6: e = launch_part_nin<6>(m, R, dtype, fac, out, carry, g, s); break;
-            case 7: e = launch_part_nin<7>(m, R, dtype, fac, out, carry, g, s); break;
+            case 2: e = launch_part_nin<2>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
+            case 3: e = launch_part_nin<3>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
+            case 4: e = launch_part_nin<4>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
+            case 5: e = launch_part_nin<5>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
+            case 6: e = launch_part_nin<6>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
+            case 7: e = launch_part_nin<7>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
             default: e = hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;

@@ -1,6 +1,20 @@
-// Partition kernel of the per-mode MTTKRP; the design is described at the top
-// of mttkrp_kernels.hip.  Included by one translation unit per mode count
-// (part_n3.hip .. part_n8.hip) so the instantiations build in parallel.
+// Partition kernel of the per-mode MTTKRP; the overall design is described at
+// the top of mttkrp_kernels.hip.  Included by one translation unit per mode
+// count (part_n3.hip .. part_n8.hip) so the instantiations build in parallel.
+//
+// Per workgroup (kPartWG threads, one partition of G * gsz nonzeros):
+//  1. The most frequently gathered rows of every input factor (the layout's
+//     hot rows, coordinates stored as kHotBit | slot) are copied into LDS.
+//  2. Each lane group of L = R/4 lanes (4 factor values per lane: 16 bytes in
+//     fp32, 8 in bf16) walks gsz consecutive nonzeros, 32 at a time: indices
+//     and values are streamed with full-line non-temporal loads and shared in
+//     the group with ds_swizzle; U nonzeros' row gathers are issued before
+//     any is used; a row repeated by the next nonzero is not gathered again;
+//     hot rows come from LDS, the rest from global memory.  The running row
+//     sum stays in registers and a row that ends inside the run is stored once.
+//  3. The first and last row partials of every group go to LDS (reusing the
+//     hot-row area) and are added in group order; rows cut by the
+//     workgroup's ends go to the carry buffer for the fix-up kernel.
 #pragma once
 
 #include <type_traits>
@@ -8,6 +22,31 @@
 #include "internal.h"
 
 namespace mk {
+
+constexpr uint32_t kHotBitDev = 0x80000000u;
+
+// Threads per partition workgroup: 1024 (16 waves sharing one LDS hot-row
+// cache) for 3-mode tensors, whose lane state fits in 128 registers; with 4
+// or more modes the per-nonzero state is larger, so 256-thread workgroups,
+// four per CU, each with a quarter of the LDS.
+#ifndef MK_WG_3MODE
+#define MK_WG_3MODE 1024
+#endif
+#ifndef MK_U_3MODE
+#define MK_U_3MODE 4
+#endif
+constexpr int part_wg(int n_in) { return n_in <= 2 ? MK_WG_3MODE : 256; }
+
+// Dynamic LDS bytes of a partition workgroup.
+inline uint32_t part_lds_bytes(int n_in, int R, int dtype, uint32_t nhot)
+{
+    const uint32_t groups = part_wg(n_in) / (R / 4);
+    const uint32_t es = dtype == MTTKRP_FP32 ? 4 : 2;
+    const uint32_t hot = (uint32_t)n_in * nhot * (uint32_t)R * es;
+    const uint32_t slots = 2u * groups * (uint32_t)R * 4u;
+    return (hot > slots ? hot : slots) + 2u * groups * 4u;
+}
+
 namespace part {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -24,7 +63,8 @@ __device__ __forceinline__ void static_for(F&& f)
 }
 
 // Value of lane SRC of each aligned group of L lanes, for every lane of the
-// group (ds_swizzle in bit mode: and-mask keeps the group, or-mask picks SRC).
+// group (ds_swizzle in bit mode: the and-mask keeps the group, the or-mask
+// selects SRC).
 template <int L, int SRC>
 __device__ __forceinline__ uint32_t group_bcast(uint32_t x)
 {
@@ -59,27 +99,51 @@ __device__ __forceinline__ void load_words(const uint32_t* p, uint32_t (&w)[V])
     }
 }
 
-// Elements per 16-byte slice.
+// Four consecutive factor values: 16 bytes of fp32 or 8 bytes of bf16.
 template <int DT>
-constexpr int vec_of() { return DT == MTTKRP_FP32 ? 4 : 8; }
+struct Slice {
+    using T = typename std::conditional<DT == MTTKRP_FP32, u32x4, u32x2>::type;
+    static constexpr int kBytes = DT == MTTKRP_FP32 ? 16 : 8;
+    static constexpr int kElem = DT == MTTKRP_FP32 ? 4 : 2;
+};
 
-// The 16-byte slice `gl` of row `row` of an I x R factor.
 template <int R, int DT>
-__device__ __forceinline__ u32x4 load_slice(const void* fac, uint32_t row, int gl)
+__device__ __forceinline__ typename Slice<DT>::T load_global(const void* fac, uint32_t row, int gl)
 {
-    if constexpr (DT == MTTKRP_FP32) {
-        const float* p = static_cast<const float*>(fac) + (uint64_t)row * R + gl * 4;
-        return *reinterpret_cast<const u32x4*>(p);
-    } else {
-        const uint16_t* p = static_cast<const uint16_t*>(fac) + (uint64_t)row * R + gl * 8;
-        return *reinterpret_cast<const u32x4*>(p);
-    }
+    const char* p = static_cast<const char*>(fac) + ((uint64_t)row * R + gl * 4) * Slice<DT>::kElem;
+    return *reinterpret_cast<const typename Slice<DT>::T*>(p);
 }
 
-// Unpack a slice into VEC floats (bf16 -> fp32 is exact: the bf16 bits are the
-// high half of the fp32 pattern).
+// Buffer-resource loads: 32-bit offsets, and an offset past the end returns
+// zero without touching memory, which turns a skipped gather into a no-op
+// lane instead of a branch.
+constexpr uint32_t kRsrcWord3 = 0x00020000u;   // raw buffer, gfx9-family format bits
+constexpr uint32_t kSkipOffset = 0xFFFFFFF0u;  // beyond every factor (factors are < 4 GiB - 16)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, (int)kRsrcWord3);
+}
+
 template <int DT>
-__device__ __forceinline__ void unpack(const u32x4 v, float* f)
+__device__ __forceinline__ typename Slice<DT>::T load_buffer(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (DT == MTTKRP_FP32) return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    else return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+}
+
+typedef __attribute__((address_space(3))) const char lds_char;
+
+template <int R, int DT>
+__device__ __forceinline__ typename Slice<DT>::T load_lds(lds_char* base, uint32_t slot, int gl)
+{
+    lds_char* p = base + (slot * R + gl * 4) * Slice<DT>::kElem;
+    return *reinterpret_cast<__attribute__((address_space(3))) const typename Slice<DT>::T*>(p);
+}
+
+// bf16 -> fp32 is exact: the bf16 bits are the high half of the fp32 pattern.
+template <int DT>
+__device__ __forceinline__ void unpack4(const typename Slice<DT>::T v, float (&f)[4])
 {
     if constexpr (DT == MTTKRP_FP32) {
         f[0] = __uint_as_float(v.x);
@@ -91,27 +155,21 @@ __device__ __forceinline__ void unpack(const u32x4 v, float* f)
         f[1] = __uint_as_float(v.x & 0xffff0000u);
         f[2] = __uint_as_float(v.y << 16);
         f[3] = __uint_as_float(v.y & 0xffff0000u);
-        f[4] = __uint_as_float(v.z << 16);
-        f[5] = __uint_as_float(v.z & 0xffff0000u);
-        f[6] = __uint_as_float(v.w << 16);
-        f[7] = __uint_as_float(v.w & 0xffff0000u);
     }
 }
 
-template <int VEC>
-__device__ __forceinline__ void store_vec(float* dst, const float* v)
+__device__ __forceinline__ void store4(float* dst, const float (&v)[4])
 {
-    static_for<0, VEC / 4>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        f32x4 t = {v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
-        *reinterpret_cast<f32x4*>(dst + 4 * j) = t;
-    });
+    const f32x4 t = {v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<f32x4*>(dst) = t;
 }
 
 template <int NIN>
 struct PartArgs {
     const uint32_t* idx[NIN];
     const void* fac[NIN];
+    const uint32_t* hot_rows[NIN];
+    uint32_t fac_bytes[NIN];   // bytes of each input factor (< 4 GiB - 16)
     const float* val;
     const uint2* winfo;
     const uint32_t* row_id;
@@ -120,149 +178,266 @@ struct PartArgs {
     uint64_t nnz;
     uint32_t nrows_nz;
     uint32_t gsz;
+    uint32_t nhot;       // hot slots per input mode held in LDS
 };
 
-// One workgroup = one partition of G * gsz consecutive nonzeros.
+// Nonzeros whose row gathers are issued before the first is used, chosen so
+// that a 1024-thread workgroup (128 registers per lane) does not spill.
 template <int NIN, int R, int DT>
-__global__ __launch_bounds__(kWG) void mttkrp_part_kernel(PartArgs<NIN> a)
+constexpr int gathers_in_flight()
 {
-    constexpr int VEC = vec_of<DT>();
-    constexpr int L = R / VEC;          // lanes per group
-    constexpr int G = kWG / L;          // groups per workgroup
-    constexpr int V = 32 / L;           // streamed words per lane per 32 nonzeros
-    constexpr int U = NIN <= 2 ? 8 : (NIN <= 4 ? 4 : 2);  // nonzeros with gathers in flight
-    static_assert(R % VEC == 0 && L >= 2 && L <= 16 && 32 % U == 0, "unsupported shape");
+    if constexpr (NIN <= 2) return (DT == MTTKRP_FP32 && R == 16) ? 2 : MK_U_3MODE;
+    else if constexpr (NIN <= 3) return (DT == MTTKRP_FP32 && R == 16) ? 2 : 4;
+    else return 2;
+}
 
-    __shared__ float s_head[G * R];     // partial sum of each group's first row
-    __shared__ float s_tail[G * R];     // partial sum of each group's last row (if different)
-    __shared__ int s_trow[G];           // ordinal of the last row, -1 if the group has one row
-    __shared__ int s_hstart[G];         // 1: group's first nonzero starts a row; 0: continues one; -1: empty
+// State of one lane group while it walks its run of nonzeros.
+template <int NIN, int DT>
+struct GroupState {
+    float acc[4];
+    float head[4];
+    int first_row;
+    int cur;
+    uint32_t prev_idx[NIN];                 // coordinate of the last nonzero gathered
+    typename Slice<DT>::T prev_row[NIN];    // its factor slice
+};
+
+// One batch of 32 consecutive nonzeros starting at b (b is a multiple of 32).
+// FULL: all 32 are valid (no per-nonzero bounds tests).
+template <int NIN, int R, int DT, bool FULL>
+__device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __amdgpu_buffer_rsrc_t (&rsrc)[NIN],
+                                              lds_char* hot_lds, GroupState<NIN, DT>& st, uint64_t b, int nvalid,
+                                              bool first_batch, int gl, int wave_grp0)
+{
+    constexpr int L = R / 4;
+    constexpr int V = 32 / L;
+    constexpr int U = gathers_in_flight<NIN, R, DT>();
+    using ST = typename Slice<DT>::T;
+
+    const uint2 w = a.winfo[b >> 5];
+    uint32_t flags = w.x;
+    if (first_batch) flags &= ~1u;
+    if (!FULL && nvalid < 32) flags &= (1u << nvalid) - 1u;
+
+    uint32_t sidx[NIN][V];
+    uint32_t sval[V];
+    static_for<0, NIN>([&](auto M) {
+        constexpr int m = decltype(M)::value;
+        load_words<V>(a.idx[m] + b + gl * V, sidx[m]);
+    });
+    load_words<V>(reinterpret_cast<const uint32_t*>(a.val) + b + gl * V, sval);
+    // Output rows of the next L row ordinals, for the stores of this batch.
+    const int rbase = st.cur;
+    const uint32_t rid_pf = a.row_id[min((uint32_t)(rbase + gl), a.nrows_nz - 1u)];
+
+    static_for<0, 32 / U>([&](auto SB) {
+        constexpr int sb = decltype(SB)::value * U;
+        if (FULL || sb < nvalid) {
+            // (a) Share the sub-batch's coordinates and values inside the group.
+            uint32_t vidx[U][NIN];
+            float vv[U];
+            static_for<0, U>([&](auto UU) {
+                constexpr int u = decltype(UU)::value;
+                constexpr int k = sb + u;
+                vv[u] = __uint_as_float(group_bcast<L, k / V>(sval[k % V]));
+                static_for<0, NIN>([&](auto M) {
+                    constexpr int m = decltype(M)::value;
+                    vidx[u][m] = group_bcast<L, k / V>(sidx[m][k % V]);
+                });
+            });
+            // (b) Issue every gather of the sub-batch before any is used.  Rows
+            // outside the hot set come through buffer loads (a lane that needs
+            // nothing gets an out-of-range offset and reads zero); hot rows
+            // come from LDS into separate zeroed registers.  Exactly one of the
+            // two is nonzero for a lane that gathers, so they are OR-ed later.
+            ST gg[U][NIN];
+            ST hh[U][NIN];
+            bool same[U][NIN];
+            static_for<0, U>([&](auto UU) {
+                constexpr int u = decltype(UU)::value;
+                constexpr int k = sb + u;
+                static_for<0, NIN>([&](auto M) {
+                    constexpr int m = decltype(M)::value;
+                    const uint32_t v = vidx[u][m];
+                    const uint32_t pv = u == 0 ? st.prev_idx[m] : vidx[u == 0 ? 0 : u - 1][m];
+                    const bool need = (FULL || k < nvalid) && v != pv;
+                    same[u][m] = v == pv;
+                    const bool hot = (v & kHotBitDev) != 0;
+                    const uint32_t off = (need && !hot) ? (v * (uint32_t)R + (uint32_t)gl * 4u) * Slice<DT>::kElem
+                                                        : kSkipOffset;
+                    gg[u][m] = load_buffer<DT>(rsrc[m], off);
+                    hh[u][m] = ST{};
+                    if (need && hot)
+                        hh[u][m] = load_lds<R, DT>(hot_lds + (size_t)m * a.nhot * R * Slice<DT>::kElem,
+                                                   v & ~kHotBitDev, gl);
+                });
+            });
+            static_for<0, NIN>([&](auto M) {
+                constexpr int m = decltype(M)::value;
+                if (FULL) {
+                    st.prev_idx[m] = vidx[U - 1][m];
+                } else {
+                    static_for<0, U>([&](auto UU) {
+                        constexpr int u = decltype(UU)::value;
+                        if (sb + u < nvalid) st.prev_idx[m] = vidx[u][m];
+                    });
+                }
+            });
+            // (c) Products and running row sums.
+            static_for<0, U>([&](auto UU) {
+                constexpr int u = decltype(UU)::value;
+                constexpr int k = sb + u;
+                if (FULL || k < nvalid) {
+                    float p[4];
+                    static_for<0, NIN>([&](auto M) {
+                        constexpr int m = decltype(M)::value;
+                        const ST fresh = gg[u][m] | hh[u][m];
+                        const ST s = same[u][m] ? st.prev_row[m] : fresh;
+                        st.prev_row[m] = s;
+                        float q[4];
+                        unpack4<DT>(s, q);
+                        if constexpr (m == 0) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) p[e] = q[e] * vv[u];
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) p[e] *= q[e];
+                        }
+                    });
+                    if ((flags >> k) & 1u) {
+                        // Row `cur` ends before nonzero k.
+                        if (st.cur == st.first_row) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) st.head[e] = st.acc[e];
+                        } else {
+                            const int o = st.cur - rbase;
+                            uint32_t rid;
+                            if (o < L)
+                                rid = (uint32_t)__builtin_amdgcn_ds_bpermute((wave_grp0 + o) << 2, (int)rid_pf);
+                            else
+                                rid = a.row_id[st.cur];
+                            store4(a.out + (uint64_t)rid * R + gl * 4, st.acc);
+                        }
+                        ++st.cur;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) st.acc[e] = p[e];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) st.acc[e] += p[e];
+                    }
+                }
+            });
+        }
+    });
+}
+
+template <int NIN, int R, int DT>
+__global__ __launch_bounds__(part_wg(NIN)) void mttkrp_part_kernel(PartArgs<NIN> a)
+{
+    constexpr int kPartWG = part_wg(NIN);
+    constexpr int L = R / 4;            // lanes per group
+    constexpr int G = kPartWG / L;      // groups per workgroup
+    static_assert(R % 4 == 0 && L >= 2 && L <= 16, "unsupported rank");
+    extern __shared__ __attribute__((aligned(16))) char smem[];
 
     const int tid = threadIdx.x;
     const int g = tid / L;
     const int gl = tid % L;
-    const int wave_grp0 = (tid & 63) & ~(L - 1);   // wave lane of this group's lane 0
+    const int wave_grp0 = (tid & 63) & ~(L - 1);
+
+    // 1. Hot rows of every input factor into LDS: 16-byte chunks, eight per
+    //    thread in flight (row numbers first, then the data, then the stores).
+    const uint32_t row_bytes = R * Slice<DT>::kElem;
+    if (a.nhot) {
+        constexpr int F = 8;
+        const uint32_t cpr = row_bytes / 16;
+        const uint32_t chunks = a.nhot * cpr;
+        static_for<0, NIN>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            char* dst = smem + (size_t)m * a.nhot * row_bytes;
+            const char* fac = static_cast<const char*>(a.fac[m]);
+            for (uint32_t c0 = tid; c0 < chunks; c0 += F * kPartWG) {
+                uint32_t row[F];
+                u32x4 d[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const uint32_t c = c0 + f * kPartWG;
+                    row[f] = c < chunks ? a.hot_rows[m][c / cpr] : 0u;
+                }
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const uint32_t c = c0 + f * kPartWG;
+                    if (c < chunks) d[f] = *reinterpret_cast<const u32x4*>(fac + (uint64_t)row[f] * row_bytes + (c % cpr) * 16);
+                }
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const uint32_t c = c0 + f * kPartWG;
+                    if (c < chunks) *reinterpret_cast<u32x4*>(dst + (size_t)(c / cpr) * row_bytes + (c % cpr) * 16) = d[f];
+                }
+            }
+        });
+    }
+    __syncthreads();
+
+    // 2. Walk this group's run of nonzeros.
     const uint64_t wg_beg = (uint64_t)blockIdx.x * G * a.gsz;
     const uint64_t g_beg = wg_beg + (uint64_t)g * a.gsz;
-
-    float acc[VEC];
+    GroupState<NIN, DT> st;
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
-    int first_row = -1;
-    int cur = -1;
+    for (int e = 0; e < 4; ++e) st.acc[e] = st.head[e] = 0.0f;
+    st.first_row = -1;
+    st.cur = -1;
+#pragma unroll
+    for (int m = 0; m < NIN; ++m) st.prev_idx[m] = 0xffffffffu;
     int hstart = -1;
-
     if (g_beg < a.nnz) {
         const uint64_t g_end = min(g_beg + (uint64_t)a.gsz, a.nnz);
         const uint2 w0 = a.winfo[g_beg >> 5];
-        first_row = cur = (int)w0.y;
+        st.first_row = st.cur = (int)w0.y;
         hstart = (int)(w0.x & 1u);
-        for (uint64_t b = g_beg; b < g_end; b += 32) {
-            const uint2 w = a.winfo[b >> 5];
-            const int nvalid = (int)min((uint64_t)32, g_end - b);
-            uint32_t flags = w.x;
-            if (b == g_beg) flags &= ~1u;
-            if (nvalid < 32) flags &= (1u << nvalid) - 1u;
+        uint64_t b = g_beg;
+        lds_char* hot_lds = (lds_char*)smem;
+        __amdgpu_buffer_rsrc_t rsrc[NIN];
+#pragma unroll
+        for (int m = 0; m < NIN; ++m) rsrc[m] = make_rsrc(a.fac[m], a.fac_bytes[m]);
+        for (; b + 32 <= g_end; b += 32)
+            process_batch<NIN, R, DT, true>(a, rsrc, hot_lds, st, b, 32, b == g_beg, gl, wave_grp0);
+        if (b < g_end)
+            process_batch<NIN, R, DT, false>(a, rsrc, hot_lds, st, b, (int)(g_end - b), b == g_beg, gl, wave_grp0);
+    }
+    __syncthreads();   // every group is done with the hot rows
 
-            uint32_t sidx[NIN][V];
-            uint32_t sval[V];
-            static_for<0, NIN>([&](auto M) {
-                constexpr int m = decltype(M)::value;
-                load_words<V>(a.idx[m] + b + gl * V, sidx[m]);
-            });
-            load_words<V>(reinterpret_cast<const uint32_t*>(a.val) + b + gl * V, sval);
-            // Output rows of the next L row ordinals, for the stores of this batch.
-            const int rbase = cur;
-            const uint32_t rid_pf = a.row_id[min((uint32_t)(rbase + gl), a.nrows_nz - 1u)];
-
-            static_for<0, 32 / U>([&](auto SB) {
-                constexpr int sb = decltype(SB)::value * U;
-                if (sb < nvalid) {
-                    u32x4 gv[U][NIN];
-                    float vv[U];
-                    static_for<0, U>([&](auto UU) {
-                        constexpr int u = decltype(UU)::value;
-                        constexpr int k = sb + u;
-                        constexpr int src = k / V;
-                        constexpr int reg = k % V;
-                        vv[u] = __uint_as_float(group_bcast<L, src>(sval[reg]));
-                        static_for<0, NIN>([&](auto M) {
-                            constexpr int m = decltype(M)::value;
-                            const uint32_t row = group_bcast<L, src>(sidx[m][reg]);
-                            if (k < nvalid) gv[u][m] = load_slice<R, DT>(a.fac[m], row, gl);
-                            else gv[u][m] = u32x4{0u, 0u, 0u, 0u};
-                        });
-                    });
-                    static_for<0, U>([&](auto UU) {
-                        constexpr int u = decltype(UU)::value;
-                        constexpr int k = sb + u;
-                        if (k < nvalid) {
-                            float p[VEC];
-                            unpack<DT>(gv[u][0], p);
-#pragma unroll
-                            for (int e = 0; e < VEC; ++e) p[e] *= vv[u];
-                            static_for<1, NIN>([&](auto M) {
-                                constexpr int m = decltype(M)::value;
-                                float q[VEC];
-                                unpack<DT>(gv[u][m], q);
-#pragma unroll
-                                for (int e = 0; e < VEC; ++e) p[e] *= q[e];
-                            });
-                            if ((flags >> k) & 1u) {
-                                // Row `cur` ends before nonzero k.
-                                if (cur == first_row) {
-#pragma unroll
-                                    for (int e = 0; e < VEC; ++e) s_head[g * R + gl * VEC + e] = acc[e];
-                                } else {
-                                    const int o = cur - rbase;
-                                    uint32_t rid;
-                                    if (o < L)
-                                        rid = (uint32_t)__builtin_amdgcn_ds_bpermute((wave_grp0 + o) << 2,
-                                                                                    (int)rid_pf);
-                                    else
-                                        rid = a.row_id[cur];
-                                    store_vec<VEC>(a.out + (uint64_t)rid * R + gl * VEC, acc);
-                                }
-                                ++cur;
-#pragma unroll
-                                for (int e = 0; e < VEC; ++e) acc[e] = p[e];
-                            } else {
-#pragma unroll
-                                for (int e = 0; e < VEC; ++e) acc[e] += p[e];
-                            }
-                        }
-                    });
-                }
-            });
-        }
-        if (cur == first_row) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) s_head[g * R + gl * VEC + e] = acc[e];
-        } else {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) s_tail[g * R + gl * VEC + e] = acc[e];
-        }
+    // 3. Group partials into LDS, then combine them in group order.
+    float* s_head = reinterpret_cast<float*>(smem);
+    float* s_tail = s_head + G * R;
+    int* s_trow = reinterpret_cast<int*>(smem + (a.nhot * NIN * row_bytes > 2u * G * R * 4u
+                                                     ? a.nhot * NIN * row_bytes
+                                                     : 2u * G * R * 4u));
+    int* s_hstart = s_trow + G;
+    const bool multi = st.first_row >= 0 && st.cur != st.first_row;
+    if (st.first_row >= 0) {
+        store4(s_head + g * R + gl * 4, multi ? st.head : st.acc);
+        if (multi) store4(s_tail + g * R + gl * 4, st.acc);
     }
     if (gl == 0) {
-        s_trow[g] = (first_row >= 0 && cur != first_row) ? cur : -1;
+        s_trow[g] = multi ? st.cur : -1;
         s_hstart[g] = hstart;
     }
     __syncthreads();
 
-    // ---- combine the groups' first/last rows in group order ----
     const uint64_t next_beg = wg_beg + (uint64_t)G * a.gsz;
     const bool row_continues = next_beg < a.nnz && !(a.winfo[next_beg >> 5].x & 1u);
     const int hs = s_hstart[g];
     if (hs < 0) return;
     const int trow = s_trow[g];
 
-    // A run starts at this group's first row (if g == 0 or a row starts with the
-    // group) and/or at its last row; its owner adds the following groups' first
-    // rows while they continue it.
+    // A run starts at this group's first row (if g == 0 or a row starts with
+    // the group) and/or at its last row; its owner adds the following groups'
+    // first rows while they continue it.
     auto emit = [&](const float* src, int row, bool from_first_of_wg, bool extend) {
-        float sum[VEC];
+        float sum[4];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) sum[e] = src[g * R + gl * VEC + e];
+        for (int e = 0; e < 4; ++e) sum[e] = src[g * R + gl * 4 + e];
         bool reaches_end = extend;
         if (extend) {
             for (int j = g + 1; j < G; ++j) {
@@ -271,7 +446,7 @@ __global__ __launch_bounds__(kWG) void mttkrp_part_kernel(PartArgs<NIN> a)
                     break;
                 }
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) sum[e] += s_head[j * R + gl * VEC + e];
+                for (int e = 0; e < 4; ++e) sum[e] += s_head[j * R + gl * 4 + e];
                 if (s_trow[j] >= 0) {
                     reaches_end = false;
                     break;
@@ -280,26 +455,25 @@ __global__ __launch_bounds__(kWG) void mttkrp_part_kernel(PartArgs<NIN> a)
         }
         const bool head_split = from_first_of_wg && s_hstart[0] == 0;
         const bool tail_split = reaches_end && row_continues;
-        if (head_split || tail_split) {
-            float* dst = a.carry + ((uint64_t)blockIdx.x * 2 + (from_first_of_wg ? 0 : 1)) * R + gl * VEC;
-            store_vec<VEC>(dst, sum);
-        } else {
-            const uint32_t rid = a.row_id[row];
-            store_vec<VEC>(a.out + (uint64_t)rid * R + gl * VEC, sum);
-        }
+        if (head_split || tail_split)
+            store4(a.carry + ((uint64_t)blockIdx.x * 2 + (from_first_of_wg ? 0 : 1)) * R + gl * 4, sum);
+        else
+            store4(a.out + (uint64_t)a.row_id[row] * R + gl * 4, sum);
     };
-    if (g == 0 || hs == 1) emit(s_head, first_row, g == 0, trow < 0);
+    if (g == 0 || hs == 1) emit(s_head, st.first_row, g == 0, trow < 0);
     if (trow >= 0) emit(s_tail, trow, false, true);
 }
 
 template <int NIN, int R, int DT>
-hipError_t launch_part(const DevMode& m, const void* const* fac, float* out, float* carry, const Geometry& g,
-                       hipStream_t s)
+hipError_t launch_part(const DevMode& m, const void* const* fac, const uint32_t* const* hot_rows, uint32_t nhot,
+                       float* out, float* carry, const Geometry& g, hipStream_t s)
 {
     PartArgs<NIN> a;
     for (int j = 0; j < NIN; ++j) {
         a.idx[j] = m.idx[j];
         a.fac[j] = fac[j];
+        a.hot_rows[j] = hot_rows[j];
+        a.fac_bytes[j] = (uint32_t)((uint64_t)m.in_dims[j] * R * Slice<DT>::kElem);
     }
     a.val = m.val;
     a.winfo = m.winfo;
@@ -309,18 +483,27 @@ hipError_t launch_part(const DevMode& m, const void* const* fac, float* out, flo
     a.nnz = m.nnz;
     a.nrows_nz = (uint32_t)m.nrows_nz;
     a.gsz = g.gsz;
-    hipLaunchKernelGGL((mttkrp_part_kernel<NIN, R, DT>), dim3(g.nparts), dim3(kWG), 0, s, a);
+    a.nhot = nhot;
+    const uint32_t lds = part_lds_bytes(NIN, R, DT, nhot);
+    static uint32_t lds_set = 0;   // largest dynamic LDS size already allowed for this instantiation
+    if (lds > lds_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mttkrp_part_kernel<NIN, R, DT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set = lds;
+    }
+    hipLaunchKernelGGL((mttkrp_part_kernel<NIN, R, DT>), dim3(g.nparts), dim3(part_wg(NIN)), lds, s, a);
     return hipGetLastError();
 }
 
 template <int NIN, int DT>
-hipError_t dispatch_r(const DevMode& m, int R, const void* const* fac, float* out, float* carry, const Geometry& g,
-                      hipStream_t s)
+hipError_t dispatch_r(const DevMode& m, int R, const void* const* fac, const uint32_t* const* hot_rows, uint32_t nhot,
+                      float* out, float* carry, const Geometry& g, hipStream_t s)
 {
     switch (R) {
-        case 16: return launch_part<NIN, 16, DT>(m, fac, out, carry, g, s);
-        case 32: return launch_part<NIN, 32, DT>(m, fac, out, carry, g, s);
-        case 64: return launch_part<NIN, 64, DT>(m, fac, out, carry, g, s);
+        case 16: return launch_part<NIN, 16, DT>(m, fac, hot_rows, nhot, out, carry, g, s);
+        case 32: return launch_part<NIN, 32, DT>(m, fac, hot_rows, nhot, out, carry, g, s);
+        case 64: return launch_part<NIN, 64, DT>(m, fac, hot_rows, nhot, out, carry, g, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -328,11 +511,13 @@ hipError_t dispatch_r(const DevMode& m, int R, const void* const* fac, float* ou
 }  // namespace part
 
 template <int NIN>
-hipError_t launch_part_nin(const DevMode& m, int R, int dtype, const void* const* fac, float* out, float* carry,
+hipError_t launch_part_nin(const DevMode& m, int R, int dtype, const void* const* fac,
+                           const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry,
                            const Geometry& g, hipStream_t s)
 {
-    return dtype == MTTKRP_FP32 ? part::dispatch_r<NIN, MTTKRP_FP32>(m, R, fac, out, carry, g, s)
-                                : part::dispatch_r<NIN, MTTKRP_BF16>(m, R, fac, out, carry, g, s);
+    return dtype == MTTKRP_FP32
+               ? part::dispatch_r<NIN, MTTKRP_FP32>(m, R, fac, hot_rows, nhot, out, carry, g, s)
+               : part::dispatch_r<NIN, MTTKRP_BF16>(m, R, fac, hot_rows, nhot, out, carry, g, s);
 }
 
 }  // namespace mk

@@ -2,6 +2,6 @@
 #include "part_kernel.h"
 
 namespace mk {
-template hipError_t launch_part_nin<2>(const DevMode&, int, int, const void* const*, float*, float*,
-                                         const Geometry&, hipStream_t);
+template hipError_t launch_part_nin<2>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                         uint32_t, float*, float*, const Geometry&, hipStream_t);
 }  // namespace mk

@@ -38,6 +38,15 @@ def row_of_each_nonzero(v):
     return v["row_id"][ordinal].astype(np.int64), bits, ordinal
 
 
+def decode(v, j):
+    """Coordinates of input mode j with hot slots mapped back to rows."""
+    raw = v["idx"][j].astype(np.int64)
+    hot = (raw & 0x80000000) != 0
+    out = raw.copy()
+    out[hot] = v["hot_rows"][j][raw[hot] & 0x7FFFFFFF]
+    return out
+
+
 def check_view(idx, val, dims, v, n):
     N = len(dims)
     nnz = idx.shape[0]
@@ -47,8 +56,14 @@ def check_view(idx, val, dims, v, n):
     # a permutation of the input, carrying every coordinate and value
     assert np.array_equal(np.sort(src), np.arange(nnz))
     for j, m in enumerate(v["in_modes"]):
-        assert np.array_equal(v["idx"][j][:nnz], idx[src, m])
+        assert np.array_equal(decode(v, j)[:nnz], idx[src, m])
         assert not v["idx"][j][nnz:].any()
+        # hot rows: the most frequent rows of mode m (degree >= 2), by degree then row
+        deg = np.bincount(idx[:, m].astype(np.int64), minlength=dims[m])
+        hot = v["hot_rows"][j]
+        used = hot[: min(v["nhot"], int(np.sum(deg >= 2)))]
+        order = np.lexsort((np.arange(dims[m]), -deg))
+        assert np.array_equal(used, order[: used.shape[0]])
     assert np.array_equal(v["val"][:nnz], val[src])
     assert not v["val"][nnz:].any()
     rows, bits, ordinal = row_of_each_nonzero(v)

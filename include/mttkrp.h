@@ -68,7 +68,7 @@ typedef struct {
     uint64_t hbm_budget_bytes; /* refuse to build (MTTKRP_ENOMEM) when the footprint exceeds this; 0 = no budget */
     int host_only;             /* 1: build the host arrays only (for inspection); no device memory, runs refused */
     int hot_rows;              /* rows of each input factor kept in LDS during a run: the most frequently
-                                  gathered ones.  -1 = as many as fit (default), 0 = none, k > 0 = at most k */
+                                  gathered ones.  -1 = as many as fit, 0 = none (default), k > 0 = at most k */
 } mttkrp_opts;
 
 /* Fill `o` with the defaults listed above. */
@@ -140,6 +140,46 @@ typedef struct {
 } mttkrp_info;
 
 mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
+
+/* ---- Batching: many small tensors per launch ----
+ * A batch groups handles of tensors with the same N.  mttkrp_batch_run runs
+ * the MTTKRP along one mode for every tensor of the batch with one
+ * partition-kernel launch and one fix-up launch: a static list of (tensor,
+ * partition) work items, sized so that every workgroup gets about the same
+ * number of nonzeros, walked by a grid of resident workgroups.  Results are
+ * bitwise identical to mttkrp_run on each handle with the same R whenever the
+ * per-tensor partitioning is the same, and always equal within rounding. */
+typedef struct mttkrp_batch* mttkrp_batch_handle;
+
+/* layouts: host array of `count` device handles (same N, each with max_R >= R).
+ * The handles must outlive the batch.  opts may be NULL (parts_per_cu sizes
+ * the work list).  Allocates the batch's descriptor tables and carry rows. */
+mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
+                                  mttkrp_batch_handle* out);
+
+/* factors: host array of count * N device pointers, tensor t's A_m at
+ *          [t * N + m] (I_m x R fp32; the mode's own entry is not read);
+ * outs:    host array of count device pointers, tensor t's I_mode x R fp32
+ *          output (overwritten).
+ * When the pointers differ from the previous call's, the descriptor tables
+ * are re-uploaded, which synchronises the stream first. */
+mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* const* factors, float* const* outs,
+                               hipStream_t stream);
+
+/* Release a batch (not its layouts).  NULL is ignored. */
+void mttkrp_batch_free(mttkrp_batch_handle b);
+
+/* As cpd_als_iter, but only enqueued: nothing is read back and the stream is
+ * not synchronised, so sweeps can be captured into a HIP graph and replayed.
+ * A V that is not positive definite sets a sticky device flag (and makes the
+ * factors NaN); cpd_als_status reports it. */
+mttkrp_status cpd_als_iter_async(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
+                                 hipStream_t stream);
+
+/* MTTKRP_ENOTSPD if any sweep since the last check met a V that is not
+ * positive definite (then clears the flag), else MTTKRP_OK.  Synchronises the
+ * stream. */
+mttkrp_status cpd_als_status(mttkrp_handle h, hipStream_t stream);
 
 /* Release a handle and all of its device memory (synchronises the device).
  * NULL is ignored. */

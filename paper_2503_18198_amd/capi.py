@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "MTTKRP_OK", 1: "MTTKRP_EINVAL", 2: "MTTKRP_ERANGE", 3: "MTTK
 # Every symbol the header declares.
 EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "mttkrp_layout_bytes", "mttkrp_run",
             "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
-            "mttkrp_layout_view", "mttkrp_layout_info"]
+            "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create", "mttkrp_batch_run",
+            "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status"]
 
 
 class MttkrpError(RuntimeError):
@@ -81,8 +82,16 @@ def _load():
     lib.mttkrp_last_error.restype = ctypes.c_char_p
     lib.mttkrp_layout_view.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mttkrp_mode_view)]
     lib.mttkrp_layout_info.argtypes = [vp, ctypes.POINTER(mttkrp_info)]
+    lib.mttkrp_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(mttkrp_opts),
+                                        ctypes.POINTER(vp)]
+    lib.mttkrp_batch_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.cpd_als_iter_async.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.c_int, vp, vp]
+    lib.cpd_als_status.argtypes = [vp, vp]
+    lib.mttkrp_batch_free.argtypes = [vp]
+    lib.mttkrp_batch_free.restype = None
     for name in ("mttkrp_footprint", "mttkrp_layout_build", "mttkrp_run", "mttkrp_run_bf16", "cpd_als_init",
-                 "cpd_als_iter", "mttkrp_layout_view", "mttkrp_layout_info"):
+                 "cpd_als_iter", "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create",
+                 "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -257,6 +266,23 @@ def cpd_als_iter(h: Layout, factors, lam, R: int, fit_out=None, stream=None):
                              ctypes.c_void_p(_stream(stream))))
 
 
+def cpd_als_iter_async(h: Layout, factors, lam, R: int, fit_out=None, stream=None):
+    """One CP-ALS sweep, enqueued only (capturable into a HIP graph)."""
+    import torch
+    N = len(h.dims)
+    for m, f in enumerate(factors):
+        _check_factor(f, h.dims[m], R, "fp32", f"factor {m}")
+    if lam.dtype != torch.float64 or not lam.is_cuda or lam.numel() < R:
+        raise MttkrpError(MTTKRP_EINVAL, "lambda must be a float64 device tensor with R entries")
+    _check(_lib.cpd_als_iter_async(ctypes.c_void_p(h.ptr), _ptr_array(factors, N), ctypes.c_void_p(lam.data_ptr()),
+                                   int(R), ctypes.c_void_p(fit_out.data_ptr() if fit_out is not None else 0),
+                                   ctypes.c_void_p(_stream(stream))))
+
+
+def cpd_als_status(h: Layout, stream=None):
+    _check(_lib.cpd_als_status(ctypes.c_void_p(h.ptr), ctypes.c_void_p(_stream(stream))))
+
+
 def mttkrp_layout_view(h: Layout, mode: int) -> dict:
     """Copies of the host arrays of one mode copy (host-only layouts)."""
     v = mttkrp_mode_view()
@@ -274,3 +300,63 @@ def mttkrp_layout_view(h: Layout, mode: int) -> dict:
                 row_id=arr(v.row_id, v.nrows_nz, np.uint32), empty_rows=arr(v.empty_rows, v.nempty, np.uint32),
                 src_pos=arr(v.src_pos, v.nnz, np.uint64), nhot=int(v.nhot),
                 hot_rows=[arr(v.hot_rows[j], v.nhot, np.uint32) for j in range(v.n_in)])
+
+
+class Batch:
+    """Owns an ``mttkrp_batch_handle``; keeps its layouts alive."""
+
+    def __init__(self, ptr: int, layouts, R: int):
+        self._ptr = ptr
+        self.layouts = list(layouts)
+        self.R = R
+
+    @property
+    def ptr(self) -> int:
+        if not self._ptr:
+            raise MttkrpError(MTTKRP_EINVAL, "batch already freed")
+        return self._ptr
+
+    def free(self):
+        if self._ptr:
+            _lib.mttkrp_batch_free(ctypes.c_void_p(self._ptr))
+            self._ptr = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def mttkrp_batch_create(layouts, R: int, opts=None) -> Batch:
+    arr = (ctypes.c_void_p * len(layouts))(*[h.ptr for h in layouts])
+    o = _opts(opts)
+    b = ctypes.c_void_p()
+    _check(_lib.mttkrp_batch_create(arr, len(layouts), int(R), ctypes.byref(o) if o is not None else None,
+                                    ctypes.byref(b)))
+    return Batch(b.value, layouts, R)
+
+
+def mttkrp_batch_run(b: Batch, mode: int, factors, outs, stream=None):
+    """factors: list (per tensor) of lists of N fp32 device tensors; outs: list of outputs."""
+    import torch
+    N = len(b.layouts[0].dims)
+    if len(factors) != len(b.layouts) or len(outs) != len(b.layouts):
+        raise MttkrpError(MTTKRP_EINVAL, "need factors and outputs for every tensor of the batch")
+    if not 0 <= int(mode) < N:
+        raise MttkrpError(MTTKRP_EINVAL, "mode out of range")
+    fp = (ctypes.c_void_p * (len(b.layouts) * N))()
+    op = (ctypes.c_void_p * len(b.layouts))()
+    for t, (h, fs, o) in enumerate(zip(b.layouts, factors, outs)):
+        for m in range(N):
+            if m != mode:
+                _check_factor(fs[m], h.dims[m], b.R, "fp32", f"factor {m} of tensor {t}")
+                fp[t * N + m] = int(fs[m].data_ptr())
+        if o.dtype != torch.float32 or not o.is_cuda or not o.is_contiguous() or tuple(o.shape) != (h.dims[mode], b.R):
+            raise MttkrpError(MTTKRP_EINVAL, f"output of tensor {t} must be ({h.dims[mode]}, {b.R}) float32")
+        op[t] = int(o.data_ptr())
+    _check(_lib.mttkrp_batch_run(ctypes.c_void_p(b.ptr), int(mode), fp, op, ctypes.c_void_p(_stream(stream))))
+
+
+def mttkrp_batch_free(b: Batch):
+    b.free()

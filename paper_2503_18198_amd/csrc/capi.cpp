@@ -136,7 +136,7 @@ void mttkrp_opts_default(mttkrp_opts* o)
     o->max_R = 64;
     o->hbm_budget_bytes = 0;
     o->host_only = 0;
-    o->hot_rows = -1;
+    o->hot_rows = 0;
 }
 
 const char* mttkrp_last_error(void) { return g_err.c_str(); }
@@ -468,15 +468,17 @@ mttkrp_status cpd_als_init(mttkrp_handle h, const float* const* factors, int R, 
         if (e == hipSuccess && h->opts.factor_dtype == MTTKRP_BF16)
             e = mk::cast_bf16(factors[m], (uint64_t)h->dims[m] * R, h->als.bf16[m], stream);
     }
+    if (e == hipSuccess) e = mk::als_hadamard(h->als.grams, h->N, -1, R, h->als.V, h->als.scal + 1, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "cpd_als_init");
     h->als_R = R;
     return MTTKRP_OK;
 }
 
-mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
-                           hipStream_t stream)
+// One sweep, enqueued only (no host synchronisation; capturable).  The
+// not-positive-definite flag is cleared at the start when reset_flag is set.
+static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
+                               hipStream_t stream, bool reset_flag)
 {
-    g_err.clear();
     mttkrp_status s = check_factors(h, reinterpret_cast<const void* const*>(factors), R);
     if (s) return s;
     if (h->als_R != R) return fail(MTTKRP_EINVAL, "call cpd_als_init with this R first");
@@ -490,7 +492,7 @@ mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambd
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         const uint32_t I = h->dims[n];
         const uint64_t RR = (uint64_t)R * R;
-        e = mk::als_hadamard(w.grams, N, n, R, w.V, flag, n == 0, stream);
+        e = mk::als_hadamard(w.grams, N, n, R, w.V, flag, reset_flag && n == 0, stream);
         if (e == hipSuccess) e = mk::als_cholesky_inverse(w.V, R, w.W, w.Linv, flag, stream);
         if (e == hipSuccess) {
             const void* fac[MTTKRP_MAX_MODES];
@@ -506,12 +508,233 @@ mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambd
     if (e == hipSuccess)
         e = mk::als_fit(w.M, factors[N - 1], h->dims[N - 1], w.lam, w.grams, N, R, h->normX2,
                         fit_out ? fit_out : w.scal, lambda, w, stream);
-    if (e != hipSuccess) return hip_fail(e, "cpd_als_iter");
+    if (e != hipSuccess) return hip_fail(e, "CP-ALS sweep");
+    return MTTKRP_OK;
+}
+
+static mttkrp_status read_flag(mttkrp_handle h, hipStream_t stream)
+{
     double f = 0.0;
-    e = hipMemcpyAsync(&f, flag, sizeof(double), hipMemcpyDeviceToHost, stream);
+    hipError_t e = hipMemcpyAsync(&f, h->als.scal + 1, sizeof(double), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "cpd_als_iter");
+    if (e != hipSuccess) return hip_fail(e, "reading the CP-ALS status");
     if (f != 0.0) return fail(MTTKRP_ENOTSPD, "a normal-equation matrix V is not positive definite");
+    return MTTKRP_OK;
+}
+
+mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
+                           hipStream_t stream)
+{
+    g_err.clear();
+    mttkrp_status s = als_sweep(h, factors, lambda, R, fit_out, stream, true);
+    if (s) return s;
+    return read_flag(h, stream);
+}
+
+mttkrp_status cpd_als_iter_async(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
+                                 hipStream_t stream)
+{
+    g_err.clear();
+    return als_sweep(h, factors, lambda, R, fit_out, stream, false);
+}
+
+mttkrp_status cpd_als_status(mttkrp_handle h, hipStream_t stream)
+{
+    g_err.clear();
+    if (!h || h->host_only) return fail(MTTKRP_EINVAL, "NULL or host-only handle");
+    mttkrp_status s = read_flag(h, stream);
+    if (s == MTTKRP_ENOTSPD) {
+        // clear the sticky flag for the next sweeps
+        mk::als_hadamard(h->als.grams, h->N, -1, h->als_R ? h->als_R : 16, h->als.V, h->als.scal + 1, 1, stream);
+        (void)hipStreamSynchronize(stream);
+    }
+    return s;
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+
+struct mttkrp_batch {
+    int count = 0, N = 0, R = 0;
+    std::vector<mttkrp_handle> hs;
+    void* dmem = nullptr;
+    float* carry = nullptr;
+    std::vector<uint64_t> carry_off;                      // per tensor, in floats
+    std::vector<std::vector<mk::Geometry>> geo;           // [mode][tensor]
+    char* part_desc[MTTKRP_MAX_MODES] = {};               // device descriptor tables
+    char* fix_desc[MTTKRP_MAX_MODES] = {};
+    uint2* part_work[MTTKRP_MAX_MODES] = {};
+    uint2* fix_work[MTTKRP_MAX_MODES] = {};
+    uint32_t npart_work[MTTKRP_MAX_MODES] = {};
+    uint32_t nfix_work[MTTKRP_MAX_MODES] = {};
+    uint32_t grid_part = 0, grid_fix = 0;
+    std::vector<const void*> last_ptrs[MTTKRP_MAX_MODES]; // pointers of the uploaded descriptors
+};
+
+extern "C" {
+
+void mttkrp_batch_free(mttkrp_batch_handle b)
+{
+    if (!b) return;
+    if (b->dmem) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b->dmem);
+    }
+    delete b;
+}
+
+mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
+                                  mttkrp_batch_handle* out)
+{
+    g_err.clear();
+    if (!out) return fail(MTTKRP_EINVAL, "NULL out");
+    *out = nullptr;
+    if (!layouts || count <= 0) return fail(MTTKRP_EINVAL, "need at least one layout");
+    if (!r_supported(R)) return fail(MTTKRP_EUNSUPPORTED, "R must be 16, 32 or 64");
+    mttkrp_opts o;
+    mttkrp_status st = check_opts(opts, &o);
+    if (st) return st;
+    const int N = layouts[0] ? layouts[0]->N : 0;
+    uint64_t total_nnz = 0;
+    for (int t = 0; t < count; ++t) {
+        const mttkrp_handle h = layouts[t];
+        if (!h || h->host_only) return fail(MTTKRP_EINVAL, "layout " + std::to_string(t) + " is NULL or host-only");
+        if (h->N != N) return fail(MTTKRP_EINVAL, "all layouts of a batch need the same N");
+        if (R > h->opts.max_R) return fail(MTTKRP_EINVAL, "R exceeds the max_R of layout " + std::to_string(t));
+        for (int m = 0; m < N; ++m)
+            if ((uint64_t)h->dims[m] * (uint64_t)R * 4ull >= 0xFFFFFFF0ull)
+                return fail(MTTKRP_EUNSUPPORTED, "a factor of layout " + std::to_string(t) + " is 4 GiB or larger");
+        total_nnz += h->nnz;
+    }
+    auto* b = new mttkrp_batch();
+    b->count = count;
+    b->N = N;
+    b->R = R;
+    b->hs.assign(layouts, layouts + count);
+    const int cus = layouts[0]->cu_count;
+    // Every workgroup of the batch gets about the same nonzero count.
+    const uint64_t target = (uint64_t)cus * (uint64_t)o.parts_per_cu;
+    b->geo.assign(N, std::vector<mk::Geometry>(count));
+    std::vector<uint32_t> max_parts(count, 0);
+    for (int n = 0; n < N; ++n)
+        for (int t = 0; t < count; ++t) {
+            const uint64_t nnz = b->hs[t]->nnz;
+            const int tp = (int)std::max<uint64_t>(1, total_nnz ? (nnz * target + total_nnz / 2) / total_nnz : 1);
+            b->geo[n][t] = mk::plan_geometry(nnz, N - 1, R, tp, kMaxParts);
+            max_parts[t] = std::max(max_parts[t], b->geo[n][t].nparts);
+        }
+    // Work lists and sizes.
+    std::vector<std::vector<uint2>> pw(N), fw(N);
+    const size_t pdb = mk::part_desc_bytes(N - 1), fdb = mk::fix_desc_bytes();
+    std::vector<char> scratch_desc(std::max(pdb, fdb));
+    for (int n = 0; n < N; ++n)
+        for (int t = 0; t < count; ++t) {
+            const mk::Geometry& g = b->geo[n][t];
+            const uint32_t np = b->hs[t]->nnz ? g.nparts : 0;
+            for (uint32_t p = 0; p < np; ++p) pw[n].push_back(make_uint2((uint32_t)t, p));
+            const uint32_t nb = mk::fill_fix_desc(scratch_desc.data(), b->hs[t]->dev[n], g, nullptr, nullptr, R);
+            for (uint32_t k = 0; k < nb; ++k) fw[n].push_back(make_uint2((uint32_t)t, k));
+        }
+    uint64_t carry_floats = 0;
+    b->carry_off.resize(count);
+    for (int t = 0; t < count; ++t) {
+        b->carry_off[t] = carry_floats;
+        carry_floats += (uint64_t)std::max<uint32_t>(max_parts[t], 1) * 2ull * (uint64_t)R;
+    }
+    uint64_t need = align_up(carry_floats * 4);
+    for (int n = 0; n < N; ++n)
+        need += align_up((uint64_t)count * pdb) + align_up((uint64_t)count * fdb) + align_up(pw[n].size() * 8 + 8) +
+                align_up(fw[n].size() * 8 + 8);
+    hipError_t e = hipMalloc(&b->dmem, need);
+    if (e != hipSuccess) {
+        b->dmem = nullptr;
+        delete b;
+        (void)hipGetLastError();
+        return fail(MTTKRP_ENOMEM, "hipMalloc of " + std::to_string(need) + " B for the batch failed");
+    }
+    char* base = static_cast<char*>(b->dmem);
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) -> char* {
+        char* p = base + off;
+        off += align_up(bytes);
+        return p;
+    };
+    b->carry = reinterpret_cast<float*>(take(carry_floats * 4));
+    for (int n = 0; n < N && e == hipSuccess; ++n) {
+        b->part_desc[n] = take((uint64_t)count * pdb);
+        b->fix_desc[n] = take((uint64_t)count * fdb);
+        b->part_work[n] = reinterpret_cast<uint2*>(take(pw[n].size() * 8 + 8));
+        b->fix_work[n] = reinterpret_cast<uint2*>(take(fw[n].size() * 8 + 8));
+        b->npart_work[n] = (uint32_t)pw[n].size();
+        b->nfix_work[n] = (uint32_t)fw[n].size();
+        if (!pw[n].empty())
+            e = hipMemcpy(b->part_work[n], pw[n].data(), pw[n].size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !fw[n].empty())
+            e = hipMemcpy(b->fix_work[n], fw[n].data(), fw[n].size() * 8, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        mttkrp_status s2 = hip_fail(e, "mttkrp_batch_create");
+        mttkrp_batch_free(b);
+        return s2;
+    }
+    b->grid_part = (uint32_t)cus * (uint32_t)std::max(1, 1024 / mk::partition_wg_threads(N - 1));
+    b->grid_fix = (uint32_t)cus * 8u;
+    *out = b;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* const* factors, float* const* outs,
+                               hipStream_t stream)
+{
+    g_err.clear();
+    if (!b) return fail(MTTKRP_EINVAL, "NULL batch");
+    if (mode < 0 || mode >= b->N) return fail(MTTKRP_EINVAL, "mode out of range");
+    if (!factors || !outs) return fail(MTTKRP_EINVAL, "NULL factors or outs");
+    const int N = b->N, R = b->R;
+    // Pointers of this call; re-upload the descriptors only when they change.
+    std::vector<const void*> ptrs;
+    ptrs.reserve((size_t)b->count * (N + 1));
+    for (int t = 0; t < b->count; ++t) {
+        for (int m = 0; m < N; ++m) {
+            const float* f = factors[(size_t)t * N + m];
+            if (m != mode && (!f || reinterpret_cast<uintptr_t>(f) % 16))
+                return fail(MTTKRP_EINVAL, "factor " + std::to_string(m) + " of tensor " + std::to_string(t) +
+                                               " is NULL or not 16-byte aligned");
+            ptrs.push_back(m == mode ? nullptr : f);
+        }
+        if (!outs[t] || reinterpret_cast<uintptr_t>(outs[t]) % 16)
+            return fail(MTTKRP_EINVAL, "output of tensor " + std::to_string(t) + " is NULL or not 16-byte aligned");
+        ptrs.push_back(outs[t]);
+    }
+    hipError_t e = hipSuccess;
+    if (ptrs != b->last_ptrs[mode]) {
+        const size_t pdb = mk::part_desc_bytes(N - 1), fdb = mk::fix_desc_bytes();
+        std::vector<char> pd((size_t)b->count * pdb), fd((size_t)b->count * fdb);
+        for (int t = 0; t < b->count; ++t) {
+            const mk::DevMode& d = b->hs[t]->dev[mode];
+            const mk::Geometry& g = b->geo[mode][t];
+            const void* fac[mk::kMaxIn];
+            for (int j = 0; j < d.n_in; ++j) fac[j] = factors[(size_t)t * N + d.in_modes[j]];
+            float* carry = b->carry + b->carry_off[t];
+            mk::fill_part_desc(pd.data() + (size_t)t * pdb, d, R, MTTKRP_FP32, fac, outs[t], carry, g.gsz);
+            mk::fill_fix_desc(fd.data() + (size_t)t * fdb, d, g, carry, outs[t], R);
+        }
+        e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) e = hipMemcpy(b->part_desc[mode], pd.data(), pd.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->fix_desc[mode], fd.data(), fd.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "uploading batch descriptors");
+        b->last_ptrs[mode] = std::move(ptrs);
+    }
+    const uint32_t gp = std::min(b->grid_part, std::max<uint32_t>(b->npart_work[mode], 1));
+    e = mk::launch_batch_part(N - 1, R, MTTKRP_FP32, b->part_desc[mode], b->part_work[mode], b->npart_work[mode], gp,
+                              stream);
+    if (e == hipSuccess) {
+        const uint32_t gf = std::min(b->grid_fix, std::max<uint32_t>(b->nfix_work[mode], 1));
+        e = mk::launch_batch_fixup(b->fix_desc[mode], b->fix_work[mode], b->nfix_work[mode], gf, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batched MTTKRP launch");
     return MTTKRP_OK;
 }
 

@@ -50,6 +50,17 @@ hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* 
                          const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry,
                          const Geometry& g, hipStream_t s);
 
+// Batched launches: device descriptor arrays plus (tensor, item) work lists.
+size_t part_desc_bytes(int n_in);
+void fill_part_desc(void* dst, const DevMode& m, int R, int dtype, const void* const* fac, float* out, float* carry,
+                    uint32_t gsz);
+size_t fix_desc_bytes();
+// Returns the number of fix-up blocks of this copy.
+uint32_t fill_fix_desc(void* dst, const DevMode& m, const Geometry& g, float* carry, float* out, int R);
+hipError_t launch_batch_part(int n_in, int R, int dtype, const void* descs, const uint2* work, uint32_t nwork,
+                             uint32_t grid, hipStream_t s);
+hipError_t launch_batch_fixup(const void* descs, const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s);
+
 // CP-ALS helpers (als_kernels.hip).  All FP64 unless noted.
 struct AlsWork {
     double* grams = nullptr;     // N x R x R

@@ -31,6 +31,24 @@
 namespace mk {
 
 // Instantiated in part_n3.hip .. part_n8.hip.
+extern template size_t part_desc_bytes_nin<2>();
+extern template void fill_part_desc_nin<2>(void*, const DevMode&, int, int, const void* const*, float*, float*, uint32_t);
+extern template hipError_t launch_batch_part_nin<2>(int, int, const void*, const uint2*, uint32_t, uint32_t, hipStream_t);
+extern template size_t part_desc_bytes_nin<3>();
+extern template void fill_part_desc_nin<3>(void*, const DevMode&, int, int, const void* const*, float*, float*, uint32_t);
+extern template hipError_t launch_batch_part_nin<3>(int, int, const void*, const uint2*, uint32_t, uint32_t, hipStream_t);
+extern template size_t part_desc_bytes_nin<4>();
+extern template void fill_part_desc_nin<4>(void*, const DevMode&, int, int, const void* const*, float*, float*, uint32_t);
+extern template hipError_t launch_batch_part_nin<4>(int, int, const void*, const uint2*, uint32_t, uint32_t, hipStream_t);
+extern template size_t part_desc_bytes_nin<5>();
+extern template void fill_part_desc_nin<5>(void*, const DevMode&, int, int, const void* const*, float*, float*, uint32_t);
+extern template hipError_t launch_batch_part_nin<5>(int, int, const void*, const uint2*, uint32_t, uint32_t, hipStream_t);
+extern template size_t part_desc_bytes_nin<6>();
+extern template void fill_part_desc_nin<6>(void*, const DevMode&, int, int, const void* const*, float*, float*, uint32_t);
+extern template hipError_t launch_batch_part_nin<6>(int, int, const void*, const uint2*, uint32_t, uint32_t, hipStream_t);
+extern template size_t part_desc_bytes_nin<7>();
+extern template void fill_part_desc_nin<7>(void*, const DevMode&, int, int, const void* const*, float*, float*, uint32_t);
+extern template hipError_t launch_batch_part_nin<7>(int, int, const void*, const uint2*, uint32_t, uint32_t, hipStream_t);
 extern template hipError_t launch_part_nin<2>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
                                                 uint32_t, float*, float*, const Geometry&, hipStream_t);
 extern template hipError_t launch_part_nin<3>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
@@ -61,16 +79,18 @@ struct FixArgs {
 
 constexpr int kEmptyPerBlock = 64;
 
-// Rows cut by partition boundaries: add the partials of every partition that
-// holds part of the row, in partition order, in FP64.  Then zero the rows
-// without nonzeros.
-__global__ __launch_bounds__(kWG) void mttkrp_fixup_kernel(FixArgs a)
+// Block `blk` of the fix-up of one mode copy.  Blocks below nbound handle
+// partition boundary q = blk + 1: if a row is cut there and was not already
+// cut at boundary q - 1, the partials of every partition holding part of it
+// are added in partition order in FP64 and the row is stored.  The other
+// blocks zero rows without nonzeros, kEmptyPerBlock rows each.
+__device__ __forceinline__ void fixup_body(const FixArgs& a, uint32_t blk)
 {
     __shared__ double s_part[kWG];
     const int tid = threadIdx.x;
     const int R = a.R;
-    if (blockIdx.x < a.nbound) {
-        const uint32_t q = blockIdx.x + 1;           // partition q begins at q * wgc
+    if (blk < a.nbound) {
+        const uint32_t q = blk + 1;                   // partition q begins at q * wgc
         const uint2 wq = a.winfo[(q * a.wgc) >> 5];
         if (wq.x & 1u) return;                        // a row starts at the boundary: nothing is cut
         const uint32_t r = wq.y;                      // ordinal of the cut row
@@ -107,13 +127,27 @@ __global__ __launch_bounds__(kWG) void mttkrp_fixup_kernel(FixArgs a)
             a.out[(uint64_t)a.row_id[r] * R + col] = (float)tot;
         }
     } else {
-        const uint64_t e0 = (uint64_t)(blockIdx.x - a.nbound) * kEmptyPerBlock;
+        const uint64_t e0 = (uint64_t)(blk - a.nbound) * kEmptyPerBlock;
         const uint64_t e1 = min(e0 + kEmptyPerBlock, a.nempty);
         const uint64_t n = (e1 - e0) * (uint64_t)R;
         for (uint64_t t = tid; t < n; t += kWG) {
             const uint64_t e = e0 + t / R;
             a.out[(uint64_t)a.empty_rows[e] * R + (t % R)] = 0.0f;
         }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void mttkrp_fixup_kernel(FixArgs a) { fixup_body(a, blockIdx.x); }
+
+// The fix-ups of many tensors' copies of one mode in one launch.
+__global__ __launch_bounds__(kWG) void mttkrp_batch_fixup_kernel(const FixArgs* __restrict__ descs,
+                                                                 const uint2* __restrict__ work, uint32_t nwork)
+{
+    for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const uint2 wk = work[w];
+        const FixArgs a = descs[wk.x];
+        fixup_body(a, wk.y);
+        __syncthreads();
     }
 }
 
@@ -181,6 +215,74 @@ hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* 
         e = hipGetLastError();
     }
     return e;
+}
+
+size_t fix_desc_bytes() { return sizeof(FixArgs); }
+
+uint32_t fill_fix_desc(void* dst, const DevMode& m, const Geometry& g, float* carry, float* out, int R)
+{
+    FixArgs& f = *static_cast<FixArgs*>(dst);
+    f.winfo = m.winfo;
+    f.row_id = m.row_id;
+    f.empty_rows = m.empty_rows;
+    f.carry = carry;
+    f.out = out;
+    f.wgc = g.wgc;
+    f.nparts = m.nnz > 0 ? g.nparts : 0;
+    f.nbound = f.nparts > 1 ? f.nparts - 1 : 0;
+    f.nempty = m.nempty;
+    f.R = R;
+    return f.nbound + (uint32_t)((m.nempty + kEmptyPerBlock - 1) / kEmptyPerBlock);
+}
+
+hipError_t launch_batch_fixup(const void* descs, const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s)
+{
+    if (nwork == 0) return hipSuccess;
+    hipLaunchKernelGGL(mttkrp_batch_fixup_kernel, dim3(grid), dim3(kWG), 0, s, static_cast<const FixArgs*>(descs), work,
+                       nwork);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_part(int n_in, int R, int dtype, const void* descs, const uint2* work, uint32_t nwork,
+                             uint32_t grid, hipStream_t s)
+{
+    if (nwork == 0) return hipSuccess;
+    switch (n_in) {
+        case 2: return launch_batch_part_nin<2>(R, dtype, descs, work, nwork, grid, s);
+        case 3: return launch_batch_part_nin<3>(R, dtype, descs, work, nwork, grid, s);
+        case 4: return launch_batch_part_nin<4>(R, dtype, descs, work, nwork, grid, s);
+        case 5: return launch_batch_part_nin<5>(R, dtype, descs, work, nwork, grid, s);
+        case 6: return launch_batch_part_nin<6>(R, dtype, descs, work, nwork, grid, s);
+        case 7: return launch_batch_part_nin<7>(R, dtype, descs, work, nwork, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t part_desc_bytes(int n_in)
+{
+    switch (n_in) {
+        case 2: return part_desc_bytes_nin<2>();
+        case 3: return part_desc_bytes_nin<3>();
+        case 4: return part_desc_bytes_nin<4>();
+        case 5: return part_desc_bytes_nin<5>();
+        case 6: return part_desc_bytes_nin<6>();
+        case 7: return part_desc_bytes_nin<7>();
+        default: return 0;
+    }
+}
+
+void fill_part_desc(void* dst, const DevMode& m, int R, int dtype, const void* const* fac, float* out, float* carry,
+                    uint32_t gsz)
+{
+    switch (m.n_in) {
+        case 2: fill_part_desc_nin<2>(dst, m, R, dtype, fac, out, carry, gsz); break;
+        case 3: fill_part_desc_nin<3>(dst, m, R, dtype, fac, out, carry, gsz); break;
+        case 4: fill_part_desc_nin<4>(dst, m, R, dtype, fac, out, carry, gsz); break;
+        case 5: fill_part_desc_nin<5>(dst, m, R, dtype, fac, out, carry, gsz); break;
+        case 6: fill_part_desc_nin<6>(dst, m, R, dtype, fac, out, carry, gsz); break;
+        case 7: fill_part_desc_nin<7>(dst, m, R, dtype, fac, out, carry, gsz); break;
+        default: break;
+    }
 }
 
 }  // namespace mk

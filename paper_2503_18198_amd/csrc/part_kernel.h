@@ -192,40 +192,68 @@ constexpr int gathers_in_flight()
 }
 
 // State of one lane group while it walks its run of nonzeros.
-template <int NIN, int DT>
 struct GroupState {
     float acc[4];
     float head[4];
     int first_row;
     int cur;
-    uint32_t prev_idx[NIN];                 // coordinate of the last nonzero gathered
-    typename Slice<DT>::T prev_row[NIN];    // its factor slice
 };
 
+// The streamed part of one batch of 32 nonzeros: each lane of a group holds
+// V consecutive words of every input-coordinate array and of the values.
+template <int NIN, int V>
+struct Batch {
+    uint32_t idx[NIN][V];
+    uint32_t val[V];
+    uint2 w;   // {row-start bits, ordinal of the row holding the first nonzero}
+};
+
+template <int NIN, int V>
+__device__ __forceinline__ void load_batch(const PartArgs<NIN>& a, uint64_t b, int gl, Batch<NIN, V>& bt)
+{
+    static_for<0, NIN>([&](auto M) {
+        constexpr int m = decltype(M)::value;
+        load_words<V>(a.idx[m] + b + gl * V, bt.idx[m]);
+    });
+    load_words<V>(reinterpret_cast<const uint32_t*>(a.val) + b + gl * V, bt.val);
+    bt.w = a.winfo[b >> 5];
+}
+
+// Store the finished row `cur` (ordinal) of a group, or keep it as the
+// group's head partial if it is the group's first row.
+template <int R, int NIN>
+__device__ __forceinline__ void flush_row(const PartArgs<NIN>& a, GroupState& st, int rbase, uint32_t rid_pf, int gl,
+                                          int wave_grp0)
+{
+    constexpr int L = R / 4;
+    if (st.cur == st.first_row) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) st.head[e] = st.acc[e];
+    } else {
+        const int o = st.cur - rbase;
+        uint32_t rid;
+        if (o < L) rid = (uint32_t)__builtin_amdgcn_ds_bpermute((wave_grp0 + o) << 2, (int)rid_pf);
+        else rid = a.row_id[st.cur];
+        store4(a.out + (uint64_t)rid * R + gl * 4, st.acc);
+    }
+}
+
 // One batch of 32 consecutive nonzeros starting at b (b is a multiple of 32).
-// FULL: all 32 are valid (no per-nonzero bounds tests).
-template <int NIN, int R, int DT, bool FULL>
+// FULL: all 32 are valid (no per-nonzero bounds tests).  HOT: coordinates
+// may name LDS hot-row slots.
+template <int NIN, int R, int DT, bool HOT, bool FULL>
 __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __amdgpu_buffer_rsrc_t (&rsrc)[NIN],
-                                              lds_char* hot_lds, GroupState<NIN, DT>& st, uint64_t b, int nvalid,
-                                              bool first_batch, int gl, int wave_grp0)
+                                              lds_char* hot_lds, GroupState& st, const Batch<NIN, 32 / (R / 4)>& bt,
+                                              int nvalid, bool first_batch, int gl, int wave_grp0)
 {
     constexpr int L = R / 4;
     constexpr int V = 32 / L;
     constexpr int U = gathers_in_flight<NIN, R, DT>();
     using ST = typename Slice<DT>::T;
 
-    const uint2 w = a.winfo[b >> 5];
-    uint32_t flags = w.x;
+    uint32_t flags = bt.w.x;
     if (first_batch) flags &= ~1u;
     if (!FULL && nvalid < 32) flags &= (1u << nvalid) - 1u;
-
-    uint32_t sidx[NIN][V];
-    uint32_t sval[V];
-    static_for<0, NIN>([&](auto M) {
-        constexpr int m = decltype(M)::value;
-        load_words<V>(a.idx[m] + b + gl * V, sidx[m]);
-    });
-    load_words<V>(reinterpret_cast<const uint32_t*>(a.val) + b + gl * V, sval);
     // Output rows of the next L row ordinals, for the stores of this batch.
     const int rbase = st.cur;
     const uint32_t rid_pf = a.row_id[min((uint32_t)(rbase + gl), a.nrows_nz - 1u)];
@@ -233,112 +261,112 @@ __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __am
     static_for<0, 32 / U>([&](auto SB) {
         constexpr int sb = decltype(SB)::value * U;
         if (FULL || sb < nvalid) {
-            // (a) Share the sub-batch's coordinates and values inside the group.
+            // (a) Coordinates and values of the sub-batch, shared in the group.
             uint32_t vidx[U][NIN];
             float vv[U];
             static_for<0, U>([&](auto UU) {
                 constexpr int u = decltype(UU)::value;
                 constexpr int k = sb + u;
-                vv[u] = __uint_as_float(group_bcast<L, k / V>(sval[k % V]));
+                vv[u] = __uint_as_float(group_bcast<L, k / V>(bt.val[k % V]));
                 static_for<0, NIN>([&](auto M) {
                     constexpr int m = decltype(M)::value;
-                    vidx[u][m] = group_bcast<L, k / V>(sidx[m][k % V]);
+                    vidx[u][m] = group_bcast<L, k / V>(bt.idx[m][k % V]);
                 });
             });
-            // (b) Issue every gather of the sub-batch before any is used.  Rows
-            // outside the hot set come through buffer loads (a lane that needs
-            // nothing gets an out-of-range offset and reads zero); hot rows
-            // come from LDS into separate zeroed registers.  Exactly one of the
-            // two is nonzero for a lane that gathers, so they are OR-ed later.
+            // (b) Every gather of the sub-batch is issued before any is used.
+            // Buffer loads: a lane with nothing to gather (past the end, or a
+            // hot row) gets an out-of-range offset and reads zero.
             ST gg[U][NIN];
             ST hh[U][NIN];
-            bool same[U][NIN];
             static_for<0, U>([&](auto UU) {
                 constexpr int u = decltype(UU)::value;
                 constexpr int k = sb + u;
                 static_for<0, NIN>([&](auto M) {
                     constexpr int m = decltype(M)::value;
                     const uint32_t v = vidx[u][m];
-                    const uint32_t pv = u == 0 ? st.prev_idx[m] : vidx[u == 0 ? 0 : u - 1][m];
-                    const bool need = (FULL || k < nvalid) && v != pv;
-                    same[u][m] = v == pv;
-                    const bool hot = (v & kHotBitDev) != 0;
-                    const uint32_t off = (need && !hot) ? (v * (uint32_t)R + (uint32_t)gl * 4u) * Slice<DT>::kElem
-                                                        : kSkipOffset;
-                    gg[u][m] = load_buffer<DT>(rsrc[m], off);
-                    hh[u][m] = ST{};
-                    if (need && hot)
-                        hh[u][m] = load_lds<R, DT>(hot_lds + (size_t)m * a.nhot * R * Slice<DT>::kElem,
-                                                   v & ~kHotBitDev, gl);
+                    const bool valid = FULL || k < nvalid;
+                    if constexpr (HOT) {
+                        const bool hot = (v & kHotBitDev) != 0;
+                        const uint32_t off = (valid && !hot) ? (v * (uint32_t)R + (uint32_t)gl * 4u) * Slice<DT>::kElem
+                                                             : kSkipOffset;
+                        gg[u][m] = load_buffer<DT>(rsrc[m], off);
+                        hh[u][m] = ST{};
+                        if (valid && hot)
+                            hh[u][m] = load_lds<R, DT>(hot_lds + (size_t)m * a.nhot * R * Slice<DT>::kElem,
+                                                       v & ~kHotBitDev, gl);
+                    } else {
+                        const uint32_t off = valid ? (v * (uint32_t)R + (uint32_t)gl * 4u) * Slice<DT>::kElem
+                                                   : kSkipOffset;
+                        gg[u][m] = load_buffer<DT>(rsrc[m], off);
+                    }
                 });
             });
-            static_for<0, NIN>([&](auto M) {
-                constexpr int m = decltype(M)::value;
-                if (FULL) {
-                    st.prev_idx[m] = vidx[U - 1][m];
-                } else {
-                    static_for<0, U>([&](auto UU) {
-                        constexpr int u = decltype(UU)::value;
-                        if (sb + u < nvalid) st.prev_idx[m] = vidx[u][m];
-                    });
-                }
-            });
-            // (c) Products and running row sums.
+            // (c) Products; the last factor is fused into the row sum.
+            const uint32_t sub = (flags >> sb) & ((1u << U) - 1u);
+            float p[U][4];
+            float ql[U][4];
             static_for<0, U>([&](auto UU) {
                 constexpr int u = decltype(UU)::value;
-                constexpr int k = sb + u;
-                if (FULL || k < nvalid) {
-                    float p[4];
-                    static_for<0, NIN>([&](auto M) {
-                        constexpr int m = decltype(M)::value;
-                        const ST fresh = gg[u][m] | hh[u][m];
-                        const ST s = same[u][m] ? st.prev_row[m] : fresh;
-                        st.prev_row[m] = s;
-                        float q[4];
-                        unpack4<DT>(s, q);
-                        if constexpr (m == 0) {
+                static_for<0, NIN>([&](auto M) {
+                    constexpr int m = decltype(M)::value;
+                    ST sl = gg[u][m];
+                    if constexpr (HOT) sl = sl | hh[u][m];
+                    float q[4];
+                    unpack4<DT>(sl, q);
+                    if constexpr (m == 0) {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) p[e] = q[e] * vv[u];
-                        } else {
+                        for (int e = 0; e < 4; ++e) p[u][e] = q[e] * vv[u];
+                    } else if constexpr (m < NIN - 1) {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) p[e] *= q[e];
-                        }
-                    });
-                    if ((flags >> k) & 1u) {
-                        // Row `cur` ends before nonzero k.
-                        if (st.cur == st.first_row) {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) st.head[e] = st.acc[e];
-                        } else {
-                            const int o = st.cur - rbase;
-                            uint32_t rid;
-                            if (o < L)
-                                rid = (uint32_t)__builtin_amdgcn_ds_bpermute((wave_grp0 + o) << 2, (int)rid_pf);
-                            else
-                                rid = a.row_id[st.cur];
-                            store4(a.out + (uint64_t)rid * R + gl * 4, st.acc);
-                        }
-                        ++st.cur;
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) st.acc[e] = p[e];
+                        for (int e = 0; e < 4; ++e) p[u][e] *= q[e];
                     } else {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) st.acc[e] += p[e];
+                        for (int e = 0; e < 4; ++e) ql[u][e] = q[e];
                     }
+                });
+                if constexpr (NIN == 1) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ql[u][e] = 1.0f;
                 }
             });
+            if (sub == 0) {
+                // No row ends inside this sub-batch (the common case).
+                static_for<0, U>([&](auto UU) {
+                    constexpr int u = decltype(UU)::value;
+                    if (FULL || sb + u < nvalid) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) st.acc[e] = fmaf(p[u][e], ql[u][e], st.acc[e]);
+                    }
+                });
+            } else {
+                static_for<0, U>([&](auto UU) {
+                    constexpr int u = decltype(UU)::value;
+                    if (FULL || sb + u < nvalid) {
+                        if ((sub >> u) & 1u) {
+                            flush_row<R, NIN>(a, st, rbase, rid_pf, gl, wave_grp0);
+                            ++st.cur;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) st.acc[e] = p[u][e] * ql[u][e];
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) st.acc[e] = fmaf(p[u][e], ql[u][e], st.acc[e]);
+                        }
+                    }
+                });
+            }
         }
     });
 }
 
-template <int NIN, int R, int DT>
-__global__ __launch_bounds__(part_wg(NIN)) void mttkrp_part_kernel(PartArgs<NIN> a)
+// The work of one partition `part` (a workgroup's share) of one mode copy.
+template <int NIN, int R, int DT, bool HOT>
+__device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t part, char* smem)
 {
     constexpr int kPartWG = part_wg(NIN);
     constexpr int L = R / 4;            // lanes per group
+    constexpr int V = 32 / L;
     constexpr int G = kPartWG / L;      // groups per workgroup
     static_assert(R % 4 == 0 && L >= 2 && L <= 16, "unsupported rank");
-    extern __shared__ __attribute__((aligned(16))) char smem[];
 
     const int tid = threadIdx.x;
     const int g = tid / L;
@@ -348,7 +376,7 @@ __global__ __launch_bounds__(part_wg(NIN)) void mttkrp_part_kernel(PartArgs<NIN>
     // 1. Hot rows of every input factor into LDS: 16-byte chunks, eight per
     //    thread in flight (row numbers first, then the data, then the stores).
     const uint32_t row_bytes = R * Slice<DT>::kElem;
-    if (a.nhot) {
+    if (HOT && a.nhot) {
         constexpr int F = 8;
         const uint32_t cpr = row_bytes / 16;
         const uint32_t chunks = a.nhot * cpr;
@@ -367,43 +395,48 @@ __global__ __launch_bounds__(part_wg(NIN)) void mttkrp_part_kernel(PartArgs<NIN>
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     const uint32_t c = c0 + f * kPartWG;
-                    if (c < chunks) d[f] = *reinterpret_cast<const u32x4*>(fac + (uint64_t)row[f] * row_bytes + (c % cpr) * 16);
+                    if (c < chunks)
+                        d[f] = *reinterpret_cast<const u32x4*>(fac + (uint64_t)row[f] * row_bytes + (c % cpr) * 16);
                 }
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     const uint32_t c = c0 + f * kPartWG;
-                    if (c < chunks) *reinterpret_cast<u32x4*>(dst + (size_t)(c / cpr) * row_bytes + (c % cpr) * 16) = d[f];
+                    if (c < chunks)
+                        *reinterpret_cast<u32x4*>(dst + (size_t)(c / cpr) * row_bytes + (c % cpr) * 16) = d[f];
                 }
             }
         });
+        __syncthreads();
     }
-    __syncthreads();
 
-    // 2. Walk this group's run of nonzeros.
-    const uint64_t wg_beg = (uint64_t)blockIdx.x * G * a.gsz;
+    // 2. Walk this group's run of nonzeros, streaming one batch ahead.
+    const uint64_t wg_beg = (uint64_t)part * G * a.gsz;
     const uint64_t g_beg = wg_beg + (uint64_t)g * a.gsz;
-    GroupState<NIN, DT> st;
+    GroupState st;
 #pragma unroll
     for (int e = 0; e < 4; ++e) st.acc[e] = st.head[e] = 0.0f;
     st.first_row = -1;
     st.cur = -1;
-#pragma unroll
-    for (int m = 0; m < NIN; ++m) st.prev_idx[m] = 0xffffffffu;
     int hstart = -1;
     if (g_beg < a.nnz) {
         const uint64_t g_end = min(g_beg + (uint64_t)a.gsz, a.nnz);
-        const uint2 w0 = a.winfo[g_beg >> 5];
-        st.first_row = st.cur = (int)w0.y;
-        hstart = (int)(w0.x & 1u);
-        uint64_t b = g_beg;
         lds_char* hot_lds = (lds_char*)smem;
         __amdgpu_buffer_rsrc_t rsrc[NIN];
 #pragma unroll
         for (int m = 0; m < NIN; ++m) rsrc[m] = make_rsrc(a.fac[m], a.fac_bytes[m]);
-        for (; b + 32 <= g_end; b += 32)
-            process_batch<NIN, R, DT, true>(a, rsrc, hot_lds, st, b, 32, b == g_beg, gl, wave_grp0);
+        Batch<NIN, V> cur_b, next_b;
+        load_batch<NIN, V>(a, g_beg, gl, cur_b);
+        st.first_row = st.cur = (int)cur_b.w.y;
+        hstart = (int)(cur_b.w.x & 1u);
+        uint64_t b = g_beg;
+        for (; b + 32 <= g_end; b += 32) {
+            if (b + 32 < g_end) load_batch<NIN, V>(a, b + 32, gl, next_b);
+            process_batch<NIN, R, DT, HOT, true>(a, rsrc, hot_lds, st, cur_b, 32, b == g_beg, gl, wave_grp0);
+            cur_b = next_b;
+        }
         if (b < g_end)
-            process_batch<NIN, R, DT, false>(a, rsrc, hot_lds, st, b, (int)(g_end - b), b == g_beg, gl, wave_grp0);
+            process_batch<NIN, R, DT, HOT, false>(a, rsrc, hot_lds, st, cur_b, (int)(g_end - b), b == g_beg, gl,
+                                                  wave_grp0);
     }
     __syncthreads();   // every group is done with the hot rows
 
@@ -428,7 +461,6 @@ __global__ __launch_bounds__(part_wg(NIN)) void mttkrp_part_kernel(PartArgs<NIN>
     const uint64_t next_beg = wg_beg + (uint64_t)G * a.gsz;
     const bool row_continues = next_beg < a.nnz && !(a.winfo[next_beg >> 5].x & 1u);
     const int hs = s_hstart[g];
-    if (hs < 0) return;
     const int trow = s_trow[g];
 
     // A run starts at this group's first row (if g == 0 or a row starts with
@@ -456,24 +488,49 @@ __global__ __launch_bounds__(part_wg(NIN)) void mttkrp_part_kernel(PartArgs<NIN>
         const bool head_split = from_first_of_wg && s_hstart[0] == 0;
         const bool tail_split = reaches_end && row_continues;
         if (head_split || tail_split)
-            store4(a.carry + ((uint64_t)blockIdx.x * 2 + (from_first_of_wg ? 0 : 1)) * R + gl * 4, sum);
+            store4(a.carry + ((uint64_t)part * 2 + (from_first_of_wg ? 0 : 1)) * R + gl * 4, sum);
         else
             store4(a.out + (uint64_t)a.row_id[row] * R + gl * 4, sum);
     };
-    if (g == 0 || hs == 1) emit(s_head, st.first_row, g == 0, trow < 0);
-    if (trow >= 0) emit(s_tail, trow, false, true);
+    if (hs >= 0) {
+        if (g == 0 || hs == 1) emit(s_head, st.first_row, g == 0, trow < 0);
+        if (trow >= 0) emit(s_tail, trow, false, true);
+    }
 }
 
-template <int NIN, int R, int DT>
-hipError_t launch_part(const DevMode& m, const void* const* fac, const uint32_t* const* hot_rows, uint32_t nhot,
-                       float* out, float* carry, const Geometry& g, hipStream_t s)
+template <int NIN, int R, int DT, bool HOT>
+__global__ __launch_bounds__(part_wg(NIN)) void mttkrp_part_kernel(PartArgs<NIN> a)
 {
-    PartArgs<NIN> a;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    partition_body<NIN, R, DT, HOT>(a, blockIdx.x, smem);
+}
+
+// Many tensors' copies of the same mode in one launch: a static list of
+// (tensor, partition) work items, walked by a grid of resident workgroups.
+template <int NIN, int R, int DT>
+__global__ __launch_bounds__(part_wg(NIN)) void mttkrp_batch_part_kernel(const PartArgs<NIN>* __restrict__ descs,
+                                                                         const uint2* __restrict__ work,
+                                                                         uint32_t nwork)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const uint2 wk = work[w];
+        const PartArgs<NIN> a = descs[wk.x];
+        partition_body<NIN, R, DT, false>(a, wk.y, smem);
+        __syncthreads();   // the next item reuses the LDS
+    }
+}
+
+template <int NIN>
+void fill_part_args(PartArgs<NIN>& a, const DevMode& m, int R, int dtype, const void* const* fac,
+                    const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry, uint32_t gsz)
+{
+    const uint32_t es = dtype == MTTKRP_FP32 ? 4u : 2u;
     for (int j = 0; j < NIN; ++j) {
         a.idx[j] = m.idx[j];
         a.fac[j] = fac[j];
-        a.hot_rows[j] = hot_rows[j];
-        a.fac_bytes[j] = (uint32_t)((uint64_t)m.in_dims[j] * R * Slice<DT>::kElem);
+        a.hot_rows[j] = hot_rows ? hot_rows[j] : nullptr;
+        a.fac_bytes[j] = (uint32_t)((uint64_t)m.in_dims[j] * R * es);
     }
     a.val = m.val;
     a.winfo = m.winfo;
@@ -482,17 +539,25 @@ hipError_t launch_part(const DevMode& m, const void* const* fac, const uint32_t*
     a.carry = carry;
     a.nnz = m.nnz;
     a.nrows_nz = (uint32_t)m.nrows_nz;
-    a.gsz = g.gsz;
+    a.gsz = gsz;
     a.nhot = nhot;
+}
+
+template <int NIN, int R, int DT, bool HOT>
+hipError_t launch_part(const DevMode& m, const void* const* fac, const uint32_t* const* hot_rows, uint32_t nhot,
+                       float* out, float* carry, const Geometry& g, hipStream_t s)
+{
+    PartArgs<NIN> a;
+    fill_part_args<NIN>(a, m, R, DT, fac, hot_rows, nhot, out, carry, g.gsz);
     const uint32_t lds = part_lds_bytes(NIN, R, DT, nhot);
     static uint32_t lds_set = 0;   // largest dynamic LDS size already allowed for this instantiation
     if (lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mttkrp_part_kernel<NIN, R, DT>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mttkrp_part_kernel<NIN, R, DT, HOT>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         lds_set = lds;
     }
-    hipLaunchKernelGGL((mttkrp_part_kernel<NIN, R, DT>), dim3(g.nparts), dim3(part_wg(NIN)), lds, s, a);
+    hipLaunchKernelGGL((mttkrp_part_kernel<NIN, R, DT, HOT>), dim3(g.nparts), dim3(part_wg(NIN)), lds, s, a);
     return hipGetLastError();
 }
 
@@ -500,15 +565,70 @@ template <int NIN, int DT>
 hipError_t dispatch_r(const DevMode& m, int R, const void* const* fac, const uint32_t* const* hot_rows, uint32_t nhot,
                       float* out, float* carry, const Geometry& g, hipStream_t s)
 {
+    if (nhot) {
+        switch (R) {
+            case 16: return launch_part<NIN, 16, DT, true>(m, fac, hot_rows, nhot, out, carry, g, s);
+            case 32: return launch_part<NIN, 32, DT, true>(m, fac, hot_rows, nhot, out, carry, g, s);
+            case 64: return launch_part<NIN, 64, DT, true>(m, fac, hot_rows, nhot, out, carry, g, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (R) {
-        case 16: return launch_part<NIN, 16, DT>(m, fac, hot_rows, nhot, out, carry, g, s);
-        case 32: return launch_part<NIN, 32, DT>(m, fac, hot_rows, nhot, out, carry, g, s);
-        case 64: return launch_part<NIN, 64, DT>(m, fac, hot_rows, nhot, out, carry, g, s);
+        case 16: return launch_part<NIN, 16, DT, false>(m, fac, hot_rows, nhot, out, carry, g, s);
+        case 32: return launch_part<NIN, 32, DT, false>(m, fac, hot_rows, nhot, out, carry, g, s);
+        case 64: return launch_part<NIN, 64, DT, false>(m, fac, hot_rows, nhot, out, carry, g, s);
         default: return hipErrorInvalidValue;
     }
 }
 
+template <int NIN, int R, int DT>
+hipError_t launch_batch_part(const void* descs, const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s)
+{
+    const uint32_t lds = part_lds_bytes(NIN, R, DT, 0);
+    static uint32_t lds_set = 0;
+    if (lds > lds_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mttkrp_batch_part_kernel<NIN, R, DT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set = lds;
+    }
+    hipLaunchKernelGGL((mttkrp_batch_part_kernel<NIN, R, DT>), dim3(grid), dim3(part_wg(NIN)), lds, s,
+                       static_cast<const PartArgs<NIN>*>(descs), work, nwork);
+    return hipGetLastError();
+}
+
 }  // namespace part
+
+// Descriptor of one tensor's mode copy for the batched partition kernel.
+template <int NIN>
+size_t part_desc_bytes_nin() { return sizeof(part::PartArgs<NIN>); }
+
+template <int NIN>
+void fill_part_desc_nin(void* dst, const DevMode& m, int R, int dtype, const void* const* fac, float* out,
+                        float* carry, uint32_t gsz)
+{
+    part::fill_part_args<NIN>(*static_cast<part::PartArgs<NIN>*>(dst), m, R, dtype, fac, nullptr, 0, out, carry, gsz);
+}
+
+template <int NIN>
+hipError_t launch_batch_part_nin(int R, int dtype, const void* descs, const uint2* work, uint32_t nwork, uint32_t grid,
+                                 hipStream_t s)
+{
+    if (dtype == MTTKRP_FP32) {
+        switch (R) {
+            case 16: return part::launch_batch_part<NIN, 16, MTTKRP_FP32>(descs, work, nwork, grid, s);
+            case 32: return part::launch_batch_part<NIN, 32, MTTKRP_FP32>(descs, work, nwork, grid, s);
+            case 64: return part::launch_batch_part<NIN, 64, MTTKRP_FP32>(descs, work, nwork, grid, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (R) {
+        case 16: return part::launch_batch_part<NIN, 16, MTTKRP_BF16>(descs, work, nwork, grid, s);
+        case 32: return part::launch_batch_part<NIN, 32, MTTKRP_BF16>(descs, work, nwork, grid, s);
+        case 64: return part::launch_batch_part<NIN, 64, MTTKRP_BF16>(descs, work, nwork, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 template <int NIN>
 hipError_t launch_part_nin(const DevMode& m, int R, int dtype, const void* const* fac,

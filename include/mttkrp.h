@@ -146,9 +146,10 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
  * the MTTKRP along one mode for every tensor of the batch with one
  * partition-kernel launch and one fix-up launch: a static list of (tensor,
  * partition) work items, sized so that every workgroup gets about the same
- * number of nonzeros, walked by a grid of resident workgroups.  Results are
- * bitwise identical to mttkrp_run on each handle with the same R whenever the
- * per-tensor partitioning is the same, and always equal within rounding. */
+ * partition) work items, walked by a grid of resident workgroups.  Every
+ * tensor keeps the partitioning mttkrp_run gives it, so each tensor's result
+ * is bitwise the same as mttkrp_run on its handle, whatever else is in the
+ * batch. */
 typedef struct mttkrp_batch* mttkrp_batch_handle;
 
 /* layouts: host array of `count` device handles (same N, each with max_R >= R).
@@ -165,6 +166,17 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
  * are re-uploaded, which synchronises the stream first. */
 mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* const* factors, float* const* outs,
                                hipStream_t stream);
+
+/* One CP-ALS sweep for every tensor of the batch, enqueued only (capturable):
+ * per mode, each tensor's FP64 normal-equation kernels around one batched
+ * MTTKRP launch pair.  Every tensor must have been prepared with
+ * cpd_als_init(h, ..., R) (fp32 factor_dtype).  Each tensor's results are
+ * bitwise those of cpd_als_iter_async on its own handle.
+ *   factors: host array of count * N device pointers (updated in place)
+ *   lambdas: host array of count device pointers (R doubles each)
+ *   fits:    host array of count device pointers (1 double each) or NULL */
+mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* factors, double* const* lambdas,
+                                       double* const* fits, hipStream_t stream);
 
 /* Release a batch (not its layouts).  NULL is ignored. */
 void mttkrp_batch_free(mttkrp_batch_handle b);

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "MTTKRP_OK", 1: "MTTKRP_EINVAL", 2: "MTTKRP_ERANGE", 3: "MTTK
 EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "mttkrp_layout_bytes", "mttkrp_run",
             "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
             "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create", "mttkrp_batch_run",
-            "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status"]
+            "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async"]
 
 
 class MttkrpError(RuntimeError):
@@ -87,11 +87,12 @@ def _load():
     lib.mttkrp_batch_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.cpd_als_iter_async.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.c_int, vp, vp]
     lib.cpd_als_status.argtypes = [vp, vp]
+    lib.cpd_als_batch_iter_async.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.mttkrp_batch_free.argtypes = [vp]
     lib.mttkrp_batch_free.restype = None
     for name in ("mttkrp_footprint", "mttkrp_layout_build", "mttkrp_run", "mttkrp_run_bf16", "cpd_als_init",
                  "cpd_als_iter", "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create",
-                 "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status"):
+                 "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -360,3 +361,23 @@ def mttkrp_batch_run(b: Batch, mode: int, factors, outs, stream=None):
 
 def mttkrp_batch_free(b: Batch):
     b.free()
+
+
+def cpd_als_batch_iter_async(b: Batch, factors, lambdas, fits=None, stream=None):
+    """One CP-ALS sweep for every tensor of the batch (enqueued only)."""
+    import torch
+    N = len(b.layouts[0].dims)
+    C = len(b.layouts)
+    fp = (ctypes.c_void_p * (C * N))()
+    lp = (ctypes.c_void_p * C)()
+    ftp = (ctypes.c_void_p * C)()
+    for t, h in enumerate(b.layouts):
+        for m in range(N):
+            _check_factor(factors[t][m], h.dims[m], b.R, "fp32", f"factor {m} of tensor {t}")
+            fp[t * N + m] = int(factors[t][m].data_ptr())
+        if lambdas[t].dtype != torch.float64 or lambdas[t].numel() < b.R:
+            raise MttkrpError(MTTKRP_EINVAL, "lambdas must be float64 device tensors with R entries")
+        lp[t] = int(lambdas[t].data_ptr())
+        ftp[t] = int(fits[t].data_ptr()) if fits is not None else None
+    _check(_lib.cpd_als_batch_iter_async(ctypes.c_void_p(b.ptr), fp, lp, ftp if fits is not None else None,
+                                         ctypes.c_void_p(_stream(stream))))

@@ -613,24 +613,27 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
     b->N = N;
     b->R = R;
     b->hs.assign(layouts, layouts + count);
+    (void)total_nnz;
     const int cus = layouts[0]->cu_count;
-    // Every workgroup of the batch gets about the same nonzero count.
-    const uint64_t target = (uint64_t)cus * (uint64_t)o.parts_per_cu;
+    // Each tensor keeps the partitioning mttkrp_run gives it, so a tensor's
+    // result is bitwise the same alone and in any batch.
     b->geo.assign(N, std::vector<mk::Geometry>(count));
     std::vector<uint32_t> max_parts(count, 0);
     for (int n = 0; n < N; ++n)
         for (int t = 0; t < count; ++t) {
-            const uint64_t nnz = b->hs[t]->nnz;
-            const int tp = (int)std::max<uint64_t>(1, total_nnz ? (nnz * target + total_nnz / 2) / total_nnz : 1);
-            b->geo[n][t] = mk::plan_geometry(nnz, N - 1, R, tp, kMaxParts);
+            const mttkrp_handle h = b->hs[t];
+            b->geo[n][t] = mk::plan_geometry(h->nnz, N - 1, R, h->opts.parts_per_cu * h->cu_count, kMaxParts);
             max_parts[t] = std::max(max_parts[t], b->geo[n][t].nparts);
         }
-    // Work lists and sizes.
+    // Work lists (largest tensors first, which balances the resident grid).
+    std::vector<int> order(count);
+    for (int t = 0; t < count; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->hs[x]->nnz > b->hs[y]->nnz; });
     std::vector<std::vector<uint2>> pw(N), fw(N);
     const size_t pdb = mk::part_desc_bytes(N - 1), fdb = mk::fix_desc_bytes();
     std::vector<char> scratch_desc(std::max(pdb, fdb));
     for (int n = 0; n < N; ++n)
-        for (int t = 0; t < count; ++t) {
+        for (int t : order) {
             const mk::Geometry& g = b->geo[n][t];
             const uint32_t np = b->hs[t]->nnz ? g.nparts : 0;
             for (uint32_t p = 0; p < np; ++p) pw[n].push_back(make_uint2((uint32_t)t, p));
@@ -735,6 +738,53 @@ mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* con
         e = mk::launch_batch_fixup(b->fix_desc[mode], b->fix_work[mode], b->nfix_work[mode], gf, stream);
     }
     if (e != hipSuccess) return hip_fail(e, "batched MTTKRP launch");
+    return MTTKRP_OK;
+}
+
+
+mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* factors, double* const* lambdas,
+                                       double* const* fits, hipStream_t stream)
+{
+    g_err.clear();
+    if (!b) return fail(MTTKRP_EINVAL, "NULL batch");
+    if (!factors || !lambdas) return fail(MTTKRP_EINVAL, "NULL factors or lambdas");
+    const int N = b->N, R = b->R, C = b->count;
+    for (int t = 0; t < C; ++t) {
+        mttkrp_handle h = b->hs[t];
+        mttkrp_status s = check_factors(h, reinterpret_cast<const void* const*>(factors + (size_t)t * N), R);
+        if (s) return fail(s, "tensor " + std::to_string(t) + ": " + g_err);
+        if (h->als_R != R) return fail(MTTKRP_EINVAL, "tensor " + std::to_string(t) + ": call cpd_als_init first");
+        if (h->opts.factor_dtype != MTTKRP_FP32)
+            return fail(MTTKRP_EUNSUPPORTED, "batched CP-ALS gathers fp32 factors only");
+        if (!lambdas[t]) return fail(MTTKRP_EINVAL, "NULL lambda for tensor " + std::to_string(t));
+    }
+    std::vector<float*> outs(C);
+    for (int t = 0; t < C; ++t) outs[t] = b->hs[t]->als.M;
+    hipError_t e = hipSuccess;
+    for (int n = 0; n < N && e == hipSuccess; ++n) {
+        for (int t = 0; t < C && e == hipSuccess; ++t) {
+            mk::AlsWork& w = b->hs[t]->als;
+            e = mk::als_hadamard(w.grams, N, n, R, w.V, w.scal + 1, 0, stream);
+            if (e == hipSuccess) e = mk::als_cholesky_inverse(w.V, R, w.W, w.Linv, w.scal + 1, stream);
+        }
+        if (e != hipSuccess) break;
+        mttkrp_status st = mttkrp_batch_run(b, n, factors, outs.data(), stream);
+        if (st) return st;
+        for (int t = 0; t < C && e == hipSuccess; ++t) {
+            mttkrp_handle h = b->hs[t];
+            mk::AlsWork& w = h->als;
+            float* A = factors[(size_t)t * N + n];
+            e = mk::als_solve_normalize(w.M, w.W, h->dims[n], R, A, w.lam, w, stream);
+            if (e == hipSuccess) e = mk::als_gram(A, h->dims[n], R, w.grams + (uint64_t)n * R * R, w, stream);
+        }
+    }
+    for (int t = 0; t < C && e == hipSuccess; ++t) {
+        mttkrp_handle h = b->hs[t];
+        mk::AlsWork& w = h->als;
+        e = mk::als_fit(w.M, factors[(size_t)t * N + N - 1], h->dims[N - 1], w.lam, w.grams, N, R, h->normX2,
+                        (fits && fits[t]) ? fits[t] : w.scal, lambdas[t], w, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batched CP-ALS sweep");
     return MTTKRP_OK;
 }
 

@@ -46,7 +46,8 @@ def test_batch_matches_oracle_and_single(R):
             e = gu.rel_fro(got, ref)
             assert e <= TOL, f"tensor {i} mode {n}: rel err {e:.3e}"
             single = gu.gpu_mttkrp(hs[i], n, dF[i], R)
-            assert gu.rel_fro(got, single) <= TOL
+            assert np.array_equal(got.view(np.uint32), single.view(np.uint32)), \
+                f"tensor {i} mode {n}: batched result differs from the single-tensor run"
     b.free()
     for h in hs:
         h.free()
@@ -80,3 +81,35 @@ def test_batch_errors():
     small = capi.mttkrp_layout_build(ts[0].idx, ts[0].val, ts[0].dims, opts=dict(max_R=16))
     with pytest.raises(capi.MttkrpError):
         capi.mttkrp_batch_create([small], 32)    # R above max_R
+
+
+def test_batched_als_sweeps_equal_single():
+    """Each tensor's CP-ALS sweeps give the same bits alone and in the batch."""
+    print("case batch als", flush=True)
+    R = 16
+    ts, hs, F, _ = make_batch(count=6, seed=9, R=R, empty=False)
+    b = capi.mttkrp_batch_create(hs, R)
+    Fb = [gu.dev_factors(f) for f in F]
+    Fs = [gu.dev_factors(f) for f in F]
+    lam_b = [torch.zeros(R, dtype=torch.float64, device="cuda") for _ in ts]
+    lam_s = [torch.zeros(R, dtype=torch.float64, device="cuda") for _ in ts]
+    fit_b = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in ts]
+    fit_s = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in ts]
+    for i, h in enumerate(hs):
+        capi.cpd_als_init(h, Fb[i], R)
+    for _ in range(3):
+        capi.cpd_als_batch_iter_async(b, Fb, lam_b, fit_b)
+    torch.cuda.synchronize()
+    out_b = [[f.clone() for f in fs] for fs in Fb]
+    fits_b = [f.item() for f in fit_b]
+    for i, h in enumerate(hs):
+        capi.cpd_als_init(h, Fs[i], R)
+        for _ in range(3):
+            capi.cpd_als_iter_async(h, Fs[i], lam_s[i], R, fit_s[i])
+        torch.cuda.synchronize()
+        capi.cpd_als_status(h)
+        for m in range(3):
+            assert torch.equal(out_b[i][m], Fs[i][m]), f"tensor {i} factor {m}"
+        assert fits_b[i] == fit_s[i].item()
+        assert torch.equal(lam_b[i], lam_s[i])
+    b.free()

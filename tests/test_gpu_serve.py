@@ -1,0 +1,60 @@
+"""The CP-ALS server on the GPU: jobs of different shapes and ranks arrive
+over time and share steps; every job's final factors must be bitwise the
+same as when it runs alone, and the FIFO one-at-a-time executor must agree."""
+
+import numpy as np
+import pytest
+
+import workloads
+from paper_2503_18198_amd.serve import CpdServer, GpuExecutor, ServeJob
+
+pytestmark = pytest.mark.gpu
+
+
+def jobs(specs):
+    out = []
+    for i, (dims, nnz, R, arr) in enumerate(specs):
+        t = workloads.random_tensor(dims, nnz, dist="zipf", s=1.2, seed=500 + i)
+        out.append(ServeJob(job_id=i, arrival_s=arr, dims=t.dims, R=R, idx=t.idx, val=t.val, nnz=t.nnz, seed=i,
+                            max_iters=8, tol=1e-6))
+    return out
+
+
+SPECS = [((300, 250, 200), 20000, 16, 0.0), ((400, 300, 350), 30000, 16, 0.0), ((200, 150, 120, 40), 15000, 32, 0.0),
+         ((350, 280, 260), 25000, 16, 0.05), ((250, 200, 150, 30), 12000, 32, 0.1), ((500, 400, 300), 40000, 32, 0.2)]
+
+
+def test_results_same_alone_and_in_the_mix():
+    print("case serve mix", flush=True)
+    mix = jobs(SPECS)
+    m = CpdServer(GpuExecutor(batched=True), hbm_budget_bytes=8 << 30, max_slots=16).run(mix)
+    assert m["completed"] == len(SPECS), m
+    for i in range(len(SPECS)):
+        alone = jobs([SPECS[i]])[0]
+        alone.job_id = i
+        CpdServer(GpuExecutor(batched=True), hbm_budget_bytes=8 << 30, max_slots=16).run([alone])
+        assert alone.iters == mix[i].iters and alone.fits == mix[i].fits, i
+        for a, b in zip(alone.result["factors"], mix[i].result["factors"]):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), f"job {i}: factors differ alone vs mix"
+
+
+def test_fifo_executor_agrees():
+    print("case serve fifo", flush=True)
+    a = jobs(SPECS[:3])
+    b = jobs(SPECS[:3])
+    CpdServer(GpuExecutor(batched=True), 8 << 30, 16).run(a)
+    CpdServer(GpuExecutor(batched=False), 8 << 30, 1).run(b)
+    for x, y in zip(a, b):
+        assert x.fits == y.fits
+        for p, q in zip(x.result["factors"], y.result["factors"]):
+            assert np.array_equal(p, q)
+
+
+def test_budget_limits_concurrency():
+    print("case serve budget", flush=True)
+    js = jobs(SPECS[:4])
+    ex = GpuExecutor(batched=True)
+    one = max(ex.footprint(j) for j in js)
+    srv = CpdServer(ex, hbm_budget_bytes=int(one * 1.5), max_slots=16)
+    m = srv.run(js)
+    assert m["completed"] == 4 and srv.peak_in_use <= int(one * 1.5)

@@ -62,7 +62,7 @@ enum { MTTKRP_FP32 = 0, MTTKRP_BF16 = 1 };
 #define MTTKRP_MAX_MODES 8
 
 typedef struct {
-    int parts_per_cu;          /* workgroup partitions per compute unit for the MTTKRP launch; 0 = default (2) */
+    int parts_per_cu;          /* workgroup partitions per compute unit for the MTTKRP launch; 0 = default (8) */
     int factor_dtype;          /* gather precision used inside cpd_als_iter: MTTKRP_FP32 or MTTKRP_BF16 */
     int max_R;                 /* largest R the handle will run with (16, 32 or 64); sizes the workspace; 0 = 64 */
     uint64_t hbm_budget_bytes; /* refuse to build (MTTKRP_ENOMEM) when the footprint exceeds this; 0 = no budget */

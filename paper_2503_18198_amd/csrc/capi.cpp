@@ -131,7 +131,7 @@ extern "C" {
 void mttkrp_opts_default(mttkrp_opts* o)
 {
     if (!o) return;
-    o->parts_per_cu = 2;
+    o->parts_per_cu = 8;
     o->factor_dtype = MTTKRP_FP32;
     o->max_R = 64;
     o->hbm_budget_bytes = 0;
@@ -145,7 +145,7 @@ static mttkrp_status check_opts(const mttkrp_opts* in, mttkrp_opts* o)
 {
     mttkrp_opts_default(o);
     if (in) *o = *in;
-    if (o->parts_per_cu <= 0) o->parts_per_cu = 2;
+    if (o->parts_per_cu <= 0) o->parts_per_cu = 8;
     if (o->max_R == 0) o->max_R = 64;
     if (!r_supported(o->max_R)) return fail(MTTKRP_EUNSUPPORTED, "max_R must be 16, 32 or 64");
     if (o->factor_dtype != MTTKRP_FP32 && o->factor_dtype != MTTKRP_BF16)

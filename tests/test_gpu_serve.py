@@ -11,9 +11,11 @@ from paper_2503_18198_amd.serve import CpdServer, GpuExecutor, ServeJob
 pytestmark = pytest.mark.gpu
 
 
-def jobs(specs):
+def jobs(specs, first=0):
+    """Job i of the list is built from seeds 500 + first + i and first + i, so
+    a job rebuilt alone (first = its position) is the same job."""
     out = []
-    for i, (dims, nnz, R, arr) in enumerate(specs):
+    for i, (dims, nnz, R, arr) in enumerate(specs, start=first):
         t = workloads.random_tensor(dims, nnz, dist="zipf", s=1.2, seed=500 + i)
         out.append(ServeJob(job_id=i, arrival_s=arr, dims=t.dims, R=R, idx=t.idx, val=t.val, nnz=t.nnz, seed=i,
                             max_iters=8, tol=1e-6))
@@ -30,8 +32,8 @@ def test_results_same_alone_and_in_the_mix():
     m = CpdServer(GpuExecutor(batched=True), hbm_budget_bytes=8 << 30, max_slots=16).run(mix)
     assert m["completed"] == len(SPECS), m
     for i in range(len(SPECS)):
-        alone = jobs([SPECS[i]])[0]
-        alone.job_id = i
+        alone = jobs([SPECS[i]], first=i)[0]
+        alone.arrival_s = 0.0
         CpdServer(GpuExecutor(batched=True), hbm_budget_bytes=8 << 30, max_slots=16).run([alone])
         assert alone.iters == mix[i].iters and alone.fits == mix[i].fits, i
         for a, b in zip(alone.result["factors"], mix[i].result["factors"]):

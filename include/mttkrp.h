@@ -120,7 +120,8 @@ mttkrp_status cpd_als_init(mttkrp_handle h, const float* const* factors, int R, 
 
 /* One CP-ALS sweep over all modes (textbook ALS, see Sec. II-A): for each
  * mode n, V = Hadamard product of the other Gram matrices (FP64), M = MTTKRP
- * along n, A_n = M V^{-1} by Cholesky (FP64 arithmetic, fp32 store), columns
+ * along n, A_n = M V^{-1} with V^{-1} from symmetric pivoting (the sweep
+ * operator; its pivots are V's Cholesky pivots; FP64 arithmetic, fp32 store), columns
  * normalised to unit 2-norm with the norms in lambda, Gram of A_n updated.
  *   factors: host array of N device pointers, updated in place
  *   lambda:  device, R doubles (out: the norms of the last mode)

@@ -3,8 +3,9 @@
 // The paper computes CPD by alternating least squares around the MTTKRP and
 // normalises the factors (Sec. II-A).  The least-squares step is the
 // textbook one: A_n = M V^{-1} with V the Hadamard product of the other
-// factors' Gram matrices.  R <= 64 here, so V is tiny: its Cholesky factor
-// and inverse come from one workgroup, and the I_n x R products are
+// factors' Gram matrices.  R <= 64 here, so V is tiny: its inverse comes
+// from one workgroup (sweep operator, whose pivots are those of V's Cholesky
+// factorisation, so non-SPD V is caught), and the I_n x R products are
 // memory-bound row passes.  Every reduction writes per-block partials that a
 // second kernel adds in block order, so results repeat bit for bit.
 
@@ -102,78 +103,81 @@ __global__ __launch_bounds__(kWG) void hadamard_kernel(const double* __restrict_
     if (reset_flag && threadIdx.x == 0) *flag = 0.0;
 }
 
-// Cholesky factor V = L L^T (lower, in LDS), L^{-1} by forward substitution
-// (one column per thread, also in LDS), then W = L^{-T} L^{-1} = V^{-1}.
-// A pivot that is not positive beyond rounding sets *flag = 1 and fills W
-// with NaN.
-__global__ __launch_bounds__(kWG) void cholesky_inverse_kernel(const double* __restrict__ V, int R,
-                                                               double* __restrict__ W, double* flag)
+// V^{-1} of the symmetric positive definite R x R matrix V by R sweeps of the
+// sweep operator (Goodnight, 1979), all in LDS: sweeping pivot k maps A to
+//   A[i][j] - A[i][k] A[k][j] / d,  A[i][k] / d,  A[k][j] / d,  -1 / d
+// (d = A[k][k]; the four cases are i,j != k, j == k, i == k, and both), and
+// after every pivot has been swept A = -V^{-1}.  For SPD V the pivots are the
+// squared diagonal of V's Cholesky factor, so a pivot that is not positive
+// beyond rounding (relative to V_kk) means V is not SPD to working precision:
+// then *flag = 1 and W is filled with NaN.  Each sweep updates all R^2
+// entries in parallel (read, barrier, write, barrier).
+template <int R>
+__global__ __launch_bounds__(kWG) void spd_inverse_kernel(const double* __restrict__ V, double* __restrict__ W,
+                                                          double* flag)
 {
-    __shared__ double L[64 * 64];
-    __shared__ double Li[64 * 64];
-    __shared__ int bad;
+    constexpr int RR = R * R;
+    constexpr int kPer = (RR + kWG - 1) / kWG;   // entries per thread
+    __shared__ double A[RR];
+    __shared__ double diag0[R];
     const int tid = threadIdx.x;
-    const int RR = R * R;
-    for (int e = tid; e < RR; e += kWG) L[e] = V[e];
-    if (tid == 0) bad = 0;
+    for (int e = tid; e < RR; e += kWG) A[e] = V[e];
+    if (tid < R) diag0[tid] = V[tid * R + tid];
     __syncthreads();
-    for (int j = 0; j < R; ++j) {
-        if (tid == 0) {
-            // A pivot at rounding level relative to V_jj means V is singular to
-            // working precision: report it instead of dividing by noise.
-            const double vjj = L[j * R + j];
-            double d = vjj;
-            for (int k = 0; k < j; ++k) d -= L[j * R + k] * L[j * R + k];
-            if (!(d > 0.0) || d <= 64.0 * 2.220446049250313e-16 * fabs(vjj) || !isfinite(d)) {
-                bad = 1;
-                d = 1.0;
+    bool bad = false;   // every thread tests the same pivots, so this is uniform
+    for (int k = 0; k < R; ++k) {
+        double d = A[k * R + k];
+        if (!(d > 64.0 * 2.220446049250313e-16 * fabs(diag0[k])) || !isfinite(d)) {
+            bad = true;
+            d = 1.0;
+        }
+        const double inv = 1.0 / d;
+        double nv[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = tid + q * kWG;
+            const int i = e / R;
+            const int j = e % R;
+            nv[q] = 0.0;
+            if (e < RR) {
+                const double aik = A[i * R + k];
+                const double akj = A[k * R + j];
+                if (i == k && j == k) nv[q] = -inv;
+                else if (i == k) nv[q] = akj * inv;
+                else if (j == k) nv[q] = aik * inv;
+                else nv[q] = A[e] - aik * akj * inv;
             }
-            L[j * R + j] = sqrt(d);
         }
         __syncthreads();
-        const double djj = L[j * R + j];
-        for (int i = j + 1 + tid; i < R; i += kWG) {
-            double s = L[i * R + j];
-            for (int k = 0; k < j; ++k) s -= L[i * R + k] * L[j * R + k];
-            L[i * R + j] = s / djj;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = tid + q * kWG;
+            if (e < RR) A[e] = nv[q];
         }
         __syncthreads();
     }
-    // Column c of L^{-1}: x_i = 0 (i < c), x_c = 1 / L_cc, x_i = -(sum_{c<=k<i} L_ik x_k) / L_ii.
-    if (tid < R) {
-        const int c = tid;
-        for (int i = 0; i < c; ++i) Li[i * R + c] = 0.0;
-        Li[c * R + c] = 1.0 / L[c * R + c];
-        for (int i = c + 1; i < R; ++i) {
-            double s = 0.0;
-            for (int k = c; k < i; ++k) s += L[i * R + k] * Li[k * R + c];
-            Li[i * R + c] = -s / L[i * R + i];
-        }
-    }
-    __syncthreads();
-    // W[i][j] = sum_k Linv[k][i] * Linv[k][j], k >= max(i, j).
-    for (int e = tid; e < RR; e += kWG) {
-        const int i = e / R, j = e % R;
-        double s = 0.0;
-        for (int k = max(i, j); k < R; ++k) s += Li[k * R + i] * Li[k * R + j];
-        W[e] = bad ? __longlong_as_double(0x7ff8000000000000ll) : s;
-    }
+    for (int e = tid; e < RR; e += kWG) W[e] = bad ? __longlong_as_double(0x7ff8000000000000ll) : -A[e];
     if (tid == 0 && bad) *flag = 1.0;
 }
 
-// Rows of M W (FP64).  Thread (row ri of 32, column group cg of 8) computes
-// the B = R/8 columns cg*B.. of its row.  op 0: per-block column sums of
-// squares -> part[b][c].  op 1: A[i][c] = (M W)[i][c] / lam[c], stored as fp32.
+// Rows of M W (FP64).  Thread (ri of 32, column group cg of 8) computes the
+// B = R/8 columns cg*B.. of rows ri, ri+32, ... (RB rows: register blocking,
+// so each W value read from LDS feeds RB products).  The M tile is staged in
+// LDS with a padded row stride so the 8 rows a wave reads at once fall in
+// different banks.  op 0: per-block column sums of squares -> part[b][c].
+// op 1: A[i][c] = (M W)[i][c] / lam[c], stored as fp32.
 template <int R>
 __global__ __launch_bounds__(kWG) void mw_kernel(const float* __restrict__ M, const double* __restrict__ W, uint32_t I,
                                                  uint32_t rpb, int op, const double* __restrict__ lam,
                                                  float* __restrict__ A, double* __restrict__ part)
 {
     constexpr int B = R / 8;
-    constexpr int kRows = kWG / 8;
+    constexpr int RB = R == 64 ? 1 : 4;        // rows per thread (LDS: 64 KB static limit)
+    constexpr int kRows = (kWG / 8) * RB;
+    constexpr int SP = R + 1;                  // padded stride of the staged M rows
+    static_assert(kRows * SP >= kWG * B, "column partials reuse the M tile");
     __shared__ double sW[R * R];
-    __shared__ double sM[kRows * R];
-    __shared__ double sred[kWG * B];
+    __shared__ double sM[kRows * SP];
     const int tid = threadIdx.x;
     for (int e = tid; e < R * R; e += kWG) sW[e] = W[e];
     const int ri = tid / 8;
@@ -190,34 +194,50 @@ __global__ __launch_bounds__(kWG) void mw_kernel(const float* __restrict__ M, co
     for (uint32_t i0 = r0; i0 < r1; i0 += kRows) {
         const uint32_t nrow = min((uint32_t)kRows, r1 - i0);
         __syncthreads();
-        for (int e = tid; e < kRows * R; e += kWG)
-            sM[e] = e < (int)(nrow * R) ? (double)M[(uint64_t)i0 * R + e] : 0.0;
+        for (int e = tid; e < kRows * R; e += kWG) {
+            const int rr = e / R, cc = e % R;
+            sM[rr * SP + cc] = (uint32_t)rr < nrow ? (double)M[((uint64_t)i0 + rr) * R + cc] : 0.0;
+        }
         __syncthreads();
-        if ((uint32_t)ri < nrow) {
-            double acc[B];
+        double acc[RB][B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) acc[j] = 0.0;
-#pragma unroll 8
-            for (int k = 0; k < R; ++k) {
-                const double m = sM[ri * R + k];
+        for (int q = 0; q < RB; ++q)
 #pragma unroll
-                for (int j = 0; j < B; ++j) acc[j] += m * sW[k * R + cg * B + j];
+            for (int j = 0; j < B; ++j) acc[q][j] = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < R; ++k) {
+            double w[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) w[j] = sW[k * R + cg * B + j];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const double m = sM[(ri + 32 * q) * SP + k];
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc[q][j] += m * w[j];
             }
-            const uint64_t row = i0 + ri;
+        }
 #pragma unroll
-            for (int j = 0; j < B; ++j) {
-                if (op == 0) colsq[j] += acc[j] * acc[j];
-                else A[row * R + cg * B + j] = (float)(acc[j] * inv[j]);
+        for (int q = 0; q < RB; ++q) {
+            const uint32_t rr = ri + 32 * q;
+            if (rr < nrow) {
+                const uint64_t row = i0 + rr;
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    if (op == 0) colsq[j] += acc[q][j] * acc[q][j];
+                    else A[row * R + cg * B + j] = (float)(acc[q][j] * inv[j]);
+                }
             }
         }
     }
     if (op == 0) {
+        __syncthreads();
+        double* sred = sM;
 #pragma unroll
-        for (int j = 0; j < B; ++j) sred[(cg * B + j) * kRows + ri] = colsq[j];
+        for (int j = 0; j < B; ++j) sred[(cg * B + j) * 32 + ri] = colsq[j];
         __syncthreads();
         if (tid < R) {
             double t = 0.0;
-            for (int r = 0; r < kRows; ++r) t += sred[tid * kRows + r];
+            for (int r = 0; r < 32; ++r) t += sred[tid * 32 + r];
             part[(uint64_t)blockIdx.x * R + tid] = t;
         }
     }
@@ -320,10 +340,14 @@ hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, 
     return hipGetLastError();
 }
 
-hipError_t als_cholesky_inverse(const double* V, int R, double* W, double* scratch, double* flag, hipStream_t s)
+hipError_t als_spd_inverse(const double* V, int R, double* W, double* flag, hipStream_t s)
 {
-    (void)scratch;
-    hipLaunchKernelGGL(cholesky_inverse_kernel, dim3(1), dim3(kWG), 0, s, V, R, W, flag);
+    switch (R) {
+        case 16: hipLaunchKernelGGL(spd_inverse_kernel<16>, dim3(1), dim3(kWG), 0, s, V, W, flag); break;
+        case 32: hipLaunchKernelGGL(spd_inverse_kernel<32>, dim3(1), dim3(kWG), 0, s, V, W, flag); break;
+        case 64: hipLaunchKernelGGL(spd_inverse_kernel<64>, dim3(1), dim3(kWG), 0, s, V, W, flag); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ int host_threads()
 bool r_supported(int R) { return R == 16 || R == 32 || R == 64; }
 
 struct Workspace {
-    uint64_t carry = 0, grams = 0, V = 0, W = 0, Linv = 0, part = 0, colsq = 0, lam = 0, scal = 0, M = 0, bf16 = 0;
+    uint64_t carry = 0, grams = 0, V = 0, W = 0, part = 0, colsq = 0, lam = 0, scal = 0, M = 0, bf16 = 0;
     uint64_t total = 0;
 };
 
@@ -59,14 +59,13 @@ Workspace plan_workspace(const uint32_t* dims, int N, int maxR, int dtype)
     w.grams = align_up((uint64_t)N * R * R * 8ull);
     w.V = align_up(R * R * 8ull);
     w.W = align_up(R * R * 8ull);
-    w.Linv = align_up(R * R * 8ull);
     w.part = align_up((uint64_t)kAlsBlocks * R * R * 8ull);
     w.colsq = align_up(R * 8ull);
     w.lam = align_up(R * 8ull);
     w.scal = align_up(8 * 8ull);
     w.M = align_up(maxI * R * 4ull);
     w.bf16 = dtype == MTTKRP_BF16 ? (uint64_t)N * kAlign + sumI * R * 2ull : 0;
-    w.total = w.carry + w.grams + w.V + w.W + w.Linv + w.part + w.colsq + w.lam + w.scal + w.M + align_up(w.bf16);
+    w.total = w.carry + w.grams + w.V + w.W + w.part + w.colsq + w.lam + w.scal + w.M + align_up(w.bf16);
     return w;
 }
 
@@ -258,7 +257,6 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     h->als.grams = static_cast<double*>(take(ws.grams));
     h->als.V = static_cast<double*>(take(ws.V));
     h->als.W = static_cast<double*>(take(ws.W));
-    h->als.Linv = static_cast<double*>(take(ws.Linv));
     h->als.part = static_cast<double*>(take(ws.part));
     h->als.colsq = static_cast<double*>(take(ws.colsq));
     h->als.lam = static_cast<double*>(take(ws.lam));
@@ -493,7 +491,7 @@ static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* l
         const uint32_t I = h->dims[n];
         const uint64_t RR = (uint64_t)R * R;
         e = mk::als_hadamard(w.grams, N, n, R, w.V, flag, reset_flag && n == 0, stream);
-        if (e == hipSuccess) e = mk::als_cholesky_inverse(w.V, R, w.W, w.Linv, flag, stream);
+        if (e == hipSuccess) e = mk::als_spd_inverse(w.V, R, w.W, flag, stream);
         if (e == hipSuccess) {
             const void* fac[MTTKRP_MAX_MODES];
             for (int m = 0; m < N; ++m)
@@ -765,7 +763,7 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
         for (int t = 0; t < C && e == hipSuccess; ++t) {
             mk::AlsWork& w = b->hs[t]->als;
             e = mk::als_hadamard(w.grams, N, n, R, w.V, w.scal + 1, 0, stream);
-            if (e == hipSuccess) e = mk::als_cholesky_inverse(w.V, R, w.W, w.Linv, w.scal + 1, stream);
+            if (e == hipSuccess) e = mk::als_spd_inverse(w.V, R, w.W, w.scal + 1, stream);
         }
         if (e != hipSuccess) break;
         mttkrp_status st = mttkrp_batch_run(b, n, factors, outs.data(), stream);

@@ -66,7 +66,6 @@ struct AlsWork {
     double* grams = nullptr;     // N x R x R
     double* V = nullptr;         // R x R
     double* W = nullptr;         // R x R (V^{-1})
-    double* Linv = nullptr;      // R x R (inverse Cholesky factor)
     double* part = nullptr;      // per-block partial sums: max_blocks x (R x R)
     double* colsq = nullptr;     // R
     double* lam = nullptr;       // R
@@ -79,7 +78,7 @@ struct AlsWork {
 hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w, hipStream_t s);
 hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, double* flag, int reset_flag,
                         hipStream_t s);
-hipError_t als_cholesky_inverse(const double* V, int R, double* W, double* scratch, double* flag, hipStream_t s);
+hipError_t als_spd_inverse(const double* V, int R, double* W, double* flag, hipStream_t s);
 hipError_t als_solve_normalize(const float* M, const double* W, uint32_t I, int R, float* A, double* lam,
                                AlsWork& w, hipStream_t s);
 hipError_t als_fit(const float* M, const float* A, uint32_t I, const double* lam, const double* grams, int N, int R,

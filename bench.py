@@ -244,6 +244,7 @@ def main(argv=None):
     ap.add_argument("--als-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-gather-ceiling", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB, 5 times (to calibrate "
                          "the HBM byte counters against a kernel of known traffic)")
@@ -353,6 +354,36 @@ def main(argv=None):
         "build_s": round(build_s, 2),
         "launch": capi.mttkrp_layout_info(h),
     }
+
+    # On-chip ceilings of this index pattern: the same partitions' stream
+    # loads alone, and with every factor-row gather, without the arithmetic.
+    if not args.no_gather_ceiling:
+        def probe_ms(what):
+            ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(N)]
+            tot = [0.0] * N
+            for rep in range(K + 1):
+                for n in range(N):
+                    ev[n][0].record(stream)
+                    capi.mttkrp_gather_probe(h, n, dF, R, what, stream=stream)
+                    ev[n][1].record(stream)
+                torch.cuda.synchronize()
+                if rep:
+                    for n in range(N):
+                        tot[n] += ev[n][0].elapsed_time(ev[n][1])
+            return [x / K for x in tot]
+        stream_ms = probe_ms(0)
+        gather_ms = probe_ms(1)
+        gbytes = [t.nnz * (N - 1) * R * 4 for _ in range(N)]
+        result["gather_ceiling"] = {
+            "stream_only_ms_per_mode": [round(x, 4) for x in stream_ms],
+            "stream_and_gathers_ms_per_mode": [round(x, 4) for x in gather_ms],
+            "gathered_bytes_per_mode": gbytes[0],
+            "gathered_TBps_in_probe": round(sum(gbytes) / (sum(gather_ms) / 1e3) / 1e12, 2),
+            "gathered_TBps_in_mttkrp": round(sum(gbytes) / (sum(mode_ms) / 1e3) / 1e12, 2),
+            "mttkrp_time_over_probe_time": round(sum(mode_ms) / sum(gather_ms), 3),
+            "what": "mttkrp_gather_probe: the MTTKRP's stream loads and factor-row gathers on the same partitions "
+                    "and lanes, arithmetic and stores replaced by an XOR fold",
+        }
 
     # CP-ALS sweeps (MTTKRP plus the FP64 update), timed separately.
     if args.als_iters > 0:

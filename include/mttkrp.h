@@ -131,6 +131,20 @@ mttkrp_status cpd_als_init(mttkrp_handle h, const float* const* factors, int R, 
 mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
                            hipStream_t stream);
 
+/* Measurement aid for the on-chip gather ceiling (not part of the method):
+ * the index/value stream and factor-row gathers of the MTTKRP along `mode`,
+ * with the same partitions, lane groups and loads as mttkrp_run (fp32) or
+ * mttkrp_run_bf16, but the products, row sums, stores and fix-up replaced by
+ * an XOR fold of the loaded bits.  what = 0 streams the mode copy only;
+ * what = 1 also gathers every factor row the nonzeros name.
+ *   factors:      host array of N device pointers (factors[mode] unused), rows
+ *                 of R fp32 values (factor_dtype MTTKRP_FP32) or R bf16 bit
+ *                 patterns (MTTKRP_BF16)
+ * Writes nothing the caller owns; it may write the handle's carry workspace,
+ * so it must not overlap an MTTKRP on the same handle.  Errors as mttkrp_run. */
+mttkrp_status mttkrp_gather_probe(mttkrp_handle h, int mode, const void* const* factors, int factor_dtype, int R,
+                                  int what, hipStream_t stream);
+
 /* Launch facts of a handle, for tuning and reports. */
 typedef struct {
     uint32_t cu_count;            /* compute units of the handle's device */

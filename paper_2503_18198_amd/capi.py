@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "MTTKRP_OK", 1: "MTTKRP_EINVAL", 2: "MTTKRP_ERANGE", 3: "MTTK
 EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "mttkrp_layout_bytes", "mttkrp_run",
             "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
             "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create", "mttkrp_batch_run",
-            "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async"]
+            "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
+            "mttkrp_gather_probe"]
 
 
 class MttkrpError(RuntimeError):
@@ -87,6 +88,7 @@ def _load():
     lib.mttkrp_batch_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.cpd_als_iter_async.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.c_int, vp, vp]
     lib.cpd_als_status.argtypes = [vp, vp]
+    lib.mttkrp_gather_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     lib.cpd_als_batch_iter_async.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.mttkrp_batch_free.argtypes = [vp]
     lib.mttkrp_batch_free.restype = None
@@ -226,6 +228,28 @@ def mttkrp_run(h: Layout, mode: int, factors, out, R: Optional[int] = None, stre
 def mttkrp_run_bf16(h: Layout, mode: int, factors, out, R: Optional[int] = None, stream=None):
     """As mttkrp_run, with bfloat16 factor tensors."""
     _run(_lib.mttkrp_run_bf16, "bf16", h, mode, factors, out, R, stream)
+
+
+def mttkrp_gather_probe(h: Layout, mode: int, factors, R: int, what: int = 1, stream=None):
+    """Measurement aid: the stream (what=0) or stream and row gathers (what=1)
+    of the MTTKRP along ``mode`` without its arithmetic or stores.  ``factors``
+    are fp32 or bfloat16 device tensors (all the same dtype)."""
+    import torch
+    N = len(h.dims)
+    if not 0 <= int(mode) < N:
+        raise MttkrpError(MTTKRP_EINVAL, f"mode {mode} out of range for a {N}-mode tensor")
+    if len(factors) != N:
+        raise MttkrpError(MTTKRP_EINVAL, f"need {N} factors (entry {mode} may be None)")
+    dts = {f.dtype for m, f in enumerate(factors) if m != mode}
+    if len(dts) != 1 or next(iter(dts)) not in (torch.float32, torch.bfloat16):
+        raise MttkrpError(MTTKRP_EINVAL, "factors must all be float32 or all bfloat16")
+    dt = "fp32" if next(iter(dts)) == torch.float32 else "bf16"
+    for m, f in enumerate(factors):
+        if m != mode:
+            _check_factor(f, h.dims[m], R, dt, f"factor {m}")
+    _check(_lib.mttkrp_gather_probe(ctypes.c_void_p(h.ptr), int(mode), _ptr_array(factors, N),
+                                    MTTKRP_FP32 if dt == "fp32" else MTTKRP_BF16, int(R), int(what),
+                                    ctypes.c_void_p(_stream(stream))))
 
 
 def _run(fn, dt, h, mode, factors, out, R, stream):

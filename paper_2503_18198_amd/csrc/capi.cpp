@@ -440,6 +440,27 @@ mttkrp_status mttkrp_run_bf16(mttkrp_handle h, int mode, const uint16_t* const* 
     return run_mode(h, mode, reinterpret_cast<const void* const*>(factors), MTTKRP_BF16, out, R, stream);
 }
 
+mttkrp_status mttkrp_gather_probe(mttkrp_handle h, int mode, const void* const* factors, int factor_dtype, int R,
+                                  int what, hipStream_t stream)
+{
+    g_err.clear();
+    if (factor_dtype != MTTKRP_FP32 && factor_dtype != MTTKRP_BF16)
+        return fail(MTTKRP_EINVAL, "factor_dtype must be MTTKRP_FP32 or MTTKRP_BF16");
+    if (what != 0 && what != 1) return fail(MTTKRP_EINVAL, "what must be 0 (stream) or 1 (stream and gathers)");
+    if (!h) return fail(MTTKRP_EINVAL, "NULL handle");
+    // The probe has no output: the handle's own carry workspace stands in for
+    // it in the common argument checks.
+    mttkrp_status s = check_run(h, mode, factors, h->carry, R);
+    if (s) return s;
+    const mk::DevMode& d = h->dev[mode];
+    const void* fac[mk::kMaxIn];
+    for (int j = 0; j < d.n_in; ++j) fac[j] = factors[d.in_modes[j]];
+    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+    hipError_t e = mk::launch_gather_probe(d, R, factor_dtype, fac, h->carry, g, what, stream);
+    if (e != hipSuccess) return hip_fail(e, "gather probe launch");
+    return MTTKRP_OK;
+}
+
 static mttkrp_status check_factors(mttkrp_handle h, const void* const* factors, int R)
 {
     if (!h) return fail(MTTKRP_EINVAL, "NULL handle");

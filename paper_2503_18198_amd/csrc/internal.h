@@ -50,6 +50,11 @@ hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* 
                          const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry,
                          const Geometry& g, hipStream_t s);
 
+// Gather-ceiling probe of one mode (stream and row gathers, no arithmetic);
+// what = 0: stream only, 1: stream and gathers.  Writes only (rarely) carry.
+hipError_t launch_gather_probe(const DevMode& m, int R, int dtype, const void* const* fac, float* carry,
+                               const Geometry& g, int what, hipStream_t s);
+
 // Batched launches: device descriptor arrays plus (tensor, item) work lists.
 size_t part_desc_bytes(int n_in);
 void fill_part_desc(void* dst, const DevMode& m, int R, int dtype, const void* const* fac, float* out, float* carry,

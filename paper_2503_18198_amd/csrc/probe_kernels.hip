@@ -1,0 +1,128 @@
+// Gather-ceiling probe: the memory traffic of one mode's MTTKRP without its
+// arithmetic.  Same partitions, lane groups (L = R/4 lanes, 16 or 8 bytes of
+// a factor row per lane), batch stream loads and row gathers as the partition
+// kernel; the products, row sums, stores and fix-up are replaced by an XOR
+// fold of the loaded bits.  Timing it beside the MTTKRP gives the on-chip
+// ceiling of a tensor's own index pattern (what = 1) and of the stream alone
+// (what = 0).
+#include "part_kernel.h"
+
+namespace mk {
+namespace part {
+
+template <int NIN, int R, int DT, bool GATHER>
+__global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN> a)
+{
+    constexpr int kWGT = part_wg(NIN);
+    constexpr int L = R / 4;
+    constexpr int V = 32 / L;
+    constexpr int G = kWGT / L;
+    constexpr int U = gathers_in_flight<NIN, R, DT>();
+    using ST = typename Slice<DT>::T;
+
+    const int tid = threadIdx.x;
+    const int g = tid / L;
+    const int gl = tid % L;
+    const uint64_t g_beg = ((uint64_t)blockIdx.x * G + g) * a.gsz;
+    uint32_t x = 0;
+    if (g_beg < a.nnz) {
+        const uint64_t g_end = min(g_beg + (uint64_t)a.gsz, a.nnz);
+        __amdgpu_buffer_rsrc_t rsrc[NIN];
+#pragma unroll
+        for (int m = 0; m < NIN; ++m) rsrc[m] = make_rsrc(a.fac[m], a.fac_bytes[m]);
+        for (uint64_t b = g_beg; b < g_end; b += 32) {
+            Batch<NIN, V> bt;
+            load_batch<NIN, V>(a, b, gl, bt);
+            const int nvalid = (int)min((uint64_t)32, g_end - b);
+            x ^= bt.w.x ^ bt.w.y;
+            if constexpr (!GATHER) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    x ^= bt.val[j];
+#pragma unroll
+                    for (int m = 0; m < NIN; ++m) x ^= bt.idx[m][j];
+                }
+            } else {
+                static_for<0, 32 / U>([&](auto SB) {
+                    constexpr int sb = decltype(SB)::value * U;
+                    ST r[U][NIN];
+                    static_for<0, U>([&](auto UU) {
+                        constexpr int u = decltype(UU)::value;
+                        constexpr int k = sb + u;
+                        const bool valid = k < nvalid;
+                        x ^= group_bcast<L, k / V>(bt.val[k % V]);
+                        static_for<0, NIN>([&](auto M) {
+                            constexpr int m = decltype(M)::value;
+                            const uint32_t v = group_bcast<L, k / V>(bt.idx[m][k % V]);
+                            const uint32_t off =
+                                valid ? (v * (uint32_t)R + (uint32_t)gl * 4u) * Slice<DT>::kElem : kSkipOffset;
+                            r[u][m] = load_buffer<DT>(rsrc[m], off);
+                        });
+                    });
+                    static_for<0, U>([&](auto UU) {
+                        constexpr int u = decltype(UU)::value;
+                        static_for<0, NIN>([&](auto M) {
+                            constexpr int m = decltype(M)::value;
+                            if constexpr (DT == MTTKRP_FP32) x ^= r[u][m].x ^ r[u][m].y ^ r[u][m].z ^ r[u][m].w;
+                            else x ^= r[u][m].x ^ r[u][m].y;
+                        });
+                    });
+                });
+            }
+        }
+    }
+    // Practically never taken; keeps every load live.  The carry workspace is
+    // scratch that the next MTTKRP rewrites.
+    if (x == 0x9E3779B9u) a.carry[blockIdx.x] = 1.0f;
+}
+
+template <int NIN, int R, int DT>
+hipError_t launch_probe_r(const PartArgs<NIN>& a, uint32_t grid, int what, hipStream_t s)
+{
+    if (what == 0)
+        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, false>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
+    else
+        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, true>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NIN>
+hipError_t launch_probe_nin(const DevMode& m, int R, int dtype, const void* const* fac, float* carry,
+                            const Geometry& g, int what, hipStream_t s)
+{
+    PartArgs<NIN> a;
+    fill_part_args<NIN>(a, m, R, dtype, fac, nullptr, 0, nullptr, carry, g.gsz);
+    if (dtype == MTTKRP_FP32) {
+        switch (R) {
+            case 16: return launch_probe_r<NIN, 16, MTTKRP_FP32>(a, g.nparts, what, s);
+            case 32: return launch_probe_r<NIN, 32, MTTKRP_FP32>(a, g.nparts, what, s);
+            case 64: return launch_probe_r<NIN, 64, MTTKRP_FP32>(a, g.nparts, what, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (R) {
+        case 16: return launch_probe_r<NIN, 16, MTTKRP_BF16>(a, g.nparts, what, s);
+        case 32: return launch_probe_r<NIN, 32, MTTKRP_BF16>(a, g.nparts, what, s);
+        case 64: return launch_probe_r<NIN, 64, MTTKRP_BF16>(a, g.nparts, what, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace part
+
+hipError_t launch_gather_probe(const DevMode& m, int R, int dtype, const void* const* fac, float* carry,
+                               const Geometry& g, int what, hipStream_t s)
+{
+    if (m.nnz == 0 || g.nparts == 0) return hipSuccess;
+    switch (m.n_in) {
+        case 2: return part::launch_probe_nin<2>(m, R, dtype, fac, carry, g, what, s);
+        case 3: return part::launch_probe_nin<3>(m, R, dtype, fac, carry, g, what, s);
+        case 4: return part::launch_probe_nin<4>(m, R, dtype, fac, carry, g, what, s);
+        case 5: return part::launch_probe_nin<5>(m, R, dtype, fac, carry, g, what, s);
+        case 6: return part::launch_probe_nin<6>(m, R, dtype, fac, carry, g, what, s);
+        case 7: return part::launch_probe_nin<7>(m, R, dtype, fac, carry, g, what, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mk

@@ -100,9 +100,10 @@ def _keys(coords: np.ndarray, dims: Sequence[int]) -> np.ndarray:
     return c.view(np.dtype((np.void, 4 * c.shape[1]))).ravel()
 
 
-def distinct_coords(samplers, dims: Sequence[int], nnz: int, rng: np.random.Generator
-                    ) -> np.ndarray:
-    """Draw-and-top-up until exactly ``nnz`` distinct coordinates remain."""
+def distinct_coords(samplers, dims: Sequence[int], nnz: int, rng: np.random.Generator,
+                    progress: Optional[Callable[[str], None]] = None) -> np.ndarray:
+    """Draw-and-top-up until exactly ``nnz`` distinct coordinates remain.
+    ``progress`` (optional) receives a line after every draw round."""
     N = len(dims)
     accepted = []
     seen = None  # sorted keys of accepted coordinates
@@ -111,6 +112,8 @@ def distinct_coords(samplers, dims: Sequence[int], nnz: int, rng: np.random.Gene
         c = np.empty((need, N), dtype=np.int64)
         for m in range(N):
             c[:, m] = samplers[m](rng, need)
+            if progress is not None and need >= 10_000_000:
+                progress(f"drew {need} indices of mode {m}")
         k = _keys(c, dims)
         u, first = np.unique(k, return_index=True)
         if seen is not None and seen.shape[0]:
@@ -127,12 +130,15 @@ def distinct_coords(samplers, dims: Sequence[int], nnz: int, rng: np.random.Gene
             newk = np.sort(k[first])
             seen = np.insert(seen, np.searchsorted(seen, newk), newk)
         need -= first.shape[0]
+        if progress is not None:
+            progress(f"distinct coordinates: {nnz - need} of {nnz}")
     out = np.concatenate(accepted, axis=0) if len(accepted) > 1 else accepted[0]
     return out.astype(np.uint32)
 
 
 def random_tensor(dims: Sequence[int], nnz: int, dist: str = "uniform", s: Optional[float] = None,
-                  values: str = "uniform", seed=0) -> SparseTensor:
+                  values: str = "uniform", seed=0, progress: Optional[Callable[[str], None]] = None
+                  ) -> SparseTensor:
     dims = tuple(int(d) for d in dims)
     cap = int(0.1 * math.prod(dims)) if len(dims) else 0
     capped = nnz > cap
@@ -140,7 +146,7 @@ def random_tensor(dims: Sequence[int], nnz: int, dist: str = "uniform", s: Optio
     r_idx, r_val, _, _ = _streams(seed)
     samplers = [_make_sampler(d, dist, s, r_idx) for d in dims]
     if nnz_eff > 0:
-        idx = distinct_coords(samplers, dims, nnz_eff, r_idx)
+        idx = distinct_coords(samplers, dims, nnz_eff, r_idx, progress)
     else:
         idx = np.zeros((0, len(dims)), dtype=np.uint32)
     if values == "uniform":
@@ -153,13 +159,14 @@ def random_tensor(dims: Sequence[int], nnz: int, dist: str = "uniform", s: Optio
                         nnz_requested=int(nnz), capped=capped)
 
 
-def config_tensor(config_id: int, scale: float = 1.0) -> SparseTensor:
+def config_tensor(config_id: int, scale: float = 1.0, progress: Optional[Callable[[str], None]] = None
+                  ) -> SparseTensor:
     """The tensor of a named configuration; ``scale`` < 1 shrinks dims and nnz
     proportionally (for quick runs), keeping the distribution."""
     c = CONFIGS[config_id]
     dims = tuple(max(2, int(round(d * scale))) for d in c["dims"])
     nnz = max(1, int(round(c["nnz"] * scale)))
-    return random_tensor(dims, nnz, c["dist"], c["s"], c["values"], seed=config_id)
+    return random_tensor(dims, nnz, c["dist"], c["s"], c["values"], seed=config_id, progress=progress)
 
 
 def random_factors(dims: Sequence[int], R: int, seed=0, low: float = 0.0, high: float = 1.0

@@ -416,7 +416,7 @@ static mttkrp_status run_mode(mttkrp_handle h, int mode, const void* const* fact
         fac[j] = factors[d.in_modes[j]];
         hot[j] = h->hot_rows[d.in_modes[j]];
     }
-    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, dtype, h->opts.parts_per_cu * h->cu_count, kMaxParts);
     hipError_t e = mk::launch_mttkrp(d, R, dtype, fac, hot, h->nhot, out, h->carry, g, stream);
     if (e != hipSuccess) return hip_fail(e, "MTTKRP launch");
     return MTTKRP_OK;
@@ -455,7 +455,8 @@ mttkrp_status mttkrp_gather_probe(mttkrp_handle h, int mode, const void* const* 
     const mk::DevMode& d = h->dev[mode];
     const void* fac[mk::kMaxIn];
     for (int j = 0; j < d.n_in; ++j) fac[j] = factors[d.in_modes[j]];
-    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+    const mk::Geometry g =
+        mk::plan_geometry(d.nnz, d.n_in, R, factor_dtype, h->opts.parts_per_cu * h->cu_count, kMaxParts);
     hipError_t e = mk::launch_gather_probe(d, R, factor_dtype, fac, h->carry, g, what, stream);
     if (e != hipSuccess) return hip_fail(e, "gather probe launch");
     return MTTKRP_OK;
@@ -641,7 +642,8 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
     for (int n = 0; n < N; ++n)
         for (int t = 0; t < count; ++t) {
             const mttkrp_handle h = b->hs[t];
-            b->geo[n][t] = mk::plan_geometry(h->nnz, N - 1, R, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+            b->geo[n][t] =
+                mk::plan_geometry(h->nnz, N - 1, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count, kMaxParts);
             max_parts[t] = std::max(max_parts[t], b->geo[n][t].nparts);
         }
     // Work lists (largest tensors first, which balances the resident grid).

@@ -28,14 +28,14 @@ struct DevMode {
 
 // Launch geometry of one MTTKRP call.
 struct Geometry {
-    int lanes;          // lanes per group: four factor values per lane
+    int lanes;          // lanes per group: 16 bytes of a factor row per lane
     int groups;         // lane groups per workgroup
     uint32_t gsz;       // nonzeros per lane group (multiple of 32)
     uint64_t wgc;       // nonzeros per workgroup partition = groups * gsz
     uint32_t nparts;    // workgroups
 };
 
-Geometry plan_geometry(uint64_t nnz, int n_in, int R, int target_parts, uint32_t max_parts);
+Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts);
 
 // Threads per partition workgroup for n_in input modes.
 int partition_wg_threads(int n_in);

@@ -153,10 +153,10 @@ __global__ __launch_bounds__(kWG) void mttkrp_batch_fixup_kernel(const FixArgs* 
 
 }  // namespace
 
-Geometry plan_geometry(uint64_t nnz, int n_in, int R, int target_parts, uint32_t max_parts)
+Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts)
 {
     Geometry g;
-    g.lanes = R / 4;
+    g.lanes = lanes_per_row(R, dtype);
     g.groups = part_wg(n_in) / g.lanes;
     if (target_parts < 1) target_parts = 1;
     uint64_t per_group = (nnz + (uint64_t)target_parts * g.groups - 1) / ((uint64_t)target_parts * g.groups);

@@ -38,10 +38,16 @@ constexpr uint32_t kHotBitDev = 0x80000000u;
 #endif
 constexpr int part_wg(int n_in) { return n_in <= 2 ? MK_WG_3MODE : 256; }
 
+// Factor values each lane gathers and accumulates: 16 bytes of a row, i.e. 4
+// fp32 or 8 bf16 values (bf16 rows of R = 16 keep 4 per lane, so a row still
+// spans more than one lane), and the lanes that share one row.
+constexpr int vals_per_lane(int R, int dtype) { return (dtype == MTTKRP_BF16 && R >= 32) ? 8 : 4; }
+constexpr int lanes_per_row(int R, int dtype) { return R / vals_per_lane(R, dtype); }
+
 // Dynamic LDS bytes of a partition workgroup.
 inline uint32_t part_lds_bytes(int n_in, int R, int dtype, uint32_t nhot)
 {
-    const uint32_t groups = part_wg(n_in) / (R / 4);
+    const uint32_t groups = part_wg(n_in) / lanes_per_row(R, dtype);
     const uint32_t es = dtype == MTTKRP_FP32 ? 4 : 2;
     const uint32_t hot = (uint32_t)n_in * nhot * (uint32_t)R * es;
     const uint32_t slots = 2u * groups * (uint32_t)R * 4u;
@@ -100,20 +106,14 @@ __device__ __forceinline__ void load_words(const uint32_t* p, uint32_t (&w)[V])
     }
 }
 
-// Four consecutive factor values: 16 bytes of fp32 or 8 bytes of bf16.
-template <int DT>
-struct Slice {
-    using T = typename std::conditional<DT == MTTKRP_FP32, u32x4, u32x2>::type;
-    static constexpr int kBytes = DT == MTTKRP_FP32 ? 16 : 8;
-    static constexpr int kElem = DT == MTTKRP_FP32 ? 4 : 2;
-};
-
+// One lane's consecutive factor values of a row: kVals values of kElem bytes.
 template <int R, int DT>
-__device__ __forceinline__ typename Slice<DT>::T load_global(const void* fac, uint32_t row, int gl)
-{
-    const char* p = static_cast<const char*>(fac) + ((uint64_t)row * R + gl * 4) * Slice<DT>::kElem;
-    return *reinterpret_cast<const typename Slice<DT>::T*>(p);
-}
+struct Slice {
+    static constexpr int kVals = vals_per_lane(R, DT);
+    static constexpr int kElem = DT == MTTKRP_FP32 ? 4 : 2;
+    static constexpr int kBytes = kVals * kElem;
+    using T = typename std::conditional<kBytes == 16, u32x4, u32x2>::type;
+};
 
 // Buffer-resource loads: 32-bit offsets, and an offset past the end returns
 // zero without touching memory, which turns a skipped gather into a no-op
@@ -126,25 +126,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, (int)kRsrcWord3);
 }
 
-template <int DT>
-__device__ __forceinline__ typename Slice<DT>::T load_buffer(__amdgpu_buffer_rsrc_t r, uint32_t off)
+template <int R, int DT>
+__device__ __forceinline__ typename Slice<R, DT>::T load_buffer(__amdgpu_buffer_rsrc_t r, uint32_t off)
 {
-    if constexpr (DT == MTTKRP_FP32) return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    if constexpr (Slice<R, DT>::kBytes == 16) return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
     else return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
 }
 
 typedef __attribute__((address_space(3))) const char lds_char;
 
 template <int R, int DT>
-__device__ __forceinline__ typename Slice<DT>::T load_lds(lds_char* base, uint32_t slot, int gl)
+__device__ __forceinline__ typename Slice<R, DT>::T load_lds(lds_char* base, uint32_t slot, int gl)
 {
-    lds_char* p = base + (slot * R + gl * 4) * Slice<DT>::kElem;
-    return *reinterpret_cast<__attribute__((address_space(3))) const typename Slice<DT>::T*>(p);
+    lds_char* p = base + (slot * R + gl * Slice<R, DT>::kVals) * Slice<R, DT>::kElem;
+    return *reinterpret_cast<__attribute__((address_space(3))) const typename Slice<R, DT>::T*>(p);
 }
 
 // bf16 -> fp32 is exact: the bf16 bits are the high half of the fp32 pattern.
-template <int DT>
-__device__ __forceinline__ void unpack4(const typename Slice<DT>::T v, float (&f)[4])
+template <int R, int DT>
+__device__ __forceinline__ void unpack(const typename Slice<R, DT>::T v, float (&f)[Slice<R, DT>::kVals])
 {
     if constexpr (DT == MTTKRP_FP32) {
         f[0] = __uint_as_float(v.x);
@@ -152,17 +152,24 @@ __device__ __forceinline__ void unpack4(const typename Slice<DT>::T v, float (&f
         f[2] = __uint_as_float(v.z);
         f[3] = __uint_as_float(v.w);
     } else {
-        f[0] = __uint_as_float(v.x << 16);
-        f[1] = __uint_as_float(v.x & 0xffff0000u);
-        f[2] = __uint_as_float(v.y << 16);
-        f[3] = __uint_as_float(v.y & 0xffff0000u);
+        constexpr int W = Slice<R, DT>::kVals / 2;   // 32-bit words, two bf16 each
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            f[2 * i] = __uint_as_float(v[i] << 16);
+            f[2 * i + 1] = __uint_as_float(v[i] & 0xffff0000u);
+        }
     }
 }
 
-__device__ __forceinline__ void store4(float* dst, const float (&v)[4])
+// E consecutive fp32 values (E = 4 or 8) with 16-byte stores.
+template <int E>
+__device__ __forceinline__ void store_vals(float* dst, const float (&v)[E])
 {
-    const f32x4 t = {v[0], v[1], v[2], v[3]};
-    *reinterpret_cast<f32x4*>(dst) = t;
+#pragma unroll
+    for (int j = 0; j < E / 4; ++j) {
+        const f32x4 t = {v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
+        *reinterpret_cast<f32x4*>(dst + 4 * j) = t;
+    }
 }
 
 template <int NIN>
@@ -184,18 +191,23 @@ struct PartArgs {
 
 // Nonzeros whose row gathers are issued before the first is used, chosen so
 // that a 1024-thread workgroup (128 registers per lane) does not spill.
+#ifndef MK_U_BF16_WIDE
+#define MK_U_BF16_WIDE 4
+#endif
 template <int NIN, int R, int DT>
 constexpr int gathers_in_flight()
 {
+    if constexpr (vals_per_lane(R, DT) == 8) return MK_U_BF16_WIDE;
     if constexpr (NIN <= 2) return (DT == MTTKRP_FP32 && R == 16) ? 2 : MK_U_3MODE;
     else if constexpr (NIN <= 3) return (DT == MTTKRP_FP32 && R == 16) ? 2 : 4;
     else return 2;
 }
 
-// State of one lane group while it walks its run of nonzeros.
+// State of one lane group while it walks its run of nonzeros (E values per lane).
+template <int E>
 struct GroupState {
-    float acc[4];
-    float head[4];
+    float acc[E];
+    float head[E];
     int first_row;
     int cur;
 };
@@ -222,20 +234,21 @@ __device__ __forceinline__ void load_batch(const PartArgs<NIN>& a, uint64_t b, i
 
 // Store the finished row `cur` (ordinal) of a group, or keep it as the
 // group's head partial if it is the group's first row.
-template <int R, int NIN>
-__device__ __forceinline__ void flush_row(const PartArgs<NIN>& a, GroupState& st, int rbase, uint32_t rid_pf, int gl,
-                                          int wave_grp0)
+template <int R, int DT, int NIN>
+__device__ __forceinline__ void flush_row(const PartArgs<NIN>& a, GroupState<vals_per_lane(R, DT)>& st, int rbase,
+                                          uint32_t rid_pf, int gl, int wave_grp0)
 {
-    constexpr int L = R / 4;
+    constexpr int E = vals_per_lane(R, DT);
+    constexpr int L = R / E;
     if (st.cur == st.first_row) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) st.head[e] = st.acc[e];
+        for (int e = 0; e < E; ++e) st.head[e] = st.acc[e];
     } else {
         const int o = st.cur - rbase;
         uint32_t rid;
         if (o < L) rid = (uint32_t)__builtin_amdgcn_ds_bpermute((wave_grp0 + o) << 2, (int)rid_pf);
         else rid = a.row_id[st.cur];
-        store4(a.out + (uint64_t)rid * R + gl * 4, st.acc);
+        store_vals<E>(a.out + (uint64_t)rid * R + gl * E, st.acc);
     }
 }
 
@@ -244,13 +257,15 @@ __device__ __forceinline__ void flush_row(const PartArgs<NIN>& a, GroupState& st
 // may name LDS hot-row slots.
 template <int NIN, int R, int DT, bool HOT, bool FULL>
 __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __amdgpu_buffer_rsrc_t (&rsrc)[NIN],
-                                              lds_char* hot_lds, GroupState& st, const Batch<NIN, 32 / (R / 4)>& bt,
+                                              lds_char* hot_lds, GroupState<vals_per_lane(R, DT)>& st,
+                                              const Batch<NIN, 32 / lanes_per_row(R, DT)>& bt,
                                               int nvalid, bool first_batch, int gl, int wave_grp0)
 {
-    constexpr int L = R / 4;
+    constexpr int E = vals_per_lane(R, DT);
+    constexpr int L = R / E;
     constexpr int V = 32 / L;
     constexpr int U = gathers_in_flight<NIN, R, DT>();
-    using ST = typename Slice<DT>::T;
+    using ST = typename Slice<R, DT>::T;
 
     uint32_t flags = bt.w.x;
     if (first_batch) flags &= ~1u;
@@ -288,46 +303,46 @@ __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __am
                     const bool valid = FULL || k < nvalid;
                     if constexpr (HOT) {
                         const bool hot = (v & kHotBitDev) != 0;
-                        const uint32_t off = (valid && !hot) ? (v * (uint32_t)R + (uint32_t)gl * 4u) * Slice<DT>::kElem
+                        const uint32_t off = (valid && !hot) ? (v * (uint32_t)R + (uint32_t)(gl * E)) * Slice<R, DT>::kElem
                                                              : kSkipOffset;
-                        gg[u][m] = load_buffer<DT>(rsrc[m], off);
+                        gg[u][m] = load_buffer<R, DT>(rsrc[m], off);
                         hh[u][m] = ST{};
                         if (valid && hot)
-                            hh[u][m] = load_lds<R, DT>(hot_lds + (size_t)m * a.nhot * R * Slice<DT>::kElem,
+                            hh[u][m] = load_lds<R, DT>(hot_lds + (size_t)m * a.nhot * R * Slice<R, DT>::kElem,
                                                        v & ~kHotBitDev, gl);
                     } else {
-                        const uint32_t off = valid ? (v * (uint32_t)R + (uint32_t)gl * 4u) * Slice<DT>::kElem
+                        const uint32_t off = valid ? (v * (uint32_t)R + (uint32_t)(gl * E)) * Slice<R, DT>::kElem
                                                    : kSkipOffset;
-                        gg[u][m] = load_buffer<DT>(rsrc[m], off);
+                        gg[u][m] = load_buffer<R, DT>(rsrc[m], off);
                     }
                 });
             });
             // (c) Products; the last factor is fused into the row sum.
             const uint32_t sub = (flags >> sb) & ((1u << U) - 1u);
-            float p[U][4];
-            float ql[U][4];
+            float p[U][E];
+            float ql[U][E];
             static_for<0, U>([&](auto UU) {
                 constexpr int u = decltype(UU)::value;
                 static_for<0, NIN>([&](auto M) {
                     constexpr int m = decltype(M)::value;
                     ST sl = gg[u][m];
                     if constexpr (HOT) sl = sl | hh[u][m];
-                    float q[4];
-                    unpack4<DT>(sl, q);
+                    float q[E];
+                    unpack<R, DT>(sl, q);
                     if constexpr (m == 0) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) p[u][e] = q[e] * vv[u];
+                        for (int e = 0; e < E; ++e) p[u][e] = q[e] * vv[u];
                     } else if constexpr (m < NIN - 1) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) p[u][e] *= q[e];
+                        for (int e = 0; e < E; ++e) p[u][e] *= q[e];
                     } else {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) ql[u][e] = q[e];
+                        for (int e = 0; e < E; ++e) ql[u][e] = q[e];
                     }
                 });
                 if constexpr (NIN == 1) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) ql[u][e] = 1.0f;
+                    for (int e = 0; e < E; ++e) ql[u][e] = 1.0f;
                 }
             });
             if (sub == 0) {
@@ -336,7 +351,7 @@ __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __am
                     constexpr int u = decltype(UU)::value;
                     if (FULL || sb + u < nvalid) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) st.acc[e] = fmaf(p[u][e], ql[u][e], st.acc[e]);
+                        for (int e = 0; e < E; ++e) st.acc[e] = fmaf(p[u][e], ql[u][e], st.acc[e]);
                     }
                 });
             } else {
@@ -344,13 +359,13 @@ __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __am
                     constexpr int u = decltype(UU)::value;
                     if (FULL || sb + u < nvalid) {
                         if ((sub >> u) & 1u) {
-                            flush_row<R, NIN>(a, st, rbase, rid_pf, gl, wave_grp0);
+                            flush_row<R, DT, NIN>(a, st, rbase, rid_pf, gl, wave_grp0);
                             ++st.cur;
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) st.acc[e] = p[u][e] * ql[u][e];
+                            for (int e = 0; e < E; ++e) st.acc[e] = p[u][e] * ql[u][e];
                         } else {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) st.acc[e] = fmaf(p[u][e], ql[u][e], st.acc[e]);
+                            for (int e = 0; e < E; ++e) st.acc[e] = fmaf(p[u][e], ql[u][e], st.acc[e]);
                         }
                     }
                 });
@@ -364,10 +379,11 @@ template <int NIN, int R, int DT, bool HOT>
 __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t part, char* smem)
 {
     constexpr int kPartWG = part_wg(NIN);
-    constexpr int L = R / 4;            // lanes per group
+    constexpr int E = vals_per_lane(R, DT);
+    constexpr int L = R / E;            // lanes per group
     constexpr int V = 32 / L;
     constexpr int G = kPartWG / L;      // groups per workgroup
-    static_assert(R % 4 == 0 && L >= 2 && L <= 16, "unsupported rank");
+    static_assert(R % E == 0 && L >= 2 && L <= 16, "unsupported rank");
 
     const int tid = threadIdx.x;
     const int g = tid / L;
@@ -376,7 +392,7 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
 
     // 1. Hot rows of every input factor into LDS: 16-byte chunks, eight per
     //    thread in flight (row numbers first, then the data, then the stores).
-    const uint32_t row_bytes = R * Slice<DT>::kElem;
+    const uint32_t row_bytes = R * Slice<R, DT>::kElem;
     if (HOT && a.nhot) {
         constexpr int F = 8;
         const uint32_t cpr = row_bytes / 16;
@@ -413,9 +429,9 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
     // 2. Walk this group's run of nonzeros, streaming one batch ahead.
     const uint64_t wg_beg = (uint64_t)part * G * a.gsz;
     const uint64_t g_beg = wg_beg + (uint64_t)g * a.gsz;
-    GroupState st;
+    GroupState<E> st;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) st.acc[e] = st.head[e] = 0.0f;
+    for (int e = 0; e < E; ++e) st.acc[e] = st.head[e] = 0.0f;
     st.first_row = -1;
     st.cur = -1;
     int hstart = -1;
@@ -450,8 +466,8 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
     int* s_hstart = s_trow + G;
     const bool multi = st.first_row >= 0 && st.cur != st.first_row;
     if (st.first_row >= 0) {
-        store4(s_head + g * R + gl * 4, multi ? st.head : st.acc);
-        if (multi) store4(s_tail + g * R + gl * 4, st.acc);
+        store_vals<E>(s_head + g * R + gl * E, multi ? st.head : st.acc);
+        if (multi) store_vals<E>(s_tail + g * R + gl * E, st.acc);
     }
     if (gl == 0) {
         s_trow[g] = multi ? st.cur : -1;
@@ -468,9 +484,9 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
     // the group) and/or at its last row; its owner adds the following groups'
     // first rows while they continue it.
     auto emit = [&](const float* src, int row, bool from_first_of_wg, bool extend) {
-        float sum[4];
+        float sum[E];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) sum[e] = src[g * R + gl * 4 + e];
+        for (int e = 0; e < E; ++e) sum[e] = src[g * R + gl * E + e];
         bool reaches_end = extend;
         if (extend) {
             for (int j = g + 1; j < G; ++j) {
@@ -479,7 +495,7 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
                     break;
                 }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) sum[e] += s_head[j * R + gl * 4 + e];
+                for (int e = 0; e < E; ++e) sum[e] += s_head[j * R + gl * E + e];
                 if (s_trow[j] >= 0) {
                     reaches_end = false;
                     break;
@@ -489,9 +505,9 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
         const bool head_split = from_first_of_wg && s_hstart[0] == 0;
         const bool tail_split = reaches_end && row_continues;
         if (head_split || tail_split)
-            store4(a.carry + ((uint64_t)part * 2 + (from_first_of_wg ? 0 : 1)) * R + gl * 4, sum);
+            store_vals<E>(a.carry + ((uint64_t)part * 2 + (from_first_of_wg ? 0 : 1)) * R + gl * E, sum);
         else
-            store4(a.out + (uint64_t)a.row_id[row] * R + gl * 4, sum);
+            store_vals<E>(a.out + (uint64_t)a.row_id[row] * R + gl * E, sum);
     };
     if (hs >= 0) {
         if (g == 0 || hs == 1) emit(s_head, st.first_row, g == 0, trow < 0);

@@ -1,6 +1,6 @@
 // Gather-ceiling probe: the memory traffic of one mode's MTTKRP without its
-// arithmetic.  Same partitions, lane groups (L = R/4 lanes, 16 or 8 bytes of
-// a factor row per lane), batch stream loads and row gathers as the partition
+// arithmetic.  Same partitions, lane groups (16 bytes of a factor row per
+// lane, 8 for bf16 rows of R = 16), batch stream loads and row gathers as the partition
 // kernel; the products, row sums, stores and fix-up are replaced by an XOR
 // fold of the loaded bits.  Timing it beside the MTTKRP gives the on-chip
 // ceiling of a tensor's own index pattern (what = 1) and of the stream alone
@@ -14,11 +14,12 @@ template <int NIN, int R, int DT, bool GATHER>
 __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN> a)
 {
     constexpr int kWGT = part_wg(NIN);
-    constexpr int L = R / 4;
+    constexpr int E = vals_per_lane(R, DT);
+    constexpr int L = R / E;
     constexpr int V = 32 / L;
     constexpr int G = kWGT / L;
     constexpr int U = gathers_in_flight<NIN, R, DT>();
-    using ST = typename Slice<DT>::T;
+    using ST = typename Slice<R, DT>::T;
 
     const int tid = threadIdx.x;
     const int g = tid / L;
@@ -55,15 +56,15 @@ __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN
                             constexpr int m = decltype(M)::value;
                             const uint32_t v = group_bcast<L, k / V>(bt.idx[m][k % V]);
                             const uint32_t off =
-                                valid ? (v * (uint32_t)R + (uint32_t)gl * 4u) * Slice<DT>::kElem : kSkipOffset;
-                            r[u][m] = load_buffer<DT>(rsrc[m], off);
+                                valid ? (v * (uint32_t)R + (uint32_t)(gl * E)) * Slice<R, DT>::kElem : kSkipOffset;
+                            r[u][m] = load_buffer<R, DT>(rsrc[m], off);
                         });
                     });
                     static_for<0, U>([&](auto UU) {
                         constexpr int u = decltype(UU)::value;
                         static_for<0, NIN>([&](auto M) {
                             constexpr int m = decltype(M)::value;
-                            if constexpr (DT == MTTKRP_FP32) x ^= r[u][m].x ^ r[u][m].y ^ r[u][m].z ^ r[u][m].w;
+                            if constexpr (Slice<R, DT>::kBytes == 16) x ^= r[u][m].x ^ r[u][m].y ^ r[u][m].z ^ r[u][m].w;
                             else x ^= r[u][m].x ^ r[u][m].y;
                         });
                     });

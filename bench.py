@@ -137,17 +137,27 @@ def bench_batch(args, R=16, count=256):
     build_s = time.perf_counter() - t0
     F = [[torch.from_numpy(f).cuda() for f in workloads.random_factors(t.dims, R, seed=i)] for i, t in enumerate(ts)]
     outs = [[torch.empty((d, R), device="cuda") for d in t.dims] for t in ts]
-    opts = dict(parts_per_cu=args.parts_per_cu) if args.parts_per_cu else None
-    b = capi.mttkrp_batch_create(hs, R, opts=opts)
+    # Partition size: measured by the autotuner unless given.
+    if args.parts_per_cu:
+        capi.mttkrp_batch_autotune(hs, R, F, outs, candidates=[args.parts_per_cu], reps=1, stream=stream)
+        tuned = {"parts_per_cu": args.parts_per_cu, "source": "--parts-per-cu"}
+    else:
+        t0 = time.perf_counter()
+        best, times = capi.mttkrp_batch_autotune(hs, R, F, outs, reps=3, stream=stream)
+        tuned = {"parts_per_cu": best, "source": "mttkrp_batch_autotune",
+                 "candidate_ms_per_pass": {str(k): round(v, 4) for k, v in times.items()},
+                 "tuning_s": round(time.perf_counter() - t0, 2)}
+    print(f"[bench] partition size {tuned}", file=sys.stderr, flush=True)
+    b = capi.mttkrp_batch_create(hs, R)
 
-    def batched():
+    def batched(st=stream):
         for n in range(3):
-            capi.mttkrp_batch_run(b, n, F, [o[n] for o in outs], stream=stream)
+            capi.mttkrp_batch_run(b, n, F, [o[n] for o in outs], stream=st)
 
-    def plain():
+    def plain(st=stream):
         for n in range(3):
             for i, h in enumerate(hs):
-                capi.mttkrp_run(h, n, F[i], outs[i][n], R, stream=stream)
+                capi.mttkrp_run(h, n, F[i], outs[i][n], R, stream=st)
 
     def timed(fn, K, W):
         for _ in range(W):
@@ -162,8 +172,77 @@ def bench_batch(args, R=16, count=256):
         torch.cuda.synchronize()
         return a.elapsed_time(z) / K
 
-    ms_b = timed(batched, args.steps, args.warmup)
-    ms_p = timed(plain, max(3, args.steps // 4), 1)
+    def graphed(fn, K):
+        fn()                              # eager first: uploads the descriptors for these pointers
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            fn(None)
+        gr.replay()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(K):
+            gr.replay()
+        z.record(stream)
+        torch.cuda.synchronize()
+        del gr
+        return a.elapsed_time(z) / K
+
+    ms_b_eager = timed(batched, args.steps, args.warmup)
+    ms_p_eager = timed(plain, max(3, args.steps // 4), 1)
+    ms_b = graphed(batched, args.steps)
+    ms_p = graphed(plain, max(3, args.steps // 4))
+
+    # 20 CP-ALS sweeps of every tensor: batched sweeps captured once in a HIP
+    # graph and replayed, against plain per-tensor sweeps launched eagerly.
+    als_iters = 20
+    Fa = [[f.clone() for f in fs] for fs in F]
+    lam = [torch.zeros(R, dtype=torch.float64, device="cuda") for _ in ts]
+    fit = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in ts]
+    F0 = [[f.clone() for f in fs] for fs in F]
+
+    def reset():
+        for fs, f0 in zip(Fa, F0):
+            for f, g in zip(fs, f0):
+                f.copy_(g)
+        for i, h in enumerate(hs):
+            capi.cpd_als_init(h, Fa[i], R, stream=stream)
+
+    reset()
+    capi.cpd_als_batch_iter_async(b, Fa, lam, fit, stream=stream)   # uploads the descriptors for these pointers
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):   # captured on torch's capture stream (the current stream inside)
+        for _ in range(als_iters):
+            capi.cpd_als_batch_iter_async(b, Fa, lam, fit)
+    reset()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    z = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    g.replay()
+    z.record(stream)
+    torch.cuda.synchronize()
+    for h in hs:
+        capi.cpd_als_status(h, stream=stream)
+    ms_graph = a.elapsed_time(z)
+    fits_graph = [float(f.item()) for f in fit]
+    reset()
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(als_iters):
+        for i, h in enumerate(hs):
+            capi.cpd_als_iter_async(h, Fa[i], lam[i], R, fit[i], stream=stream)
+    z.record(stream)
+    torch.cuda.synchronize()
+    for h in hs:
+        capi.cpd_als_status(h, stream=stream)
+    ms_plain_als = a.elapsed_time(z)
+    same = all(float(f.item()) == fg for f, fg in zip(fit, fits_graph))
+    del g
+
     flops = sum(3 * R * t.nnz * 3 for t in ts)
     byts = sum(sum(algorithmic_bytes(t.dims, t.nnz, R)) for t in ts)
     res = {
@@ -176,10 +255,17 @@ def bench_batch(args, R=16, count=256):
         "config": {"workload": f"batch256-R16: {count} 3-mode tensors, dims U[100,5000], nnz log-U[1e3,1e6] "
                                f"(capped), uniform distinct, R={R}; one step = all modes of every tensor",
                    "total_nnz": total_nnz, "R": R},
+        "partition_size": tuned,
+        "timing": "one step = 3 modes; both methods replayed from a HIP graph of one step",
         "plain_ms_per_step": round(ms_p, 4),
         "batched_speedup_vs_plain": round(ms_p / ms_b, 3),
+        "eager_launch_ms_per_step": {"batched": round(ms_b_eager, 4), "plain": round(ms_p_eager, 4)},
         "gflops": round(flops / (ms_b / 1e3) / 1e9, 1),
         "hbm_pct_peak": round(100.0 * byts / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
+        "als_20_sweeps": {"batched_graph_ms": round(ms_graph, 3), "plain_eager_ms": round(ms_plain_als, 3),
+                          "speedup": round(ms_plain_als / ms_graph, 3),
+                          "tensor_sweeps_per_s": round(count * als_iters / (ms_graph / 1e3), 1),
+                          "fits_bitwise_equal": same},
         "build_s": round(build_s, 2),
     }
     b.free()

@@ -160,7 +160,6 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
  * A batch groups handles of tensors with the same N.  mttkrp_batch_run runs
  * the MTTKRP along one mode for every tensor of the batch with one
  * partition-kernel launch and one fix-up launch: a static list of (tensor,
- * partition) work items, sized so that every workgroup gets about the same
  * partition) work items, walked by a grid of resident workgroups.  Every
  * tensor keeps the partitioning mttkrp_run gives it, so each tensor's result
  * is bitwise the same as mttkrp_run on its handle, whatever else is in the
@@ -168,8 +167,9 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
 typedef struct mttkrp_batch* mttkrp_batch_handle;
 
 /* layouts: host array of `count` device handles (same N, each with max_R >= R).
- * The handles must outlive the batch.  opts may be NULL (parts_per_cu sizes
- * the work list).  Allocates the batch's descriptor tables and carry rows. */
+ * The handles must outlive the batch.  Each tensor is partitioned with its own
+ * handle's parts_per_cu; opts (may be NULL) is validated only.  Allocates the
+ * batch's descriptor tables and carry rows. */
 mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
                                   mttkrp_batch_handle* out);
 
@@ -192,6 +192,23 @@ mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* con
  *   fits:    host array of count device pointers (1 double each) or NULL */
 mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* factors, double* const* lambdas,
                                        double* const* fits, hipStream_t stream);
+
+/* Autotuner for the partition size of batched tensors (the paper sizes its
+ * partitions per SM, Sec. III-B; here the size is measured, not modelled):
+ * for each candidate parts_per_cu, set it on every layout, build the batch and
+ * time `reps` batched all-mode MTTKRP passes after one warm-up pass, with HIP
+ * events on `stream`.  The fastest candidate stays set on the layouts (so
+ * mttkrp_run, cpd_als_iter and later batches use it; results change by
+ * rounding only) and is returned.  Synchronises the stream.
+ *   candidates: n_candidates values in [1, 64]; NULL = {1, 2, 4, 8, 16}
+ *   factors:    host array of count * N device pointers, as mttkrp_batch_run
+ *   outs:       host array of count * N device pointers, tensor t's mode-n
+ *               output (I_n x R fp32, overwritten) at [t * N + n]
+ *   times_ms:   NULL or one float per candidate: time of one all-mode pass
+ *   best_ppc:   out: the chosen parts_per_cu */
+mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int R, const int* candidates,
+                                    int n_candidates, const float* const* factors, float* const* outs, int reps,
+                                    hipStream_t stream, int* best_ppc, float* times_ms);
 
 /* Release a batch (not its layouts).  NULL is ignored. */
 void mttkrp_batch_free(mttkrp_batch_handle b);

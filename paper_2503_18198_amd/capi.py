@@ -29,7 +29,7 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
             "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create", "mttkrp_batch_run",
             "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
-            "mttkrp_gather_probe"]
+            "mttkrp_gather_probe", "mttkrp_batch_autotune"]
 
 
 class MttkrpError(RuntimeError):
@@ -88,6 +88,9 @@ def _load():
     lib.mttkrp_batch_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.cpd_als_iter_async.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.c_int, vp, vp]
     lib.cpd_als_status.argtypes = [vp, vp]
+    lib.mttkrp_batch_autotune.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
     lib.mttkrp_gather_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     lib.cpd_als_batch_iter_async.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.mttkrp_batch_free.argtypes = [vp]
@@ -360,6 +363,33 @@ def mttkrp_batch_create(layouts, R: int, opts=None) -> Batch:
     _check(_lib.mttkrp_batch_create(arr, len(layouts), int(R), ctypes.byref(o) if o is not None else None,
                                     ctypes.byref(b)))
     return Batch(b.value, layouts, R)
+
+
+def mttkrp_batch_autotune(layouts, R: int, factors, outs, candidates=None, reps: int = 3, stream=None):
+    """Time the batched all-mode MTTKRP for each candidate parts_per_cu, leave
+    the fastest set on the layouts and return ``(best, {candidate: ms})``.
+    factors: per tensor, N fp32 device tensors; outs: per tensor, N outputs
+    (tensor t's mode-n output of shape (I_n, R))."""
+    count = len(layouts)
+    N = len(layouts[0].dims)
+    if len(factors) != count or len(outs) != count:
+        raise MttkrpError(MTTKRP_EINVAL, "need factors and outputs for every tensor")
+    for t, h in enumerate(layouts):
+        if len(factors[t]) != N or len(outs[t]) != N:
+            raise MttkrpError(MTTKRP_EINVAL, f"tensor {t}: need N factors and N outputs")
+        for m in range(N):
+            _check_factor(factors[t][m], h.dims[m], R, "fp32", f"tensor {t} factor {m}")
+            _check_factor(outs[t][m], h.dims[m], R, "fp32", f"tensor {t} output {m}")
+    arr = (ctypes.c_void_p * count)(*[h.ptr for h in layouts])
+    fac = (ctypes.c_void_p * (count * N))(*[int(f.data_ptr()) for fs in factors for f in fs])
+    out = (ctypes.c_void_p * (count * N))(*[int(o.data_ptr()) for os_ in outs for o in os_])
+    cands = list(candidates) if candidates is not None else [1, 2, 4, 8, 16]
+    carr = (ctypes.c_int * len(cands))(*cands)
+    times = (ctypes.c_float * len(cands))()
+    best = ctypes.c_int()
+    _check(_lib.mttkrp_batch_autotune(arr, count, int(R), carr, len(cands), fac, out, int(reps),
+                                      ctypes.c_void_p(_stream(stream)), ctypes.byref(best), times))
+    return int(best.value), {c: float(times[i]) for i, c in enumerate(cands)}
 
 
 def mttkrp_batch_run(b: Batch, mode: int, factors, outs, stream=None):

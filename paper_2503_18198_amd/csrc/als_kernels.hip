@@ -112,17 +112,29 @@ __global__ __launch_bounds__(kWG) void hadamard_kernel(const double* __restrict_
 // beyond rounding (relative to V_kk) means V is not SPD to working precision:
 // then *flag = 1 and W is filled with NaN.  Each sweep updates all R^2
 // entries in parallel (read, barrier, write, barrier).
+//
+// One workgroup per job: job b first forms its V = Hadamard product of the
+// Gram matrices of every mode but `skip` (kept in LDS and stored to V), then
+// inverts it into W.  One launch serves one tensor or every tensor of a batch.
 template <int R>
-__global__ __launch_bounds__(kWG) void spd_inverse_kernel(const double* __restrict__ V, double* __restrict__ W,
-                                                          double* flag)
+__global__ __launch_bounds__(kWG) void normal_eq_inverse_kernel(const InvJob* __restrict__ jobs, int N, int skip,
+                                                                int reset_flag)
 {
     constexpr int RR = R * R;
     constexpr int kPer = (RR + kWG - 1) / kWG;   // entries per thread
     __shared__ double A[RR];
     __shared__ double diag0[R];
+    const InvJob jb = jobs[blockIdx.x];
     const int tid = threadIdx.x;
-    for (int e = tid; e < RR; e += kWG) A[e] = V[e];
-    if (tid < R) diag0[tid] = V[tid * R + tid];
+    for (int e = tid; e < RR; e += kWG) {
+        double v = 1.0;
+        for (int m = 0; m < N; ++m)
+            if (m != skip) v *= jb.grams[(uint64_t)m * RR + e];
+        A[e] = v;
+        jb.V[e] = v;
+    }
+    __syncthreads();
+    if (tid < R) diag0[tid] = A[tid * R + tid];
     __syncthreads();
     bool bad = false;   // every thread tests the same pivots, so this is uniform
     for (int k = 0; k < R; ++k) {
@@ -156,8 +168,11 @@ __global__ __launch_bounds__(kWG) void spd_inverse_kernel(const double* __restri
         }
         __syncthreads();
     }
-    for (int e = tid; e < RR; e += kWG) W[e] = bad ? __longlong_as_double(0x7ff8000000000000ll) : -A[e];
-    if (tid == 0 && bad) *flag = 1.0;
+    for (int e = tid; e < RR; e += kWG) jb.W[e] = bad ? __longlong_as_double(0x7ff8000000000000ll) : -A[e];
+    if (tid == 0) {
+        if (reset_flag) *jb.flag = 0.0;
+        if (bad) *jb.flag = 1.0;
+    }
 }
 
 // Rows of M W (FP64).  Thread (ri of 32, column group cg of 8) computes the
@@ -340,12 +355,13 @@ hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, 
     return hipGetLastError();
 }
 
-hipError_t als_spd_inverse(const double* V, int R, double* W, double* flag, hipStream_t s)
+hipError_t als_normal_eq_inverse(const InvJob* jobs, int count, int N, int skip, int R, int reset_flag, hipStream_t s)
 {
+    if (count <= 0) return hipSuccess;
     switch (R) {
-        case 16: hipLaunchKernelGGL(spd_inverse_kernel<16>, dim3(1), dim3(kWG), 0, s, V, W, flag); break;
-        case 32: hipLaunchKernelGGL(spd_inverse_kernel<32>, dim3(1), dim3(kWG), 0, s, V, W, flag); break;
-        case 64: hipLaunchKernelGGL(spd_inverse_kernel<64>, dim3(1), dim3(kWG), 0, s, V, W, flag); break;
+        case 16: hipLaunchKernelGGL(normal_eq_inverse_kernel<16>, dim3(count), dim3(kWG), 0, s, jobs, N, skip, reset_flag); break;
+        case 32: hipLaunchKernelGGL(normal_eq_inverse_kernel<32>, dim3(count), dim3(kWG), 0, s, jobs, N, skip, reset_flag); break;
+        case 64: hipLaunchKernelGGL(normal_eq_inverse_kernel<64>, dim3(count), dim3(kWG), 0, s, jobs, N, skip, reset_flag); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -42,7 +42,7 @@ int host_threads()
 bool r_supported(int R) { return R == 16 || R == 32 || R == 64; }
 
 struct Workspace {
-    uint64_t carry = 0, grams = 0, V = 0, W = 0, part = 0, colsq = 0, lam = 0, scal = 0, M = 0, bf16 = 0;
+    uint64_t carry = 0, grams = 0, V = 0, W = 0, part = 0, colsq = 0, lam = 0, scal = 0, job = 0, M = 0, bf16 = 0;
     uint64_t total = 0;
 };
 
@@ -63,9 +63,10 @@ Workspace plan_workspace(const uint32_t* dims, int N, int maxR, int dtype)
     w.colsq = align_up(R * 8ull);
     w.lam = align_up(R * 8ull);
     w.scal = align_up(8 * 8ull);
+    w.job = align_up(sizeof(mk::InvJob));
     w.M = align_up(maxI * R * 4ull);
     w.bf16 = dtype == MTTKRP_BF16 ? (uint64_t)N * kAlign + sumI * R * 2ull : 0;
-    w.total = w.carry + w.grams + w.V + w.W + w.part + w.colsq + w.lam + w.scal + w.M + align_up(w.bf16);
+    w.total = w.carry + w.grams + w.V + w.W + w.part + w.colsq + w.lam + w.scal + w.job + w.M + align_up(w.bf16);
     return w;
 }
 
@@ -121,6 +122,7 @@ struct mttkrp_layout {
     uint64_t dbytes = 0;
     float* carry = nullptr;
     mk::AlsWork als;
+    mk::InvJob inv_job_host{};                         // host source of als.job (kept alive for the copy)
     double normX2 = 0.0;
     int als_R = 0;
 };
@@ -261,6 +263,10 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     h->als.colsq = static_cast<double*>(take(ws.colsq));
     h->als.lam = static_cast<double*>(take(ws.lam));
     h->als.scal = static_cast<double*>(take(ws.scal));
+    h->als.job = static_cast<mk::InvJob*>(take(ws.job));
+    h->inv_job_host = mk::InvJob{h->als.grams, h->als.V, h->als.W, h->als.scal + 1};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->als.job, &h->inv_job_host, sizeof(mk::InvJob), hipMemcpyHostToDevice, stream);
     h->als.M = static_cast<float*>(take(ws.M));
     h->als.max_blocks = kAlsBlocks;
     if (o.factor_dtype == MTTKRP_BF16)
@@ -507,13 +513,11 @@ static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* l
     const int N = h->N;
     const bool bf16 = h->opts.factor_dtype == MTTKRP_BF16;
     const int dtype = bf16 ? MTTKRP_BF16 : MTTKRP_FP32;
-    double* flag = w.scal + 1;
     hipError_t e = hipSuccess;
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         const uint32_t I = h->dims[n];
         const uint64_t RR = (uint64_t)R * R;
-        e = mk::als_hadamard(w.grams, N, n, R, w.V, flag, reset_flag && n == 0, stream);
-        if (e == hipSuccess) e = mk::als_spd_inverse(w.V, R, w.W, flag, stream);
+        e = mk::als_normal_eq_inverse(w.job, 1, N, n, R, reset_flag && n == 0, stream);
         if (e == hipSuccess) {
             const void* fac[MTTKRP_MAX_MODES];
             for (int m = 0; m < N; ++m)
@@ -591,6 +595,7 @@ struct mttkrp_batch {
     uint32_t nfix_work[MTTKRP_MAX_MODES] = {};
     uint32_t grid_part = 0, grid_fix = 0;
     std::vector<const void*> last_ptrs[MTTKRP_MAX_MODES]; // pointers of the uploaded descriptors
+    mk::InvJob* inv_jobs = nullptr;                       // device: every tensor's normal-equation inverse job
 };
 
 extern "C" {
@@ -667,7 +672,7 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
         b->carry_off[t] = carry_floats;
         carry_floats += (uint64_t)std::max<uint32_t>(max_parts[t], 1) * 2ull * (uint64_t)R;
     }
-    uint64_t need = align_up(carry_floats * 4);
+    uint64_t need = align_up(carry_floats * 4) + align_up((uint64_t)count * sizeof(mk::InvJob));
     for (int n = 0; n < N; ++n)
         need += align_up((uint64_t)count * pdb) + align_up((uint64_t)count * fdb) + align_up(pw[n].size() * 8 + 8) +
                 align_up(fw[n].size() * 8 + 8);
@@ -686,6 +691,12 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
         return p;
     };
     b->carry = reinterpret_cast<float*>(take(carry_floats * 4));
+    b->inv_jobs = reinterpret_cast<mk::InvJob*>(take((uint64_t)count * sizeof(mk::InvJob)));
+    {
+        std::vector<mk::InvJob> jobs(count);
+        for (int t = 0; t < count; ++t) jobs[t] = b->hs[t]->inv_job_host;
+        e = hipMemcpy(b->inv_jobs, jobs.data(), jobs.size() * sizeof(mk::InvJob), hipMemcpyHostToDevice);
+    }
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         b->part_desc[n] = take((uint64_t)count * pdb);
         b->fix_desc[n] = take((uint64_t)count * fdb);
@@ -762,6 +773,80 @@ mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* con
     return MTTKRP_OK;
 }
 
+mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int R, const int* candidates,
+                                    int n_candidates, const float* const* factors, float* const* outs, int reps,
+                                    hipStream_t stream, int* best_ppc, float* times_ms)
+{
+    g_err.clear();
+    static const int kDefault[] = {1, 2, 4, 8, 16};
+    if (!best_ppc) return fail(MTTKRP_EINVAL, "NULL best_ppc");
+    if (!layouts || count <= 0 || !factors || !outs) return fail(MTTKRP_EINVAL, "NULL layouts, factors or outs");
+    if (!candidates) {
+        candidates = kDefault;
+        n_candidates = 5;
+    }
+    if (n_candidates <= 0) return fail(MTTKRP_EINVAL, "need at least one candidate");
+    for (int i = 0; i < n_candidates; ++i)
+        if (candidates[i] < 1 || candidates[i] > 64) return fail(MTTKRP_EINVAL, "candidates must be in [1, 64]");
+    if (reps < 1) return fail(MTTKRP_EINVAL, "reps must be >= 1");
+    for (int t = 0; t < count; ++t)
+        if (!layouts[t]) return fail(MTTKRP_EINVAL, "layout " + std::to_string(t) + " is NULL");
+    const int N = layouts[0]->N;
+    std::vector<int> old(count);
+    for (int t = 0; t < count; ++t) old[t] = layouts[t]->opts.parts_per_cu;
+    auto restore = [&]() {
+        for (int t = 0; t < count; ++t) layouts[t]->opts.parts_per_cu = old[t];
+    };
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) {
+        restore();
+        return hip_fail(e, "autotune events");
+    }
+    std::vector<float*> mode_outs(count);
+    int best = -1;
+    float best_ms = 0.0f;
+    mttkrp_status st = MTTKRP_OK;
+    for (int i = 0; i < n_candidates && st == MTTKRP_OK; ++i) {
+        for (int t = 0; t < count; ++t) layouts[t]->opts.parts_per_cu = candidates[i];
+        mttkrp_batch_handle b = nullptr;
+        st = mttkrp_batch_create(layouts, count, R, nullptr, &b);
+        if (st) break;
+        float ms = 0.0f;
+        for (int pass = 0; pass <= reps && st == MTTKRP_OK; ++pass) {
+            if (pass == 1) e = hipEventRecord(ev[0], stream);
+            for (int n = 0; n < N && st == MTTKRP_OK; ++n) {
+                for (int t = 0; t < count; ++t) mode_outs[t] = outs[(size_t)t * N + n];
+                st = mttkrp_batch_run(b, n, factors, mode_outs.data(), stream);
+            }
+        }
+        if (st == MTTKRP_OK) {
+            e = hipEventRecord(ev[1], stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+        }
+        mttkrp_batch_free(b);
+        if (st) break;
+        ms /= (float)reps;
+        if (times_ms) times_ms[i] = ms;
+        if (best < 0 || ms < best_ms) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (st) {
+        restore();
+        return st;
+    }
+    for (int t = 0; t < count; ++t) layouts[t]->opts.parts_per_cu = candidates[best];
+    *best_ppc = candidates[best];
+    return MTTKRP_OK;
+}
+
 
 mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* factors, double* const* lambdas,
                                        double* const* fits, hipStream_t stream)
@@ -783,11 +868,7 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
     for (int t = 0; t < C; ++t) outs[t] = b->hs[t]->als.M;
     hipError_t e = hipSuccess;
     for (int n = 0; n < N && e == hipSuccess; ++n) {
-        for (int t = 0; t < C && e == hipSuccess; ++t) {
-            mk::AlsWork& w = b->hs[t]->als;
-            e = mk::als_hadamard(w.grams, N, n, R, w.V, w.scal + 1, 0, stream);
-            if (e == hipSuccess) e = mk::als_spd_inverse(w.V, R, w.W, w.scal + 1, stream);
-        }
+        e = mk::als_normal_eq_inverse(b->inv_jobs, C, N, n, R, 0, stream);
         if (e != hipSuccess) break;
         mttkrp_status st = mttkrp_batch_run(b, n, factors, outs.data(), stream);
         if (st) return st;

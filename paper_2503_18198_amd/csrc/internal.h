@@ -67,6 +67,16 @@ hipError_t launch_batch_part(int n_in, int R, int dtype, const void* descs, cons
 hipError_t launch_batch_fixup(const void* descs, const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s);
 
 // CP-ALS helpers (als_kernels.hip).  All FP64 unless noted.
+// One normal-equation inverse per job: V = Hadamard product of the Gram
+// matrices of every mode but `skip`, W = V^{-1}; *flag = 1 if V is not SPD
+// (cleared first when reset_flag).  jobs: device array of `count` entries.
+struct InvJob {
+    const double* grams;   // N x R x R
+    double* V;             // R x R
+    double* W;             // R x R
+    double* flag;          // 1 double
+};
+
 struct AlsWork {
     double* grams = nullptr;     // N x R x R
     double* V = nullptr;         // R x R
@@ -77,13 +87,14 @@ struct AlsWork {
     double* scal = nullptr;      // small scalars: [0] fit, [1] not-positive-definite flag
     float* M = nullptr;          // max_I x R fp32 (MTTKRP output)
     uint16_t* bf16[MTTKRP_MAX_MODES] = {};  // bf16 copies of the factors (optional)
+    InvJob* job = nullptr;       // device copy of {grams, V, W, scal + 1} for the inverse kernel
     int max_blocks = 0;
 };
 
 hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w, hipStream_t s);
 hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, double* flag, int reset_flag,
                         hipStream_t s);
-hipError_t als_spd_inverse(const double* V, int R, double* W, double* flag, hipStream_t s);
+hipError_t als_normal_eq_inverse(const InvJob* jobs, int count, int N, int skip, int R, int reset_flag, hipStream_t s);
 hipError_t als_solve_normalize(const float* M, const double* W, uint32_t I, int R, float* A, double* lam,
                                AlsWork& w, hipStream_t s);
 hipError_t als_fit(const float* M, const float* A, uint32_t I, const double* lam, const double* grams, int N, int R,

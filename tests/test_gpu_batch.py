@@ -113,3 +113,30 @@ def test_batched_als_sweeps_equal_single():
         assert fits_b[i] == fit_s[i].item()
         assert torch.equal(lam_b[i], lam_s[i])
     b.free()
+
+
+def test_autotune_picks_a_candidate_and_keeps_results():
+    """The autotuner returns one of its candidates, leaves it set on the
+    layouts, and the batch built afterwards still matches the oracle and the
+    single-tensor runs bit for bit."""
+    print("case batch autotune", flush=True)
+    R = 16
+    ts, hs, F, dF = make_batch(count=10, seed=11, R=R)
+    outs = [[torch.empty((d, R), device="cuda") for d in t.dims] for t in ts]
+    best, times = capi.mttkrp_batch_autotune(hs, R, dF, outs, candidates=[1, 4, 16], reps=2)
+    assert best in (1, 4, 16) and set(times) == {1, 4, 16} and all(v > 0 for v in times.values())
+    assert all(capi.mttkrp_layout_info(h)["parts_per_cu"] == best for h in hs)
+    b = capi.mttkrp_batch_create(hs, R)
+    for n in range(3):
+        o = [torch.empty((t.dims[n], R), device="cuda") for t in ts]
+        capi.mttkrp_batch_run(b, n, dF, o)
+        torch.cuda.synchronize()
+        for i, t in enumerate(ts):
+            got = o[i].cpu().numpy()
+            assert gu.rel_fro(got, gu.oracle_mttkrp(t.idx, t.val, t.dims, F[i], n)) <= TOL
+            assert np.array_equal(got.view(np.uint32), gu.gpu_mttkrp(hs[i], n, dF[i], R).view(np.uint32))
+    b.free()
+    with pytest.raises(capi.MttkrpError):
+        capi.mttkrp_batch_autotune(hs, R, dF, outs, candidates=[0])
+    for h in hs:
+        h.free()

@@ -18,20 +18,40 @@ namespace {
 
 constexpr int kRowsTile = 16;   // rows staged in LDS per step of the row passes
 
-// Block b of `nblk` covers rows [b * rpb, min((b+1) * rpb, I)).
-__device__ __forceinline__ void block_rows(uint32_t I, uint32_t rpb, uint32_t& r0, uint32_t& r1)
+// Block b of a job covers rows [b * rpb, min((b+1) * rpb, I)).
+__device__ __forceinline__ void block_rows(uint32_t I, uint32_t rpb, uint32_t b, uint32_t& r0, uint32_t& r1)
 {
-    r0 = min((uint64_t)blockIdx.x * rpb, (uint64_t)I);
+    r0 = min((uint64_t)b * rpb, (uint64_t)I);
     r1 = min((uint64_t)r0 + rpb, (uint64_t)I);
+}
+
+// The (job, block) a workgroup of a row pass works on: with a job table,
+// work[blockIdx.x] names both; without one, the single job passed by value
+// and block blockIdx.x.
+__device__ __forceinline__ const DenseJob& pick_job(const DenseJob& single, const DenseJob* jobs, const uint2* work,
+                                                    uint32_t& blk)
+{
+    if (!jobs) {
+        blk = blockIdx.x;
+        return single;
+    }
+    const uint2 w = work[blockIdx.x];
+    blk = w.y;
+    return jobs[w.x];
 }
 
 // part[b][r*R + c] = sum over the block's rows i of A[i][r] * A[i][c].
 // Thread (bi, bj) of a 16 x 16 grid owns the B x B entry block (B = R/16)
 // with rows bi*B.. and columns bj*B..; rows are staged 16 at a time in LDS.
 template <int R>
-__global__ __launch_bounds__(kWG) void gram_partial_kernel(const float* __restrict__ A, uint32_t I, uint32_t rpb,
-                                                           double* __restrict__ part)
+__global__ __launch_bounds__(kWG) void gram_partial_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
+                                                           const uint2* __restrict__ work)
 {
+    uint32_t blk;
+    const DenseJob& jb = pick_job(single, jobs, work, blk);
+    const float* __restrict__ A = jb.A;
+    const uint32_t I = jb.I;
+    double* __restrict__ part = jb.part;
     constexpr int B = R / 16;
     __shared__ double tile[kRowsTile * R];
     const int tid = threadIdx.x;
@@ -42,7 +62,7 @@ __global__ __launch_bounds__(kWG) void gram_partial_kernel(const float* __restri
 #pragma unroll
         for (int j = 0; j < B; ++j) acc[i][j] = 0.0;
     uint32_t r0, r1;
-    block_rows(I, rpb, r0, r1);
+    block_rows(I, jb.rpb, blk, r0, r1);
     for (uint32_t i0 = r0; i0 < r1; i0 += kRowsTile) {
         const uint32_t nrow = min((uint32_t)kRowsTile, r1 - i0);
         __syncthreads();
@@ -66,25 +86,32 @@ __global__ __launch_bounds__(kWG) void gram_partial_kernel(const float* __restri
 #pragma unroll
     for (int i = 0; i < B; ++i)
 #pragma unroll
-        for (int j = 0; j < B; ++j) part[(uint64_t)blockIdx.x * R * R + (bi * B + i) * R + bj * B + j] = acc[i][j];
+        for (int j = 0; j < B; ++j) part[(uint64_t)blk * R * R + (bi * B + i) * R + bj * B + j] = acc[i][j];
 }
 
 // out[e] = sum over blocks b of part[b * K + e], one wave per entry: lane j
 // adds blocks j, j+64, ... in order, then a fixed butterfly adds the 64 lane
-// sums.  op 1: out[e] = sqrt(sum), with 1 in place of 0 (column norms).
-__global__ __launch_bounds__(kWG) void reduce_partials_kernel(const double* __restrict__ part, int nblk, int K,
-                                                              double* __restrict__ out, int op)
+// sums.  Workgroup g serves job g / per_job (per_job = ceil(K / 4)); `which`
+// picks the job's output: 0 lam (op: sqrt, 1 in place of 0 -> column norms),
+// 1 the Gram matrix G_out, 2 colsq.
+__global__ __launch_bounds__(kWG) void reduce_partials_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
+                                                              int K, int which)
 {
-    const int e = blockIdx.x * (kWG / 64) + threadIdx.x / 64;
+    const int per_job = (K + kWG / 64 - 1) / (kWG / 64);
+    const DenseJob& jb = jobs ? jobs[blockIdx.x / per_job] : single;
+    const int e = (blockIdx.x % per_job) * (kWG / 64) + threadIdx.x / 64;
     const int lane = threadIdx.x & 63;
     if (e >= K) return;
+    const double* __restrict__ part = jb.part;
+    const int nblk = (int)jb.nb;
     double s = 0.0;
     for (int b = lane; b < nblk; b += 64) s += part[(uint64_t)b * K + e];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) {
-        if (op == 1) s = s > 0.0 ? sqrt(s) : 1.0;
-        out[e] = s;
+        if (which == 0) jb.lam[e] = s > 0.0 ? sqrt(s) : 1.0;
+        else if (which == 1) jb.G_out[e] = s;
+        else jb.colsq[e] = s;
     }
 }
 
@@ -182,10 +209,17 @@ __global__ __launch_bounds__(kWG) void normal_eq_inverse_kernel(const InvJob* __
 // different banks.  op 0: per-block column sums of squares -> part[b][c].
 // op 1: A[i][c] = (M W)[i][c] / lam[c], stored as fp32.
 template <int R>
-__global__ __launch_bounds__(kWG) void mw_kernel(const float* __restrict__ M, const double* __restrict__ W, uint32_t I,
-                                                 uint32_t rpb, int op, const double* __restrict__ lam,
-                                                 float* __restrict__ A, double* __restrict__ part)
+__global__ __launch_bounds__(kWG) void mw_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
+                                                 const uint2* __restrict__ work, int op)
 {
+    uint32_t blk;
+    const DenseJob& jb = pick_job(single, jobs, work, blk);
+    const float* __restrict__ M = jb.M;
+    const double* __restrict__ W = jb.W;
+    const uint32_t I = jb.I;
+    const double* __restrict__ lam = jb.lam;
+    float* __restrict__ A = jb.A;
+    double* __restrict__ part = jb.part;
     constexpr int B = R / 8;
     constexpr int RB = R == 64 ? 1 : 4;        // rows per thread (LDS: 64 KB static limit)
     constexpr int kRows = (kWG / 8) * RB;
@@ -205,7 +239,7 @@ __global__ __launch_bounds__(kWG) void mw_kernel(const float* __restrict__ M, co
         colsq[j] = 0.0;
     }
     uint32_t r0, r1;
-    block_rows(I, rpb, r0, r1);
+    block_rows(I, jb.rpb, blk, r0, r1);
     for (uint32_t i0 = r0; i0 < r1; i0 += kRows) {
         const uint32_t nrow = min((uint32_t)kRows, r1 - i0);
         __syncthreads();
@@ -253,15 +287,21 @@ __global__ __launch_bounds__(kWG) void mw_kernel(const float* __restrict__ M, co
         if (tid < R) {
             double t = 0.0;
             for (int r = 0; r < 32; ++r) t += sred[tid * 32 + r];
-            part[(uint64_t)blockIdx.x * R + tid] = t;
+            part[(uint64_t)blk * R + tid] = t;
         }
     }
 }
 
 // part[b][c] = sum over the block's rows of M[i][c] * A[i][c].
-__global__ __launch_bounds__(kWG) void coldot_kernel(const float* __restrict__ M, const float* __restrict__ A,
-                                                     uint32_t I, int R, uint32_t rpb, double* __restrict__ part)
+__global__ __launch_bounds__(kWG) void coldot_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
+                                                     const uint2* __restrict__ work, int R)
 {
+    uint32_t blk;
+    const DenseJob& jb = pick_job(single, jobs, work, blk);
+    const float* __restrict__ M = jb.M;
+    const float* __restrict__ A = jb.A;
+    const uint32_t I = jb.I;
+    double* __restrict__ part = jb.part;
     __shared__ double sred[kWG];
     const int tid = threadIdx.x;
     const int rows_per_pass = kWG / R;
@@ -269,7 +309,7 @@ __global__ __launch_bounds__(kWG) void coldot_kernel(const float* __restrict__ M
     const int ri = tid / R;
     double s = 0.0;
     uint32_t r0, r1;
-    block_rows(I, rpb, r0, r1);
+    block_rows(I, jb.rpb, blk, r0, r1);
     for (uint32_t i = r0 + ri; i < r1; i += rows_per_pass)
         s += (double)M[(uint64_t)i * R + c] * (double)A[(uint64_t)i * R + c];
     sred[tid] = s;
@@ -277,15 +317,21 @@ __global__ __launch_bounds__(kWG) void coldot_kernel(const float* __restrict__ M
     if (tid < R) {
         double t = 0.0;
         for (int j = 0; j < rows_per_pass; ++j) t += sred[j * R + tid];
-        part[(uint64_t)blockIdx.x * R + tid] = t;
+        part[(uint64_t)blk * R + tid] = t;
     }
 }
 
 // fit = 1 - sqrt(max(0, |X|^2 + lam^T (*G) lam - 2 sum_r lam_r dot_r)) / |X|.
-__global__ __launch_bounds__(kWG) void fit_kernel(const double* __restrict__ dot, const double* __restrict__ lam,
-                                                  const double* __restrict__ grams, int N, int R, double normX2,
-                                                  double* fit_out, double* lam_out)
+__global__ __launch_bounds__(kWG) void fit_kernel(DenseJob single, const DenseJob* __restrict__ jobs, int R)
 {
+    const DenseJob& jb = jobs ? jobs[blockIdx.x] : single;
+    const double* __restrict__ dot = jb.colsq;
+    const double* __restrict__ lam = jb.lam;
+    const double* __restrict__ grams = jb.grams;
+    const int N = jb.N;
+    const double normX2 = jb.normX2;
+    double* fit_out = jb.fit_out;
+    double* lam_out = jb.lam_out;
     __shared__ double sx[kWG];
     __shared__ double sd[kWG];
     const int tid = threadIdx.x;
@@ -333,21 +379,6 @@ uint32_t nblocks_for(uint32_t I, int max_blocks, uint32_t& rpb)
 
 }  // namespace
 
-hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w, hipStream_t s)
-{
-    uint32_t rpb;
-    const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
-    switch (R) {
-        case 16: hipLaunchKernelGGL(gram_partial_kernel<16>, dim3(nb), dim3(kWG), 0, s, A, I, rpb, w.part); break;
-        case 32: hipLaunchKernelGGL(gram_partial_kernel<32>, dim3(nb), dim3(kWG), 0, s, A, I, rpb, w.part); break;
-        case 64: hipLaunchKernelGGL(gram_partial_kernel<64>, dim3(nb), dim3(kWG), 0, s, A, I, rpb, w.part); break;
-        default: return hipErrorInvalidValue;
-    }
-    const int K = R * R;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((K + 3) / 4), dim3(kWG), 0, s, w.part, (int)nb, K, G_out, 0);
-    return hipGetLastError();
-}
-
 hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, double* flag, int reset_flag,
                         hipStream_t s)
 {
@@ -367,39 +398,95 @@ hipError_t als_normal_eq_inverse(const InvJob* jobs, int count, int N, int skip,
     return hipGetLastError();
 }
 
-hipError_t als_solve_normalize(const float* M, const double* W, uint32_t I, int R, float* A, double* lam,
-                               AlsWork& w, hipStream_t s)
+void plan_dense_blocks(uint32_t I, int max_blocks, DenseJob& j)
 {
-    uint32_t rpb;
-    const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
-    auto pass = [&](int op) {
-        const double* lp = op == 1 ? lam : nullptr;
-        float* Ap = op == 1 ? A : nullptr;
-        double* pp = op == 0 ? w.part : nullptr;
+    j.I = I;
+    j.nb = nblocks_for(I, max_blocks, j.rpb);
+}
+
+// Each entry point runs either one job (passed by value, grid = its blocks)
+// or a job table with a (job, block) work list of `nwork` items.
+namespace {
+struct Launch {
+    const DenseJob& single;
+    const DenseJob* jobs;
+    const uint2* work;
+    uint32_t nwork;   // row-pass workgroups
+    int count;        // jobs
+    uint32_t grid() const { return jobs ? nwork : single.nb; }
+};
+
+template <int R>
+void launch_mw(const Launch& L, int op, hipStream_t s)
+{
+    hipLaunchKernelGGL(mw_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work, op);
+}
+
+template <int R>
+void launch_gram(const Launch& L, hipStream_t s)
+{
+    hipLaunchKernelGGL(gram_partial_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work);
+}
+
+void launch_reduce(const Launch& L, int K, int which, hipStream_t s)
+{
+    const int per_job = (K + kWG / 64 - 1) / (kWG / 64);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(per_job * (L.jobs ? L.count : 1))), dim3(kWG), 0, s,
+                       L.single, L.jobs, K, which);
+}
+}  // namespace
+
+hipError_t als_solve_normalize_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork,
+                                    int count, int R, hipStream_t s)
+{
+    const Launch L{single, jobs, work, nwork, count};
+    if (L.grid() == 0) return hipSuccess;
+    for (int op = 0; op < 2; ++op) {
         switch (R) {
-            case 16: hipLaunchKernelGGL(mw_kernel<16>, dim3(nb), dim3(kWG), 0, s, M, W, I, rpb, op, lp, Ap, pp); break;
-            case 32: hipLaunchKernelGGL(mw_kernel<32>, dim3(nb), dim3(kWG), 0, s, M, W, I, rpb, op, lp, Ap, pp); break;
-            case 64: hipLaunchKernelGGL(mw_kernel<64>, dim3(nb), dim3(kWG), 0, s, M, W, I, rpb, op, lp, Ap, pp); break;
-            default: break;
+            case 16: launch_mw<16>(L, op, s); break;
+            case 32: launch_mw<32>(L, op, s); break;
+            case 64: launch_mw<64>(L, op, s); break;
+            default: return hipErrorInvalidValue;
         }
-    };
-    if (R != 16 && R != 32 && R != 64) return hipErrorInvalidValue;
-    pass(0);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((R + 3) / 4), dim3(kWG), 0, s, w.part, (int)nb, R, lam, 1);
-    pass(1);
+        if (op == 0) launch_reduce(L, R, 0, s);
+    }
     return hipGetLastError();
 }
 
-hipError_t als_fit(const float* M, const float* A, uint32_t I, const double* lam, const double* grams, int N, int R,
-                   double normX2, double* fit_out, double* lam_out, AlsWork& w, hipStream_t s)
+hipError_t als_gram_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
+                         int R, hipStream_t s)
 {
-    uint32_t rpb;
-    const uint32_t nb = nblocks_for(I, w.max_blocks, rpb);
-    hipLaunchKernelGGL(coldot_kernel, dim3(nb), dim3(kWG), 0, s, M, A, I, R, rpb, w.part);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((R + 3) / 4), dim3(kWG), 0, s, w.part, (int)nb, R, w.colsq, 0);
-    hipLaunchKernelGGL(fit_kernel, dim3(1), dim3(kWG), 0, s, (const double*)w.colsq, lam, grams, N, R, normX2,
-                       fit_out, lam_out);
+    const Launch L{single, jobs, work, nwork, count};
+    if (L.grid() == 0) return hipSuccess;
+    switch (R) {
+        case 16: launch_gram<16>(L, s); break;
+        case 32: launch_gram<32>(L, s); break;
+        case 64: launch_gram<64>(L, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    launch_reduce(L, R * R, 1, s);
     return hipGetLastError();
+}
+
+hipError_t als_fit_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
+                        int R, hipStream_t s)
+{
+    const Launch L{single, jobs, work, nwork, count};
+    if (L.grid() == 0) return hipSuccess;
+    hipLaunchKernelGGL(coldot_kernel, dim3(L.grid()), dim3(kWG), 0, s, single, jobs, work, R);
+    launch_reduce(L, R, 2, s);
+    hipLaunchKernelGGL(fit_kernel, dim3((uint32_t)(jobs ? count : 1)), dim3(kWG), 0, s, single, jobs, R);
+    return hipGetLastError();
+}
+
+hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w, hipStream_t s)
+{
+    DenseJob j{};
+    j.A = const_cast<float*>(A);
+    j.part = w.part;
+    j.G_out = G_out;
+    plan_dense_blocks(I, w.max_blocks, j);
+    return als_gram_jobs(j, nullptr, nullptr, 0, 1, R, s);
 }
 
 hipError_t cast_bf16(const float* A, uint64_t n, uint16_t* out, hipStream_t s)

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <string>
 #include <thread>
+#include <cstring>
 #include <vector>
 
 #include "internal.h"
@@ -502,6 +503,36 @@ mttkrp_status cpd_als_init(mttkrp_handle h, const float* const* factors, int R, 
 
 // One sweep, enqueued only (no host synchronisation; capturable).  The
 // not-positive-definite flag is cleared at the start when reset_flag is set.
+// Row-pass job of the mode-n update of handle h (A = the new factor n).
+static mk::DenseJob dense_job(mttkrp_handle h, float* A, int n, int R)
+{
+    mk::DenseJob j{};
+    mk::AlsWork& w = h->als;
+    j.M = w.M;
+    j.W = w.W;
+    j.A = A;
+    j.lam = w.lam;
+    j.part = w.part;
+    j.G_out = w.grams + (uint64_t)n * R * R;
+    j.N = h->N;
+    mk::plan_dense_blocks(h->dims[n], w.max_blocks, j);
+    return j;
+}
+
+// Fit job of handle h after the last mode's update (A = the new last factor).
+static mk::DenseJob fit_job(mttkrp_handle h, float* A, int R, double* fit_out, double* lam_out)
+{
+    mk::DenseJob j = dense_job(h, A, h->N - 1, R);
+    mk::AlsWork& w = h->als;
+    j.G_out = nullptr;
+    j.colsq = w.colsq;
+    j.grams = w.grams;
+    j.fit_out = fit_out;
+    j.lam_out = lam_out;
+    j.normX2 = h->normX2;
+    return j;
+}
+
 static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
                                hipStream_t stream, bool reset_flag)
 {
@@ -516,7 +547,6 @@ static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* l
     hipError_t e = hipSuccess;
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         const uint32_t I = h->dims[n];
-        const uint64_t RR = (uint64_t)R * R;
         e = mk::als_normal_eq_inverse(w.job, 1, N, n, R, reset_flag && n == 0, stream);
         if (e == hipSuccess) {
             const void* fac[MTTKRP_MAX_MODES];
@@ -525,13 +555,15 @@ static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* l
             mttkrp_status st = run_mode(h, n, fac, dtype, w.M, R, stream);
             if (st) return st;
         }
-        if (e == hipSuccess) e = mk::als_solve_normalize(w.M, w.W, I, R, factors[n], w.lam, w, stream);
-        if (e == hipSuccess) e = mk::als_gram(factors[n], I, R, w.grams + (uint64_t)n * RR, w, stream);
+        mk::DenseJob j = dense_job(h, factors[n], n, R);
+        if (e == hipSuccess) e = mk::als_solve_normalize_jobs(j, nullptr, nullptr, 0, 1, R, stream);
+        if (e == hipSuccess) e = mk::als_gram_jobs(j, nullptr, nullptr, 0, 1, R, stream);
         if (e == hipSuccess && bf16) e = mk::cast_bf16(factors[n], (uint64_t)I * R, w.bf16[n], stream);
     }
-    if (e == hipSuccess)
-        e = mk::als_fit(w.M, factors[N - 1], h->dims[N - 1], w.lam, w.grams, N, R, h->normX2,
-                        fit_out ? fit_out : w.scal, lambda, w, stream);
+    if (e == hipSuccess) {
+        mk::DenseJob j = fit_job(h, factors[N - 1], R, fit_out ? fit_out : w.scal, lambda);
+        e = mk::als_fit_jobs(j, nullptr, nullptr, 0, 1, R, stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "CP-ALS sweep");
     return MTTKRP_OK;
 }
@@ -596,6 +628,10 @@ struct mttkrp_batch {
     uint32_t grid_part = 0, grid_fix = 0;
     std::vector<const void*> last_ptrs[MTTKRP_MAX_MODES]; // pointers of the uploaded descriptors
     mk::InvJob* inv_jobs = nullptr;                       // device: every tensor's normal-equation inverse job
+    mk::DenseJob* dense_jobs[MTTKRP_MAX_MODES + 1] = {};  // device: per mode (and [N]: fit) one job per tensor
+    uint2* dense_work[MTTKRP_MAX_MODES] = {};             // device: per mode, (tensor, row block) items
+    uint32_t ndense_work[MTTKRP_MAX_MODES] = {};
+    std::vector<mk::DenseJob> last_jobs[MTTKRP_MAX_MODES + 1];  // contents of the uploaded job tables
 };
 
 extern "C" {
@@ -672,7 +708,17 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
         b->carry_off[t] = carry_floats;
         carry_floats += (uint64_t)std::max<uint32_t>(max_parts[t], 1) * 2ull * (uint64_t)R;
     }
-    uint64_t need = align_up(carry_floats * 4) + align_up((uint64_t)count * sizeof(mk::InvJob));
+    // Row-pass work lists of the CP-ALS update: every tensor's row blocks of mode n.
+    std::vector<std::vector<uint2>> dw(N);
+    for (int n = 0; n < N; ++n)
+        for (int t = 0; t < count; ++t) {
+            mk::DenseJob j{};
+            mk::plan_dense_blocks(b->hs[t]->dims[n], b->hs[t]->als.max_blocks, j);
+            for (uint32_t k = 0; k < j.nb; ++k) dw[n].push_back(make_uint2((uint32_t)t, k));
+        }
+    uint64_t need = align_up(carry_floats * 4) + align_up((uint64_t)count * sizeof(mk::InvJob)) +
+                    (uint64_t)(N + 1) * align_up((uint64_t)count * sizeof(mk::DenseJob));
+    for (int n = 0; n < N; ++n) need += align_up(dw[n].size() * 8 + 8);
     for (int n = 0; n < N; ++n)
         need += align_up((uint64_t)count * pdb) + align_up((uint64_t)count * fdb) + align_up(pw[n].size() * 8 + 8) +
                 align_up(fw[n].size() * 8 + 8);
@@ -696,6 +742,12 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
         std::vector<mk::InvJob> jobs(count);
         for (int t = 0; t < count; ++t) jobs[t] = b->hs[t]->inv_job_host;
         e = hipMemcpy(b->inv_jobs, jobs.data(), jobs.size() * sizeof(mk::InvJob), hipMemcpyHostToDevice);
+    }
+    for (int n = 0; n <= N; ++n) b->dense_jobs[n] = reinterpret_cast<mk::DenseJob*>(take((uint64_t)count * sizeof(mk::DenseJob)));
+    for (int n = 0; n < N && e == hipSuccess; ++n) {
+        b->dense_work[n] = reinterpret_cast<uint2*>(take(dw[n].size() * 8 + 8));
+        b->ndense_work[n] = (uint32_t)dw[n].size();
+        if (!dw[n].empty()) e = hipMemcpy(b->dense_work[n], dw[n].data(), dw[n].size() * 8, hipMemcpyHostToDevice);
     }
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         b->part_desc[n] = take((uint64_t)count * pdb);
@@ -866,26 +918,37 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
     }
     std::vector<float*> outs(C);
     for (int t = 0; t < C; ++t) outs[t] = b->hs[t]->als.M;
+    // Job tables of this call (factor, lambda and fit pointers); re-uploaded
+    // only when they differ from the last call's, which synchronises first.
     hipError_t e = hipSuccess;
+    for (int n = 0; n <= N && e == hipSuccess; ++n) {
+        std::vector<mk::DenseJob> jobs(C);
+        for (int t = 0; t < C; ++t) {
+            mttkrp_handle h = b->hs[t];
+            float* A = factors[(size_t)t * N + (n < N ? n : N - 1)];
+            jobs[t] = n < N ? dense_job(h, A, n, R)
+                            : fit_job(h, A, R, (fits && fits[t]) ? fits[t] : h->als.scal, lambdas[t]);
+        }
+        if (jobs.size() != b->last_jobs[n].size() ||
+            std::memcmp(jobs.data(), b->last_jobs[n].data(), jobs.size() * sizeof(mk::DenseJob)) != 0) {
+            e = hipStreamSynchronize(stream);
+            if (e == hipSuccess)
+                e = hipMemcpy(b->dense_jobs[n], jobs.data(), jobs.size() * sizeof(mk::DenseJob), hipMemcpyHostToDevice);
+            if (e == hipSuccess) b->last_jobs[n] = std::move(jobs);
+        }
+    }
+    const mk::DenseJob none{};
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         e = mk::als_normal_eq_inverse(b->inv_jobs, C, N, n, R, 0, stream);
         if (e != hipSuccess) break;
         mttkrp_status st = mttkrp_batch_run(b, n, factors, outs.data(), stream);
         if (st) return st;
-        for (int t = 0; t < C && e == hipSuccess; ++t) {
-            mttkrp_handle h = b->hs[t];
-            mk::AlsWork& w = h->als;
-            float* A = factors[(size_t)t * N + n];
-            e = mk::als_solve_normalize(w.M, w.W, h->dims[n], R, A, w.lam, w, stream);
-            if (e == hipSuccess) e = mk::als_gram(A, h->dims[n], R, w.grams + (uint64_t)n * R * R, w, stream);
-        }
+        e = mk::als_solve_normalize_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R, stream);
+        if (e == hipSuccess)
+            e = mk::als_gram_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R, stream);
     }
-    for (int t = 0; t < C && e == hipSuccess; ++t) {
-        mttkrp_handle h = b->hs[t];
-        mk::AlsWork& w = h->als;
-        e = mk::als_fit(w.M, factors[(size_t)t * N + N - 1], h->dims[N - 1], w.lam, w.grams, N, R, h->normX2,
-                        (fits && fits[t]) ? fits[t] : w.scal, lambdas[t], w, stream);
-    }
+    if (e == hipSuccess)
+        e = mk::als_fit_jobs(none, b->dense_jobs[N], b->dense_work[N - 1], b->ndense_work[N - 1], C, R, stream);
     if (e != hipSuccess) return hip_fail(e, "batched CP-ALS sweep");
     return MTTKRP_OK;
 }

@@ -95,10 +95,36 @@ hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w
 hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, double* flag, int reset_flag,
                         hipStream_t s);
 hipError_t als_normal_eq_inverse(const InvJob* jobs, int count, int N, int skip, int R, int reset_flag, hipStream_t s);
-hipError_t als_solve_normalize(const float* M, const double* W, uint32_t I, int R, float* A, double* lam,
-                               AlsWork& w, hipStream_t s);
-hipError_t als_fit(const float* M, const float* A, uint32_t I, const double* lam, const double* grams, int N, int R,
-                   double normX2, double* fit_out, double* lam_out, AlsWork& w, hipStream_t s);
+
+// The row passes of one mode update of one tensor (a "job"): A = M W with
+// column norms into lam and A normalised; the Gram matrix of A; the fit.
+// A job's rows are split into nb blocks of rpb rows (plan_dense_blocks); the
+// *_jobs entry points run one job passed by value (jobs == NULL, grid = its
+// blocks) or a device job table with a device (job, block) work list of
+// nwork items, in one launch per kernel for every job.  Each job's arithmetic
+// and reduction order are the same either way.
+struct DenseJob {
+    const float* M;        // I x R MTTKRP output
+    const double* W;       // R x R inverse of V
+    float* A;              // I x R factor being updated (fp32)
+    double* lam;           // R column norms
+    double* part;          // per-block partial sums (>= nb x R x R)
+    double* colsq;         // R (fit: column dot products)
+    double* G_out;         // R x R Gram matrix of A
+    const double* grams;   // N x R x R (fit)
+    double* fit_out;       // 1 double (fit)
+    double* lam_out;       // R (fit: the caller's lambda)
+    double normX2;         // |X|^2 (fit)
+    uint32_t I, rpb, nb;
+    int N;
+};
+void plan_dense_blocks(uint32_t I, int max_blocks, DenseJob& j);
+hipError_t als_solve_normalize_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork,
+                                    int count, int R, hipStream_t s);
+hipError_t als_gram_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
+                         int R, hipStream_t s);
+hipError_t als_fit_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
+                        int R, hipStream_t s);
 hipError_t cast_bf16(const float* A, uint64_t n, uint16_t* out, hipStream_t s);
 
 }  // namespace mk

@@ -177,7 +177,9 @@ class CpdServer:
 class GpuExecutor(Executor):
     """Device state per job: layout handle, fp32 factors, lambda and fit on
     the GPU.  Each step groups the active jobs by (N, R) and runs one batched
-    CP-ALS sweep per group; groups use their own streams."""
+    CP-ALS sweep per group of two or more (a lone job runs its own sweep, with
+    no batch tables to rebuild); groups use their own streams.  A job's
+    results are bitwise the same either way."""
 
     def __init__(self, batched: bool = True):
         import torch
@@ -218,7 +220,7 @@ class GpuExecutor(Executor):
             st = self._stream(key)
             st.wait_stream(cur)
             with torch.cuda.stream(st):
-                if self.batched:
+                if self.batched and len(members) > 1:
                     ids = tuple(id(m["h"]) for m in members)
                     old = self._batches.get(key)
                     if old is None or old[0] != ids:
@@ -230,6 +232,11 @@ class GpuExecutor(Executor):
                     self.capi.cpd_als_batch_iter_async(b, [m["F"] for m in members], [m["lam"] for m in members],
                                                        [m["fit"] for m in members], stream=st)
                 else:
+                    # one job (or no batching): its own sweep, no batch tables to build
+                    old = self._batches.pop(key, None) if self.batched else None
+                    if old is not None:
+                        st.synchronize()
+                        old[1].free()
                     for m in members:
                         self.capi.cpd_als_iter_async(m["h"], m["F"], m["lam"], key[1], m["fit"], stream=st)
         for key in groups:

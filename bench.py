@@ -54,16 +54,22 @@ def algorithmic_bytes(dims, nnz, R, factor_bytes=4):
 
 
 def sources_digest():
-    """SHA-256 over the library's kernel and layout sources (sorted by name):
-    HBM traffic counted for one build is only reported for that build."""
+    """SHA-256 over the library's kernel and layout sources (sorted by name),
+    with comments and blank lines removed: HBM traffic counted for one build
+    of the code is only reported for that code."""
     import hashlib
+    import re
     d = os.path.join(ROOT, "paper_2503_18198_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
         if name.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(d, name), encoding="utf-8") as f:
+                text = f.read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
             h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(f.read())
+            h.update(code.encode())
     return h.hexdigest()
 
 

@@ -2,16 +2,17 @@
 // the top of mttkrp_kernels.hip.  Included by one translation unit per mode
 // count (part_n3.hip .. part_n8.hip) so the instantiations build in parallel.
 //
-// Per workgroup (kPartWG threads, one partition of G * gsz nonzeros):
-//  1. The most frequently gathered rows of every input factor (the layout's
-//     hot rows, coordinates stored as kHotBit | slot) are copied into LDS.
-//  2. Each lane group of L = R/4 lanes (4 factor values per lane: 16 bytes in
-//     fp32, 8 in bf16) walks gsz consecutive nonzeros, 32 at a time: indices
-//     and values are streamed with full-line non-temporal loads and shared in
-//     the group with ds_swizzle; U nonzeros' row gathers are issued before
-//     any is used; a row repeated by the next nonzero is not gathered again;
-//     hot rows come from LDS, the rest from global memory.  The running row
-//     sum stays in registers and a row that ends inside the run is stored once.
+// Per workgroup (part_wg threads, one partition of G * gsz nonzeros):
+//  1. When the layout has hot rows (the most frequently gathered rows of each
+//     input factor, coordinates stored as kHotBit | slot), they are copied
+//     into LDS.
+//  2. Each lane group of L lanes (16 bytes of a factor row per lane: 4 fp32 or
+//     8 bf16 values; bf16 rows of R = 16 use 8 bytes) walks gsz consecutive
+//     nonzeros, 32 at a time: indices and values are streamed with full-line
+//     non-temporal loads and shared in the group with ds_swizzle; U nonzeros'
+//     row gathers are issued before any is used; hot rows come from LDS, the
+//     rest from global memory.  The running row sum stays in registers and a
+//     row that ends inside the run is stored once.
 //  3. The first and last row partials of every group go to LDS (reusing the
 //     hot-row area) and are added in group order; rows cut by the
 //     workgroup's ends go to the carry buffer for the fix-up kernel.

@@ -94,34 +94,54 @@ def profiled_traffic(workload):
     return round((fetch + write) * 1024.0)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(t, R, F, budget_s=20.0):
     """The FP64 oracle on the host, all modes, on a bounded leading sample of
-    the nonzeros sized to take about ``budget_s`` seconds."""
+    the nonzeros: median of 3 runs on every host thread (about budget_s/2 in
+    all), and one run on 1 thread (about budget_s/4)."""
     import oracle
 
     threads = max(1, min(os.cpu_count() or 1, 64))
     N = len(t.dims)
     F64 = [f.astype(np.float64) for f in F]
     val = t.val.astype(np.float64)
-    probe = min(t.nnz, 500_000)
-    t0 = time.perf_counter()
-    for n in range(N):
-        oracle.mttkrp(t.idx[:probe], val[:probe], t.dims, F64, n, threads=threads)
-    dt = time.perf_counter() - t0
-    sample = int(min(t.nnz, max(probe, probe * budget_s / max(dt, 1e-3) / 2)))
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
+
+    def run(sample, nthr):
+        t0 = time.perf_counter()
         for n in range(N):
-            oracle.mttkrp(t.idx[:sample], val[:sample], t.dims, F64, n, threads=threads)
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= budget_s / 2 or reps >= 20:
-            break
-    flops = N * R * sample * N * reps
-    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample} of {t.nnz} nonzeros, all {N} modes, R={R}, FP64 C oracle, "
-                      f"{threads} OpenMP threads, {reps} repetition(s) in {dt:.1f} s"}
+            oracle.mttkrp(t.idx[:sample], val[:sample], t.dims, F64, n, threads=nthr)
+        return time.perf_counter() - t0
+
+    def sized(nthr, seconds):
+        probe = min(t.nnz, 200_000)
+        dt = run(probe, nthr)
+        return int(min(t.nnz, max(probe, probe * seconds / max(dt, 1e-3))))
+
+    s_all = sized(threads, budget_s / 6)
+    times = sorted(run(s_all, threads) for _ in range(3))
+    dt_all = times[1]
+    s_one = sized(1, budget_s / 4)
+    dt_one = run(s_one, 1)
+    rate_all = N * R * s_all * N / dt_all / 1e9
+    rate_one = N * R * s_one * N / dt_one / 1e9
+    return {"value": rate_all, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {s_all} of {t.nnz} nonzeros, all {N} modes, R={R}, FP64 C oracle, "
+                      f"{threads} OpenMP threads, median of 3 runs ({', '.join(f'{x:.2f}' for x in times)} s)",
+            "single_thread": {"value": rate_one, "unit": "GFLOP/s",
+                              "sample": f"first {s_one} nonzeros, all {N} modes, 1 thread, {dt_one:.2f} s"},
+            "cpu_model": cpu_model()}
 
 
 def bench_batch(args, R=16, count=256):
@@ -507,6 +527,7 @@ def main(argv=None):
     total_ms = start.elapsed_time(stop)
     ms_step = total_ms / K
     mode_ms = [float(np.mean([events[k][n][0].elapsed_time(events[k][n][1]) for k in range(K)])) for n in range(N)]
+    step_ms = [events[k][0][0].elapsed_time(events[k][N - 1][1]) for k in range(K)]
 
     flops = N * R * t.nnz * N
     gflops = flops / (ms_step / 1e3) / 1e9
@@ -531,6 +552,8 @@ def main(argv=None):
                    "nnz": t.nnz, "dims": list(t.dims), "R": R},
         "hbm_pct_peak": round(100.0 * sum(bytes_mode) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
         "per_mode_ms": [round(x, 4) for x in mode_ms],
+        "step_ms_median": round(float(np.median(step_ms)), 4),
+        "step_ms_min": round(float(np.min(step_ms)), 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(args.workload),
                      "kernel": "per-mode MTTKRP launch pair (mttkrp_part_kernel + mttkrp_fixup_kernel): "

@@ -36,6 +36,19 @@ WORKLOADS = {
     "uniform-100k-R16": dict(config=1, R=16),
     "batch256-R16": dict(config=4, R=16),
     "serve-poisson": dict(config=5, R=0),
+    "paper-shapes": dict(config=0, R=32),
+}
+
+# Shapes and nonzero counts of the paper's evaluation tensors (its Table III),
+# for synthetic stand-ins (seeded, Zipf(1.2) per mode).  The 3-mode
+# 2.9M x 2.1M x 25.5M, 143.6M-nonzero one is left out: generating it alone
+# would take several minutes.
+PAPER_SHAPES = {
+    "chicago-like": ((6200, 24, 77, 32), 5_300_000),
+    "enron-like": ((6100, 5700, 244_300, 1200), 54_200_000),
+    "nips-like": ((2500, 2900, 14_000, 17), 3_100_000),
+    "uber-like": ((183, 24, 1100, 1700), 3_300_000),
+    "vast-like": ((165_400, 11_400, 2, 100, 89), 26_000_000),
 }
 
 
@@ -372,6 +385,92 @@ def bench_precision(args):
     return 0
 
 
+def scheme1_imbalance(idx_col, dim, kappa):
+    """The paper's load balancing scheme 1 (Sec. III-B): rows sorted by
+    nonzero count and dealt cyclically to kappa workgroups, each owning its
+    rows.  Returns the largest workgroup load over the mean load, a lower
+    bound on its slowdown against an even nonzero split."""
+    deg = np.bincount(idx_col.astype(np.int64), minlength=dim)
+    order = np.sort(deg)[::-1]
+    loads = np.zeros(kappa, dtype=np.int64)
+    np.add.at(loads, np.arange(order.shape[0]) % kappa, order)
+    return float(loads.max() / (deg.sum() / kappa))
+
+
+def bench_paper_shapes(args, R=32):
+    """Synthetic tensors with the shapes and nonzero counts of the paper's
+    evaluation set: all-mode MTTKRP with this build's nonzero split and carry
+    fix-up, against the paper's scheme 2 (global atomics for cut rows) on the
+    same kernel, and scheme 1's load imbalance from each mode's degrees."""
+    import torch
+
+    import workloads
+    from paper_2503_18198_amd import capi
+
+    stream = torch.cuda.current_stream()
+    K, W = args.steps, args.warmup
+    rows = {}
+    for name, (dims, nnz) in PAPER_SHAPES.items():
+        t0 = time.perf_counter()
+        t = workloads.random_tensor(dims, nnz, dist="zipf", s=1.2, seed=7,
+                                    progress=lambda m: print(f"[bench] {name}: {m}", file=sys.stderr, flush=True))
+        gen_s = time.perf_counter() - t0
+        N = len(t.dims)
+        h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R), stream=stream)
+        kappa = capi.mttkrp_layout_info(h)["cu_count"]
+        dF = [torch.from_numpy(f).cuda() for f in workloads.random_factors(t.dims, R, seed=7)]
+        outs = [torch.empty((d, R), device="cuda") for d in t.dims]
+        outs2 = [torch.empty((d, R), device="cuda") for d in t.dims]
+
+        def timed(run, o):
+            for _ in range(W):
+                for n in range(N):
+                    run(h, n, dF, o[n], R, stream=stream)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(K):
+                for n in range(N):
+                    run(h, n, dF, o[n], R, stream=stream)
+            z.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(z) / K
+
+        ms = timed(capi.mttkrp_run, outs)
+        ms2 = timed(capi.mttkrp_run_scheme2, outs2)
+        diff = max(float(torch.linalg.norm(outs[n] - outs2[n]) / max(float(torch.linalg.norm(outs[n])), 1e-30))
+                   for n in range(N))
+        byts = sum(algorithmic_bytes(t.dims, t.nnz, R))
+        flops = N * R * t.nnz * N
+        rows[name] = {
+            "dims": list(t.dims), "nnz": t.nnz, "gen_s": round(gen_s, 1),
+            "ms_all_modes": round(ms, 4), "gflops": round(flops / (ms / 1e3) / 1e9, 1),
+            "hbm_frac": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "scheme2_atomics_ms_all_modes": round(ms2, 4),
+            "scheme2_rel_diff": diff,
+            "scheme1_imbalance_per_mode": [round(scheme1_imbalance(t.idx[:, n], t.dims[n], kappa), 2)
+                                           for n in range(N)],
+        }
+        print(f"[bench] {name}: {json.dumps(rows[name])}", file=sys.stderr, flush=True)
+        h.free()
+        del t
+    gm = float(np.exp(np.mean([np.log(r["scheme2_atomics_ms_all_modes"] / r["ms_all_modes"]) for r in rows.values()])))
+    res = {
+        "metric": "all-mode spMTTKRP GFLOP/s on tensors shaped like the paper's evaluation set",
+        "value": round(float(np.exp(np.mean([np.log(r["gflops"]) for r in rows.values()]))), 1),
+        "unit": "GFLOP/s (geometric mean)", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(sum(r["ms_all_modes"] for r in rows.values()), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "paper-shapes: Zipf(1.2) stand-ins with the shapes and nnz of the paper's Table III "
+                               "tensors (all but the 143.6M-nonzero one), R=32, fp32"},
+        "tensors": rows,
+        "scheme2_over_this_build_geomean": round(gm, 3),
+    }
+    print(json.dumps(res))
+    return 0
+
+
 def bench_serve(args, n_jobs=64, rhos=(0.5, 0.95, 2.0)):
     """Poisson CP-ALS jobs (3-5 modes, dims log-U[1e2,1e5], nnz log-U[1e4,1e6],
     Zipf(1.2), R in {16,32,64}, fit change < 1e-4 or 50 sweeps) served with
@@ -471,6 +570,8 @@ def main(argv=None):
         return bench_serve(args)
     if args.workload == "precision-100M-4mode":
         return bench_precision(args)
+    if args.workload == "paper-shapes":
+        return bench_paper_shapes(args)
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * 2 ** 20 // 4
         a = torch.rand(n, device="cuda")

@@ -131,6 +131,16 @@ mttkrp_status cpd_als_init(mttkrp_handle h, const float* const* factors, int R, 
 mttkrp_status cpd_als_iter(mttkrp_handle h, float* const* factors, double* lambda, int R, double* fit_out,
                            hipStream_t stream);
 
+/* For comparison only: the MTTKRP with the paper's load balancing scheme 2
+ * (Sec. III-B: equal nonzero chunks per workgroup, partial results of rows
+ * that span chunks added with global atomics) instead of mttkrp_run's
+ * deterministic carry fix-up.  Same arguments, layout and errors as
+ * mttkrp_run (fp32 factors); the output is zeroed by a kernel first.  The
+ * order of the atomic additions varies, so results agree with mttkrp_run up
+ * to rounding only and need not repeat bit for bit. */
+mttkrp_status mttkrp_run_scheme2(mttkrp_handle h, int mode, const float* const* factors, float* out, int R,
+                                 hipStream_t stream);
+
 /* Measurement aid for the on-chip gather ceiling (not part of the method):
  * the index/value stream and factor-row gathers of the MTTKRP along `mode`,
  * with the same partitions, lane groups and loads as mttkrp_run (fp32) or

@@ -29,7 +29,7 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
             "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create", "mttkrp_batch_run",
             "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
-            "mttkrp_gather_probe", "mttkrp_batch_autotune"]
+            "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2"]
 
 
 class MttkrpError(RuntimeError):
@@ -75,6 +75,7 @@ def _load():
     lib.mttkrp_layout_bytes.restype = ctypes.c_uint64
     lib.mttkrp_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
     lib.mttkrp_run_bf16.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
+    lib.mttkrp_run_scheme2.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
     lib.cpd_als_init.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
     lib.cpd_als_iter.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.c_int, vp, vp]
     lib.mttkrp_layout_free.argtypes = [vp]
@@ -97,7 +98,8 @@ def _load():
     lib.mttkrp_batch_free.restype = None
     for name in ("mttkrp_footprint", "mttkrp_layout_build", "mttkrp_run", "mttkrp_run_bf16", "cpd_als_init",
                  "cpd_als_iter", "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create",
-                 "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async"):
+                 "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
+                 "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -226,6 +228,12 @@ def mttkrp_run(h: Layout, mode: int, factors, out, R: Optional[int] = None, stre
     """out <- MTTKRP of the layout along ``mode`` with fp32 ``factors`` (list of N
     device tensors; the entry at ``mode`` may be None)."""
     _run(_lib.mttkrp_run, "fp32", h, mode, factors, out, R, stream)
+
+
+def mttkrp_run_scheme2(h: Layout, mode: int, factors, out, R: Optional[int] = None, stream=None):
+    """For comparison: the MTTKRP with the paper's scheme 2 (global atomics for
+    rows cut by partition boundaries) instead of the deterministic fix-up."""
+    _run(_lib.mttkrp_run_scheme2, "fp32", h, mode, factors, out, R, stream)
 
 
 def mttkrp_run_bf16(h: Layout, mode: int, factors, out, R: Optional[int] = None, stream=None):

@@ -447,6 +447,27 @@ mttkrp_status mttkrp_run_bf16(mttkrp_handle h, int mode, const uint16_t* const* 
     return run_mode(h, mode, reinterpret_cast<const void* const*>(factors), MTTKRP_BF16, out, R, stream);
 }
 
+mttkrp_status mttkrp_run_scheme2(mttkrp_handle h, int mode, const float* const* factors, float* out, int R,
+                                 hipStream_t stream)
+{
+    g_err.clear();
+    mttkrp_status s = check_run(h, mode, reinterpret_cast<const void* const*>(factors), out, R);
+    if (s) return s;
+    const mk::DevMode& d = h->dev[mode];
+    const void* fac[mk::kMaxIn];
+    const uint32_t* hot[mk::kMaxIn];
+    for (int j = 0; j < d.n_in; ++j) {
+        fac[j] = factors[d.in_modes[j]];
+        hot[j] = h->hot_rows[d.in_modes[j]];
+    }
+    const mk::Geometry g =
+        mk::plan_geometry(d.nnz, d.n_in, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+    hipError_t e = mk::launch_mttkrp(d, R, MTTKRP_FP32, fac, hot, h->nhot, out, h->carry, g, stream, true,
+                                     h->dims[mode]);
+    if (e != hipSuccess) return hip_fail(e, "MTTKRP (scheme 2) launch");
+    return MTTKRP_OK;
+}
+
 mttkrp_status mttkrp_gather_probe(mttkrp_handle h, int mode, const void* const* factors, int factor_dtype, int R,
                                   int what, hipStream_t stream)
 {

@@ -43,12 +43,15 @@ int partition_wg_threads(int n_in);
 // Dynamic LDS of the partition kernel for n_in input modes and nhot cached rows per mode.
 uint32_t partition_lds_bytes(int n_in, int R, int dtype, uint32_t nhot);
 
-// Enqueue the per-mode MTTKRP: partition kernel then fix-up kernel.
+// Enqueue the per-mode MTTKRP: partition kernel then fix-up kernel.  With
+// atomic_cut (the paper's scheme 2, for comparison) the output (out_rows x R)
+// is zeroed first and rows cut by partition boundaries are added with global
+// atomics instead of the deterministic carry fix-up.
 // `fac` and `hot_rows` hold the N-1 input factors and their hot-row tables in
 // the order of m.in_modes; nhot rows of each are cached in LDS.
 hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* fac,
                          const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry,
-                         const Geometry& g, hipStream_t s);
+                         const Geometry& g, hipStream_t s, bool atomic_cut = false, uint32_t out_rows = 0);
 
 // Gather-ceiling probe of one mode (stream and row gathers, no arithmetic);
 // what = 0: stream only, 1: stream and gathers.  Writes only (rarely) carry.

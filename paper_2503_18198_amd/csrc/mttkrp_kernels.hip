@@ -50,17 +50,17 @@ extern template size_t part_desc_bytes_nin<7>();
 extern template void fill_part_desc_nin<7>(void*, const DevMode&, int, int, const void* const*, float*, float*, uint32_t);
 extern template hipError_t launch_batch_part_nin<7>(int, int, const void*, const uint2*, uint32_t, uint32_t, hipStream_t);
 extern template hipError_t launch_part_nin<2>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
-                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+                                                uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 extern template hipError_t launch_part_nin<3>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
-                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+                                                uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 extern template hipError_t launch_part_nin<4>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
-                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+                                                uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 extern template hipError_t launch_part_nin<5>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
-                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+                                                uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 extern template hipError_t launch_part_nin<6>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
-                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+                                                uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 extern template hipError_t launch_part_nin<7>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
-                                                uint32_t, float*, float*, const Geometry&, hipStream_t);
+                                                uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 
 namespace {
 
@@ -180,23 +180,42 @@ uint32_t partition_lds_bytes(int n_in, int R, int dtype, uint32_t nhot) { return
 
 int partition_wg_threads(int n_in) { return part_wg(n_in); }
 
+// out[0..n) = 0 (a kernel, not a memset, so that it can sit in a captured graph).
+__global__ __launch_bounds__(kWG) void zero_fill_kernel(float* __restrict__ p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kWG) p[i] = 0.0f;
+}
+
 hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* fac,
                          const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry,
-                         const Geometry& g, hipStream_t s)
+                         const Geometry& g, hipStream_t s, bool atomic_cut, uint32_t out_rows)
 {
     hipError_t e = hipSuccess;
+    if (atomic_cut) {
+        // The paper's scheme 2: zero the output, add rows cut by partition
+        // boundaries with global atomics, no fix-up.
+        const uint64_t n = (uint64_t)out_rows * R;
+        uint64_t blocks = (n + kWG - 1) / kWG;
+        if (blocks > 4096) blocks = 4096;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(zero_fill_kernel, dim3((uint32_t)blocks), dim3(kWG), 0, s, out, n);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const uint32_t ac = atomic_cut ? 1u : 0u;
     if (m.nnz > 0) {
         switch (m.n_in) {
-            case 2: e = launch_part_nin<2>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
-            case 3: e = launch_part_nin<3>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
-            case 4: e = launch_part_nin<4>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
-            case 5: e = launch_part_nin<5>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
-            case 6: e = launch_part_nin<6>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
-            case 7: e = launch_part_nin<7>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, s); break;
+            case 2: e = launch_part_nin<2>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, ac, s); break;
+            case 3: e = launch_part_nin<3>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, ac, s); break;
+            case 4: e = launch_part_nin<4>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, ac, s); break;
+            case 5: e = launch_part_nin<5>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, ac, s); break;
+            case 6: e = launch_part_nin<6>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, ac, s); break;
+            case 7: e = launch_part_nin<7>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, ac, s); break;
             default: e = hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;
     }
+    if (atomic_cut) return hipSuccess;
     FixArgs f;
     f.winfo = m.winfo;
     f.row_id = m.row_id;

@@ -188,6 +188,7 @@ struct PartArgs {
     uint32_t nrows_nz;
     uint32_t gsz;
     uint32_t nhot;       // hot slots per input mode held in LDS
+    uint32_t atomic_cut; // rows cut by a partition boundary: 0 partial to carry, 1 global atomic add to out
 };
 
 // Nonzeros whose row gathers are issued before the first is used, chosen so
@@ -505,7 +506,11 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
         }
         const bool head_split = from_first_of_wg && s_hstart[0] == 0;
         const bool tail_split = reaches_end && row_continues;
-        if (head_split || tail_split)
+        if ((head_split || tail_split) && a.atomic_cut) {
+            float* dst = a.out + (uint64_t)a.row_id[row] * R + gl * E;
+#pragma unroll
+            for (int e = 0; e < E; ++e) atomicAdd(dst + e, sum[e]);
+        } else if (head_split || tail_split)
             store_vals<E>(a.carry + ((uint64_t)part * 2 + (from_first_of_wg ? 0 : 1)) * R + gl * E, sum);
         else
             store_vals<E>(a.out + (uint64_t)a.row_id[row] * R + gl * E, sum);
@@ -559,14 +564,16 @@ void fill_part_args(PartArgs<NIN>& a, const DevMode& m, int R, int dtype, const 
     a.nrows_nz = (uint32_t)m.nrows_nz;
     a.gsz = gsz;
     a.nhot = nhot;
+    a.atomic_cut = 0;
 }
 
 template <int NIN, int R, int DT, bool HOT>
 hipError_t launch_part(const DevMode& m, const void* const* fac, const uint32_t* const* hot_rows, uint32_t nhot,
-                       float* out, float* carry, const Geometry& g, hipStream_t s)
+                       float* out, float* carry, const Geometry& g, uint32_t atomic_cut, hipStream_t s)
 {
     PartArgs<NIN> a;
     fill_part_args<NIN>(a, m, R, DT, fac, hot_rows, nhot, out, carry, g.gsz);
+    a.atomic_cut = atomic_cut;
     const uint32_t lds = part_lds_bytes(NIN, R, DT, nhot);
     static uint32_t lds_set = 0;   // largest dynamic LDS size already allowed for this instantiation
     if (lds > lds_set) {
@@ -581,20 +588,20 @@ hipError_t launch_part(const DevMode& m, const void* const* fac, const uint32_t*
 
 template <int NIN, int DT>
 hipError_t dispatch_r(const DevMode& m, int R, const void* const* fac, const uint32_t* const* hot_rows, uint32_t nhot,
-                      float* out, float* carry, const Geometry& g, hipStream_t s)
+                      float* out, float* carry, const Geometry& g, uint32_t atomic_cut, hipStream_t s)
 {
     if (nhot) {
         switch (R) {
-            case 16: return launch_part<NIN, 16, DT, true>(m, fac, hot_rows, nhot, out, carry, g, s);
-            case 32: return launch_part<NIN, 32, DT, true>(m, fac, hot_rows, nhot, out, carry, g, s);
-            case 64: return launch_part<NIN, 64, DT, true>(m, fac, hot_rows, nhot, out, carry, g, s);
+            case 16: return launch_part<NIN, 16, DT, true>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
+            case 32: return launch_part<NIN, 32, DT, true>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
+            case 64: return launch_part<NIN, 64, DT, true>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
             default: return hipErrorInvalidValue;
         }
     }
     switch (R) {
-        case 16: return launch_part<NIN, 16, DT, false>(m, fac, hot_rows, nhot, out, carry, g, s);
-        case 32: return launch_part<NIN, 32, DT, false>(m, fac, hot_rows, nhot, out, carry, g, s);
-        case 64: return launch_part<NIN, 64, DT, false>(m, fac, hot_rows, nhot, out, carry, g, s);
+        case 16: return launch_part<NIN, 16, DT, false>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
+        case 32: return launch_part<NIN, 32, DT, false>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
+        case 64: return launch_part<NIN, 64, DT, false>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -651,11 +658,11 @@ hipError_t launch_batch_part_nin(int R, int dtype, const void* descs, const uint
 template <int NIN>
 hipError_t launch_part_nin(const DevMode& m, int R, int dtype, const void* const* fac,
                            const uint32_t* const* hot_rows, uint32_t nhot, float* out, float* carry,
-                           const Geometry& g, hipStream_t s)
+                           const Geometry& g, uint32_t atomic_cut, hipStream_t s)
 {
     return dtype == MTTKRP_FP32
-               ? part::dispatch_r<NIN, MTTKRP_FP32>(m, R, fac, hot_rows, nhot, out, carry, g, s)
-               : part::dispatch_r<NIN, MTTKRP_BF16>(m, R, fac, hot_rows, nhot, out, carry, g, s);
+               ? part::dispatch_r<NIN, MTTKRP_FP32>(m, R, fac, hot_rows, nhot, out, carry, g, atomic_cut, s)
+               : part::dispatch_r<NIN, MTTKRP_BF16>(m, R, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
 }
 
 }  // namespace mk

@@ -122,8 +122,9 @@ def cpu_model() -> str:
 
 def cpu_baseline(t, R, F, budget_s=20.0):
     """The FP64 oracle on the host, all modes, on a bounded leading sample of
-    the nonzeros: median of 3 runs on every host thread (about budget_s/2 in
-    all), and one run on 1 thread (about budget_s/4)."""
+    the nonzeros: median of 3 runs on every host thread, and one run on 1
+    thread, each sample doubled until a run takes about budget_s/10 (the
+    whole baseline then takes about budget_s)."""
     import oracle
 
     threads = max(1, min(os.cpu_count() or 1, 64))
@@ -138,14 +139,17 @@ def cpu_baseline(t, R, F, budget_s=20.0):
         return time.perf_counter() - t0
 
     def sized(nthr, seconds):
-        probe = min(t.nnz, 200_000)
-        dt = run(probe, nthr)
-        return int(min(t.nnz, max(probe, probe * seconds / max(dt, 1e-3))))
+        # Double the sample until one run takes `seconds`: the oracle's
+        # per-thread outputs are a fixed cost that a small probe over-weights.
+        sample = min(t.nnz, 1_000_000)
+        while sample < t.nnz and run(sample, nthr) < seconds:
+            sample = min(t.nnz, 2 * sample)
+        return sample
 
-    s_all = sized(threads, budget_s / 6)
+    s_all = sized(threads, budget_s / 10)
     times = sorted(run(s_all, threads) for _ in range(3))
     dt_all = times[1]
-    s_one = sized(1, budget_s / 4)
+    s_one = sized(1, budget_s / 10)
     dt_one = run(s_one, 1)
     rate_all = N * R * s_all * N / dt_all / 1e9
     rate_one = N * R * s_one * N / dt_one / 1e9

@@ -183,3 +183,21 @@ def test_scheme2_atomics_agrees():
         e = gu.rel_fro(got, gu.oracle_mttkrp(t.idx, t.val, t.dims, F, n))
         assert e <= TOL, f"mode {n}: {e:.3e}"
     h.free()
+
+
+@pytest.mark.parametrize("dims,R", [((30, 25, 20, 15, 12), 64), ((12, 11, 10, 9, 8, 7, 6, 5), 32),
+                                    ((12, 11, 10, 9, 8, 7, 6, 5), 64)])
+def test_bf16_many_modes(dims, R):
+    """bf16 rows with 8 values per lane on the widest per-nonzero state (up to
+    7 input factors), against the oracle fed the same bf16-rounded factors."""
+    print("case bf16 many modes", dims, R, flush=True)
+    t = workloads.random_tensor(dims, 30_000, dist="zipf", s=1.1, seed=9)
+    F = workloads.random_factors(t.dims, R, seed=9)
+    Fr = [oracle.bf16_round(f) for f in F]
+    h = build(t)
+    dF = gu.dev_factors(F, dtype=torch.bfloat16)
+    for n in range(len(dims)):
+        got = gu.gpu_mttkrp(h, n, dF, R, bf16=True)
+        e = gu.rel_fro(got, gu.oracle_mttkrp(t.idx, t.val, t.dims, Fr, n))
+        assert e <= TOL, f"bf16 mode {n}: {e:.3e}"
+    h.free()

@@ -292,6 +292,138 @@ __global__ __launch_bounds__(kWG) void mw_kernel(DenseJob single, const DenseJob
     }
 }
 
+// ---- FP64 matrix-core versions of the two row passes (R = 16, 32) ----
+//
+// v_mfma_f64_16x16x4f64: D(16x16) += A(16x4) B(4x16).  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; item q of its result is
+// D[l / 16 + 4 q][l % 16].
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Rows of M W on matrix cores; same job, blocks and outputs as mw_kernel.
+// Each wave takes 16-row tiles.  Lane (lr = l % 16, lq = l / 16) loads
+// M[row lr][16h + 4lq .. +3] as one 16-byte load; its j-th value is the
+// A operand of k-step 4h + j, whose k index lq stands for k = 16h + 4lq + j,
+// so the B operand of that step is W[16h + 4lq + j][16t + lr].
+template <int R>
+__global__ __launch_bounds__(kWG) void mw_mfma_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
+                                                      const uint2* __restrict__ work, int op)
+{
+    static_assert(R == 16 || R == 32, "matrix-core row pass for R = 16 or 32");
+    constexpr int CT = R / 16;   // column tiles
+    constexpr int H = R / 16;    // 16-wide k chunks
+    __shared__ double sred[R * 16];
+    uint32_t blk;
+    const DenseJob& jb = pick_job(single, jobs, work, blk);
+    const float* __restrict__ M = jb.M;
+    const double* __restrict__ W = jb.W;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    double wf[H][4][CT];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int t = 0; t < CT; ++t) wf[h][j][t] = W[(16 * h + 4 * lq + j) * R + 16 * t + lr];
+    double inv[CT];
+    double colsq[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+        inv[t] = op == 1 ? 1.0 / jb.lam[16 * t + lr] : 0.0;
+        colsq[t] = 0.0;
+    }
+    uint32_t r0, r1;
+    block_rows(jb.I, jb.rpb, blk, r0, r1);
+    for (uint32_t tile = r0 + 16u * wave; tile < r1; tile += 64u) {
+        const uint32_t row = tile + lr;
+        f64x4 acc[CT];
+#pragma unroll
+        for (int t = 0; t < CT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            float4 m = {0.f, 0.f, 0.f, 0.f};
+            if (row < r1) m = *reinterpret_cast<const float4*>(M + (uint64_t)row * R + 16 * h + 4 * lq);
+            const double a[4] = {(double)m.x, (double)m.y, (double)m.z, (double)m.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int t = 0; t < CT; ++t) acc[t] = mfma_f64(a[j], wf[h][j][t], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < CT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t rr = tile + lq + 4 * q;
+                if (rr < r1) {
+                    if (op == 0) colsq[t] += acc[t][q] * acc[t][q];
+                    else jb.A[(uint64_t)rr * R + 16 * t + lr] = (float)(acc[t][q] * inv[t]);
+                }
+            }
+    }
+    if (op == 0) {
+        // Column c = 16t + lr: 16 partials (4 waves x 4 lane quarters), added in a fixed order.
+#pragma unroll
+        for (int t = 0; t < CT; ++t) sred[(16 * t + lr) * 16 + wave * 4 + lq] = colsq[t];
+        __syncthreads();
+        if (threadIdx.x < R) {
+            double v = 0.0;
+            for (int k = 0; k < 16; ++k) v += sred[threadIdx.x * 16 + k];
+            jb.part[(uint64_t)blk * R + threadIdx.x] = v;
+        }
+    }
+}
+
+// Gram partials of the block's rows on matrix cores: D = sum_i A[i]^T A[i]
+// over 4-row steps; the A operand is A^T (lane: row i0 + lq, column 16rt + lr),
+// the B operand A itself (row i0 + lq, column 16ct + lr).  Each wave takes
+// every fourth 4-row step; the four waves' tiles are added in a fixed order.
+template <int R>
+__global__ __launch_bounds__(kWG) void gram_mfma_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
+                                                        const uint2* __restrict__ work)
+{
+    static_assert(R == 16 || R == 32, "matrix-core Gram for R = 16 or 32");
+    constexpr int T = R / 16;
+    __shared__ double sacc[4 * R * R];
+    uint32_t blk;
+    const DenseJob& jb = pick_job(single, jobs, work, blk);
+    const float* __restrict__ A = jb.A;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    f64x4 acc[T][T];
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    uint32_t r0, r1;
+    block_rows(jb.I, jb.rpb, blk, r0, r1);
+    for (uint32_t i0 = r0 + 4u * wave; i0 < r1; i0 += 16u) {
+        const uint32_t row = i0 + lq;
+        double x[T];
+#pragma unroll
+        for (int h = 0; h < T; ++h) x[h] = row < r1 ? (double)A[(uint64_t)row * R + 16 * h + lr] : 0.0;
+#pragma unroll
+        for (int a = 0; a < T; ++a)
+#pragma unroll
+            for (int b = 0; b < T; ++b) acc[a][b] = mfma_f64(x[a], x[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                sacc[wave * R * R + (16 * a + lq + 4 * q) * R + 16 * b + lr] = acc[a][b][q];
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * R; e += kWG)
+        jb.part[(uint64_t)blk * R * R + e] =
+            ((sacc[e] + sacc[R * R + e]) + sacc[2 * R * R + e]) + sacc[3 * R * R + e];
+}
+
 // part[b][c] = sum over the block's rows of M[i][c] * A[i][c].
 __global__ __launch_bounds__(kWG) void coldot_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
                                                      const uint2* __restrict__ work, int R)
@@ -416,16 +548,23 @@ struct Launch {
     uint32_t grid() const { return jobs ? nwork : single.nb; }
 };
 
+// R = 16 and 32 run on the FP64 matrix cores; R = 64 on the vector units.
 template <int R>
 void launch_mw(const Launch& L, int op, hipStream_t s)
 {
-    hipLaunchKernelGGL(mw_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work, op);
+    if constexpr (R <= 32)
+        hipLaunchKernelGGL(mw_mfma_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work, op);
+    else
+        hipLaunchKernelGGL(mw_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work, op);
 }
 
 template <int R>
 void launch_gram(const Launch& L, hipStream_t s)
 {
-    hipLaunchKernelGGL(gram_partial_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work);
+    if constexpr (R <= 32)
+        hipLaunchKernelGGL(gram_mfma_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work);
+    else
+        hipLaunchKernelGGL(gram_partial_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work);
 }
 
 void launch_reduce(const Launch& L, int K, int which, hipStream_t s)

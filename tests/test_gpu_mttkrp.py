@@ -201,3 +201,24 @@ def test_bf16_many_modes(dims, R):
         e = gu.rel_fro(got, gu.oracle_mttkrp(t.idx, t.val, t.dims, Fr, n))
         assert e <= TOL, f"bf16 mode {n}: {e:.3e}"
     h.free()
+
+
+@pytest.mark.parametrize("dims,R,bf16", [((3000, 2500, 2000), 16, False), ((3000, 2500, 2000), 32, False),
+                                         ((3000, 2500, 2000), 64, False), ((3000, 2500, 2000), 32, True),
+                                         ((3000, 2500, 2000), 64, True), ((800, 700, 600, 500), 32, False),
+                                         ((800, 700, 600, 500), 32, True)])
+def test_hot_row_cache(dims, R, bf16):
+    """The optional LDS hot-row cache: the most gathered rows of every input
+    factor come from LDS, the rest from global memory, in the same launch."""
+    print("case hot rows", dims, R, bf16, flush=True)
+    t = workloads.random_tensor(dims, 300_000, dist="zipf", s=1.2, seed=13)
+    F = workloads.random_factors(t.dims, R, seed=13)
+    h = build(t, max_R=R, hot_rows=-1)
+    assert capi.mttkrp_layout_info(h)["hot_rows"] > 0
+    dF = gu.dev_factors(F, dtype=torch.bfloat16 if bf16 else torch.float32)
+    Fr = [oracle.bf16_round(f) for f in F] if bf16 else F
+    for n in range(len(dims)):
+        got = gu.gpu_mttkrp(h, n, dF, R, bf16=bf16)
+        e = gu.rel_fro(got, gu.oracle_mttkrp(t.idx, t.val, t.dims, Fr, n))
+        assert e <= TOL, f"mode {n}: {e:.3e}"
+    h.free()

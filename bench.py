@@ -31,12 +31,12 @@ METRIC = "all-mode spMTTKRP GFLOP/s & HBM % peak; batched req/s + p50/p99 latenc
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    "zipf1.2-20M-R32": dict(config=2, R=32),
-    "precision-100M-4mode": dict(config=3, R=32),
-    "uniform-100k-R16": dict(config=1, R=16),
-    "batch256-R16": dict(config=4, R=16),
-    "serve-poisson": dict(config=5, R=0),
-    "paper-shapes": dict(config=0, R=32),
+    "zipf1.2-20M-R32": dict(tensor="zipf1.2-20M", R=32),
+    "precision-100M-4mode": dict(tensor="zipf1.1-100M-4mode", R=32),
+    "uniform-100k-R16": dict(tensor="small-uniform", R=16),
+    "batch256-R16": dict(tensor=None, R=16),
+    "serve-poisson": dict(tensor=None, R=0),
+    "paper-shapes": dict(tensor=None, R=32),
 }
 
 # Shapes and nonzero counts of the paper's evaluation tensors (its Table III),
@@ -332,7 +332,7 @@ def bench_precision(args):
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    t = workloads.config_tensor(3, progress=log)
+    t = workloads.named_tensor("zipf1.1-100M-4mode", progress=log)
     N = len(t.dims)
     log(f"generated {t.dims} nnz={t.nnz}")
     stream = torch.cuda.current_stream()
@@ -591,8 +591,8 @@ def main(argv=None):
     wl = WORKLOADS[args.workload]
     R = wl["R"]
     t_gen = time.perf_counter()
-    t = workloads.config_tensor(wl["config"])
-    F = workloads.random_factors(t.dims, R, seed=wl["config"])
+    t = workloads.named_tensor(wl["tensor"])
+    F = workloads.random_factors(t.dims, R, seed=workloads.WORKLOADS[wl["tensor"]]["seed"])
     gen_s = time.perf_counter() - t_gen
     N = len(t.dims)
     print(f"[bench] generated {t.dims} nnz={t.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
@@ -654,7 +654,7 @@ def main(argv=None):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {N}-mode {'x'.join(map(str, t.dims))}, {t.nnz} distinct nonzeros "
-                               f"({'Zipf(%s)' % workloads.CONFIGS[wl['config']]['s'] if workloads.CONFIGS[wl['config']]['dist'] == 'zipf' else 'uniform'}), "
+                               f"({'Zipf(%s)' % workloads.WORKLOADS[wl['tensor']]['s'] if workloads.WORKLOADS[wl['tensor']]['dist'] == 'zipf' else 'uniform'}), "
                                f"R={R}, fp32 factors, all-mode MTTKRP per step",
                    "nnz": t.nnz, "dims": list(t.dims), "R": R},
         "hbm_pct_peak": round(100.0 * sum(bytes_mode) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 2),

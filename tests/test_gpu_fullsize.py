@@ -33,10 +33,10 @@ def launch_geometry(nnz, n_in, R, info, max_parts=8192):
     return gsz, gsz * groups, parts
 
 
-def test_config2_full_size_sampled_rows():
-    print("case full-size config 2", flush=True)
+def test_zipf20m_full_size_sampled_rows():
+    print("case full-size zipf1.2-20M", flush=True)
     R = 32
-    t = workloads.config_tensor(2)
+    t = workloads.named_tensor("zipf1.2-20M")
     F = workloads.random_factors(t.dims, R, seed=2)
     h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R))
     dF = gu.dev_factors(F)

@@ -38,7 +38,7 @@ BF16_BOUND = (1 + 2.0 ** -8) ** 3 - 1 + 1e-5
 @pytest.fixture(scope="module")
 def tensor():
     print(f"case precision workload scale {SCALE}", flush=True)
-    return workloads.config_tensor(3, scale=SCALE, progress=lambda m: print(f"  {m}", flush=True))
+    return workloads.named_tensor("zipf1.1-100M-4mode", scale=SCALE, progress=lambda m: print(f"  {m}", flush=True))
 
 
 def sample_rows(t, n, rng):

@@ -8,11 +8,11 @@ without sharing any code of the method.
 
 from .gen import (  # noqa: F401
     SparseTensor,
-    config_tensor,
+    named_tensor,
     batch_tensors,
     job_stream,
     random_factors,
     random_tensor,
     zipf_cdf,
-    CONFIGS,
+    WORKLOADS,
 )

@@ -26,13 +26,13 @@ from typing import Callable, List, Optional, Sequence
 import numpy as np
 
 # Named workloads.  Sizes follow the benchmark table of this project.
-CONFIGS = {
-    1: dict(name="small-uniform", dims=(1000, 800, 600), nnz=100_000, dist="uniform",
-            s=None, values="uniform", R=16),
-    2: dict(name="zipf1.2-20M", dims=(200_000, 150_000, 100_000), nnz=20_000_000,
-            dist="zipf", s=1.2, values="uniform", R=32),
-    3: dict(name="zipf1.1-100M-4mode", dims=(50_000, 40_000, 30_000, 2_000), nnz=100_000_000,
-            dist="zipf", s=1.1, values="lognormal", R=32),
+WORKLOADS = {
+    "small-uniform": dict(dims=(1000, 800, 600), nnz=100_000, dist="uniform", s=None, values="uniform", R=16,
+                          seed=1),
+    "zipf1.2-20M": dict(dims=(200_000, 150_000, 100_000), nnz=20_000_000, dist="zipf", s=1.2, values="uniform",
+                        R=32, seed=2),
+    "zipf1.1-100M-4mode": dict(dims=(50_000, 40_000, 30_000, 2_000), nnz=100_000_000, dist="zipf", s=1.1,
+                               values="lognormal", R=32, seed=3),
 }
 
 
@@ -159,14 +159,14 @@ def random_tensor(dims: Sequence[int], nnz: int, dist: str = "uniform", s: Optio
                         nnz_requested=int(nnz), capped=capped)
 
 
-def config_tensor(config_id: int, scale: float = 1.0, progress: Optional[Callable[[str], None]] = None
-                  ) -> SparseTensor:
-    """The tensor of a named configuration; ``scale`` < 1 shrinks dims and nnz
+def named_tensor(name: str, scale: float = 1.0, progress: Optional[Callable[[str], None]] = None
+                 ) -> SparseTensor:
+    """The tensor of a named workload; ``scale`` < 1 shrinks dims and nnz
     proportionally (for quick runs), keeping the distribution."""
-    c = CONFIGS[config_id]
+    c = WORKLOADS[name]
     dims = tuple(max(2, int(round(d * scale))) for d in c["dims"])
     nnz = max(1, int(round(c["nnz"] * scale)))
-    return random_tensor(dims, nnz, c["dist"], c["s"], c["values"], seed=config_id, progress=progress)
+    return random_tensor(dims, nnz, c["dist"], c["s"], c["values"], seed=c["seed"], progress=progress)
 
 
 def random_factors(dims: Sequence[int], R: int, seed=0, low: float = 0.0, high: float = 1.0

@@ -29,8 +29,10 @@
  *    asynchronous unless stated otherwise.  A handle owns scratch memory
  *    (carry rows, CP-ALS workspace), so one handle must be used by one stream
  *    at a time; different handles are independent.
- *  - Results are reproducible bit for bit for a fixed handle, R and dtype:
- *    no atomics, fixed summation order.
+ *  - Results are reproducible bit for bit for a fixed handle (including its
+ *    parts_per_cu), R and dtype: no atomics, fixed summation order.  The one
+ *    exception is mttkrp_run_scheme2, kept to compare with the paper's
+ *    atomic-based scheme.
  */
 #ifndef MTTKRP_H
 #define MTTKRP_H

@@ -552,7 +552,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true", help="accepted for compatibility; parity lives in tests/")
     ap.add_argument("--no-gather-ceiling", action="store_true")
-    ap.add_argument("--serve-slots", type=int, nargs="+", default=[4],
+    ap.add_argument("--serve-slots", type=int, nargs="+", default=[8, 4],
                     help="concurrent job slots of the continuous-batching server (serve-poisson)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB, 5 times (to calibrate "

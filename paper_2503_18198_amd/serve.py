@@ -190,6 +190,11 @@ class GpuExecutor(Executor):
         self.batched = batched
         self._batches: Dict[Tuple[int, int], Tuple[tuple, object]] = {}   # group -> (member ids, batch)
         self._streams: Dict[Tuple[int, int], object] = {}
+        # Fits of a step are gathered on the device and copied to pinned host
+        # memory with one asynchronous copy (a pageable .cpu() costs ~1 ms).
+        self._fit_dev = torch.empty(0, dtype=torch.float64, device="cuda")
+        self._fit_host = torch.empty(0, dtype=torch.float64)
+        self._fit_event = torch.cuda.Event()
 
     def footprint(self, job: ServeJob) -> int:
         lib = self.capi.mttkrp_footprint(job.dims, job.nnz, opts=dict(max_R=job.R))
@@ -241,8 +246,16 @@ class GpuExecutor(Executor):
                         self.capi.cpd_als_iter_async(m["h"], m["F"], m["lam"], key[1], m["fit"], stream=st)
         for key in groups:
             cur.wait_stream(self._stream(key))
-        fits = torch.cat([s["fit"] for s in slots]).cpu().numpy()
-        return [float(x) for x in fits]
+        n = len(slots)
+        if self._fit_dev.numel() < n:
+            cap = max(64, 2 * n)
+            self._fit_dev = torch.empty(cap, dtype=torch.float64, device="cuda")
+            self._fit_host = torch.empty(cap, dtype=torch.float64, pin_memory=True)
+        torch.cat([s["fit"] for s in slots], out=self._fit_dev[:n])
+        self._fit_host[:n].copy_(self._fit_dev[:n], non_blocking=True)
+        self._fit_event.record(cur)
+        self._fit_event.synchronize()
+        return self._fit_host[:n].tolist()
 
     def release(self, slot):
         torch = self.torch

@@ -219,10 +219,11 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
 
     const int threads = host_threads();
     std::vector<mk::HotSet> hot = mk::select_hot_rows(coo_idx, nnz, dims, N, nhot);
+    mk::BuildScratch scratch;
     if (h->host_only) {
         h->host.resize(N);
         for (int n = 0; n < N; ++n)
-            mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, true, threads, &hot, h->host[n]);
+            mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, true, threads, &hot, h->host[n], &scratch);
         for (auto& hs : hot) hs.rows.resize(nhot, 0u);
         h->hot = std::move(hot);
         *out = h;
@@ -283,11 +284,11 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
 
-    // Mode copies: build on the host one mode at a time, upload, release.
+    // Mode copies: built on the host one mode at a time into the same buffers, uploaded.
     double normX2 = 0.0;
+    mk::HostMode hm;
     for (int n = 0; n < N && e == hipSuccess; ++n) {
-        mk::HostMode hm;
-        mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, false, threads, &hot, hm);
+        mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, false, threads, &hot, hm, &scratch);
         mk::DevMode& d = h->dev[n];
         d.nnz = hm.nnz;
         d.nnz_pad = hm.nnz_pad;
@@ -326,8 +327,7 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
                 k = j;
             }
         }
-        // The host arrays are released at the end of this iteration; wait for
-        // the copies that read them.
+        // The next mode overwrites the host arrays; wait for the copies that read them.
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
     }
     h->normX2 = normX2;

@@ -1,5 +1,6 @@
 // Host construction of the mode-specific copies (Sec. III-B scheme 2 order,
-// Sec. III-C COO copies).  Runs once per tensor; O(nnz log(row length)) per mode.
+// Sec. III-C COO copies).  Runs once per tensor: per mode, a stable radix sort
+// of packed coordinate keys, one pass per 11 key bits.
 #include "layout.h"
 
 #include <algorithm>
@@ -60,6 +61,132 @@ int bits_for(uint32_t d)
     return b;
 }
 
+// Chunk t of `chunks` equal ranges of [0, n); the same split in every call.
+void parallel_chunks(uint64_t n, int chunks, const std::function<void(int, uint64_t, uint64_t)>& f)
+{
+    if (chunks <= 1) {
+        f(0, 0, n);
+        return;
+    }
+    std::vector<std::thread> ts;
+    ts.reserve(chunks);
+    for (int t = 0; t < chunks; ++t)
+        ts.emplace_back(f, t, n * (uint64_t)t / (uint64_t)chunks, n * (uint64_t)(t + 1) / (uint64_t)chunks);
+    for (auto& t : ts) t.join();
+}
+
+// Stable least-significant-digit radix sort of (key, pos) pairs on the low
+// `bits` bits of the keys, 11 bits per pass, ping-ponging between the two
+// buffer pairs.  A pass whose digit is the same for every key is skipped.
+// Stability keeps equal keys in input order.  Returns true when the sorted
+// pairs end in (tkey, tpos).
+template <class K>
+bool radix_sort_pairs(K* key, uint32_t* pos, K* tkey, uint32_t* tpos, uint64_t n, int bits, int threads)
+{
+    constexpr int kDigit = 11;   // 2048 buckets: fewer passes than bytes, histograms still in L1
+    constexpr uint32_t kBuckets = 1u << kDigit;
+    const int T = (threads <= 1 || n < (1u << 16)) ? 1 : threads;
+    std::vector<uint64_t> hist((size_t)T * kBuckets);
+    bool swapped = false;
+    for (int shift = 0; shift < bits; shift += kDigit) {
+        parallel_chunks(n, T, [&](int t, uint64_t lo, uint64_t hi) {
+            uint64_t* h = &hist[(size_t)t * kBuckets];
+            std::fill(h, h + kBuckets, 0);
+            for (uint64_t k = lo; k < hi; ++k) h[(uint32_t)(key[k] >> shift) & (kBuckets - 1)]++;
+        });
+        bool constant = false;
+        uint64_t run = 0;
+        for (uint32_t d = 0; d < kBuckets; ++d) {
+            uint64_t tot = 0;
+            for (int t = 0; t < T; ++t) {
+                const uint64_t c = hist[(size_t)t * kBuckets + d];
+                hist[(size_t)t * kBuckets + d] = run + tot;
+                tot += c;
+            }
+            if (tot == n) constant = true;
+            run += tot;
+        }
+        if (constant) continue;
+        parallel_chunks(n, T, [&](int t, uint64_t lo, uint64_t hi) {
+            uint64_t* o = &hist[(size_t)t * kBuckets];
+            for (uint64_t k = lo; k < hi; ++k) {
+                const uint64_t dst = o[(uint32_t)(key[k] >> shift) & (kBuckets - 1)]++;
+                tkey[dst] = key[k];
+                tpos[dst] = pos[k];
+            }
+        });
+        std::swap(key, tkey);
+        std::swap(pos, tpos);
+        swapped = !swapped;
+    }
+    return swapped;
+}
+
+// Order of one mode copy by a packed integer key: the output index in the
+// top bits, then the other indices in cyclic order.  Sorted stably from the
+// input order, equal coordinates keep their input order.  Fills start (row
+// starts), out.idx (decoded from the keys), out.val and out.src_pos.
+template <class K>
+void sort_by_packed_key(const uint32_t* coo, const float* vals, uint64_t nnz, const uint32_t* dims, int N, int n,
+                        const std::vector<int>& cyc, int threads, const std::vector<HotSet>* hot, bool keep_src_pos,
+                        BuildScratch& sc, std::vector<uint64_t>& start, HostMode& out)
+{
+    const uint64_t I = dims[n];
+    const int nf = (int)cyc.size();
+    std::vector<int> fbits(nf), fshift(nf), fslot(nf);
+    int below = 0;
+    for (int f = nf - 1; f >= 0; --f) {
+        fbits[f] = bits_for(dims[cyc[f]]);
+        fshift[f] = below;
+        below += fbits[f];
+        fslot[f] = cyc[f] < n ? cyc[f] : cyc[f] - 1;   // position among the increasing input modes
+    }
+    const int row_bits = bits_for(dims[n]);
+    const int row_shift = below;
+    if (sc.key.size() < nnz) {
+        sc.key.resize(nnz);
+        sc.tkey.resize(nnz);
+        sc.pos.resize(nnz);
+        sc.tpos.resize(nnz);
+    }
+    K* key = reinterpret_cast<K*>(sc.key.data());
+    K* tkey = reinterpret_cast<K*>(sc.tkey.data());
+    uint32_t* pos = sc.pos.data();
+    uint32_t* tpos = sc.tpos.data();
+    parallel_for(nnz, threads, [&](uint64_t lo, uint64_t hi) {
+        for (uint64_t k = lo; k < hi; ++k) {
+            const uint32_t* p = coo + k * N;
+            K v = (K)p[n];
+            for (int f = 0; f < nf; ++f) v = fbits[f] ? ((v << fbits[f]) | (K)p[cyc[f]]) : v;
+            key[k] = v;
+            pos[k] = (uint32_t)k;
+        }
+    });
+    if (radix_sort_pairs(key, pos, tkey, tpos, nnz, row_shift + row_bits, threads)) {
+        std::swap(key, tkey);
+        std::swap(pos, tpos);
+    }
+
+    auto row_of = [&](uint64_t k) -> uint64_t { return row_bits ? (uint64_t)(key[k] >> row_shift) : 0; };
+    start.assign(I + 1, nnz);
+    const bool use_hot = hot && !hot->empty() && !(*hot)[0].slot.empty();
+    parallel_for(nnz, threads, [&](uint64_t lo, uint64_t hi) {
+        for (uint64_t k = lo; k < hi; ++k) {
+            // rows from just after the previous nonzero's row up to this one start here
+            const uint64_t r = row_of(k);
+            for (uint64_t i = k ? row_of(k - 1) + 1 : 0; i <= r; ++i) start[i] = k;
+            for (int f = 0; f < nf; ++f) {
+                const uint32_t mask = fbits[f] ? (uint32_t)((1ull << fbits[f]) - 1) : 0u;
+                const uint32_t v = (uint32_t)(key[k] >> fshift[f]) & mask;
+                const int32_t sl = use_hot ? (*hot)[cyc[f]].slot[v] : -1;
+                out.idx[fslot[f]][k] = sl >= 0 ? (kHotBit | (uint32_t)sl) : v;
+            }
+            out.val[k] = vals[pos[k]];
+            if (keep_src_pos) out.src_pos[k] = pos[k];
+        }
+    });
+}
+
 }  // namespace
 
 std::string validate_coo(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N, bool* range_error)
@@ -72,13 +199,26 @@ std::string validate_coo(const uint32_t* coo, uint64_t nnz, const uint32_t* dims
             return "dims[" + std::to_string(m) + "] must be in [1, 2^31-1]";
     if (nnz >= (1ull << 32)) return "nnz must be below 2^32";
     if (nnz && !coo) return "coo_idx is NULL";
-    for (uint64_t k = 0; k < nnz; ++k)
-        for (int m = 0; m < N; ++m)
-            if (coo[k * (uint64_t)N + m] >= dims[m]) {
-                *range_error = true;
-                return "nonzero " + std::to_string(k) + ": coordinate " + std::to_string(coo[k * (uint64_t)N + m]) +
-                       " >= dims[" + std::to_string(m) + "] = " + std::to_string(dims[m]);
-            }
+    // the first offending nonzero, found by chunks in parallel
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int T = nnz < (1u << 16) ? 1 : (int)std::max(1u, std::min(hw, 32u));
+    std::vector<uint64_t> bad(T, nnz);
+    parallel_chunks(nnz, T, [&](int t, uint64_t lo, uint64_t hi) {
+        for (uint64_t k = lo; k < hi && bad[t] == nnz; ++k)
+            for (int m = 0; m < N; ++m)
+                if (coo[k * (uint64_t)N + m] >= dims[m]) {
+                    bad[t] = k;
+                    break;
+                }
+    });
+    const uint64_t k = *std::min_element(bad.begin(), bad.end());
+    if (k == nnz) return "";
+    for (int m = 0; m < N; ++m)
+        if (coo[k * (uint64_t)N + m] >= dims[m]) {
+            *range_error = true;
+            return "nonzero " + std::to_string(k) + ": coordinate " + std::to_string(coo[k * (uint64_t)N + m]) +
+                   " >= dims[" + std::to_string(m) + "] = " + std::to_string(dims[m]);
+        }
     return "";
 }
 
@@ -91,6 +231,7 @@ uint64_t mode_device_bytes(uint64_t nnz, int N, uint64_t I_mode)
 std::vector<HotSet> select_hot_rows(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N, uint32_t k)
 {
     std::vector<HotSet> hs(N);
+    if (k == 0) return hs;   // empty slot tables: no row is hot
     for (int m = 0; m < N; ++m) {
         std::vector<uint64_t> deg(dims[m], 0);
         for (uint64_t e = 0; e < nnz; ++e) deg[coo[e * N + m]]++;
@@ -109,54 +250,56 @@ std::vector<HotSet> select_hot_rows(const uint32_t* coo, uint64_t nnz, const uin
 }
 
 void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const uint32_t* dims, int N, int mode,
-                     bool keep_src_pos, int threads, const std::vector<HotSet>* hot, HostMode& out)
+                     bool keep_src_pos, int threads, const std::vector<HotSet>* hot, HostMode& out,
+                     BuildScratch* scratch)
 {
     const int n = mode;
     const uint64_t I = dims[n];
-    out = HostMode{};
     out.mode = n;
+    out.in_modes.clear();
     for (int m = 0; m < N; ++m)
         if (m != n) out.in_modes.push_back(m);
     const int n_in = N - 1;
     out.nnz = nnz;
     out.nnz_pad = (nnz + 31) / 32 * 32;
-
-    // 1. Stable counting sort by output index: rows in increasing order,
-    //    caller's order inside each row.
-    std::vector<uint64_t> start(I + 1, 0);
-    for (uint64_t k = 0; k < nnz; ++k) start[coo[k * N + n] + 1]++;
-    for (uint64_t i = 0; i < I; ++i) start[i + 1] += start[i];
-    std::vector<uint32_t> perm(nnz);
-    {
-        std::vector<uint64_t> fill(start.begin(), start.end() - 1);
-        for (uint64_t k = 0; k < nnz; ++k) perm[fill[coo[k * N + n]]++] = (uint32_t)k;
+    // Buffers keep their capacity from an earlier mode; only the padding is cleared.
+    out.idx.resize(n_in);
+    for (auto& v : out.idx) {
+        v.resize(out.nnz_pad);
+        std::fill(v.begin() + nnz, v.end(), 0u);
     }
+    out.val.resize(out.nnz_pad);
+    std::fill(out.val.begin() + nnz, out.val.end(), 0.0f);
+    out.src_pos.resize(keep_src_pos ? nnz : 0);
+    out.row_id.clear();
+    out.empty_rows.clear();
 
-    // 2. Inside each row: by the other indices in cyclic order, then by input position.
     std::vector<int> cyc;
     for (int j = 1; j < N; ++j) cyc.push_back((n + j) % N);
-    int total_bits = 0;
-    for (int m : cyc) total_bits += bits_for(dims[m]);
-    if (total_bits <= 64) {
-        std::vector<std::pair<uint64_t, uint32_t>> rec(nnz);
-        std::vector<int> sh;
-        for (int m : cyc) sh.push_back(bits_for(dims[m]));
-        parallel_for(nnz, threads, [&](uint64_t lo, uint64_t hi) {
-            for (uint64_t k = lo; k < hi; ++k) {
-                const uint32_t* p = coo + (uint64_t)perm[k] * N;
-                uint64_t key = 0;
-                for (size_t j = 0; j < cyc.size(); ++j) key = (sh[j] ? (key << sh[j]) : key) | p[cyc[j]];
-                rec[k] = {key, perm[k]};
-            }
-        });
-        parallel_rows(start, threads, [&](uint64_t r0, uint64_t r1) {
-            for (uint64_t i = r0; i < r1; ++i)
-                if (start[i + 1] - start[i] > 1) std::sort(rec.begin() + start[i], rec.begin() + start[i + 1]);
-        });
-        parallel_for(nnz, threads, [&](uint64_t lo, uint64_t hi) {
-            for (uint64_t k = lo; k < hi; ++k) perm[k] = rec[k].second;
-        });
+    int key_bits = bits_for(dims[n]);
+    for (int m : cyc) key_bits += bits_for(dims[m]);
+    std::vector<uint64_t> start;
+    if (key_bits <= 128) {
+        // 1-3. Radix sort of packed (row, cyclic others) keys; indices decoded from the keys.
+        BuildScratch local;
+        BuildScratch& sc = scratch ? *scratch : local;
+        if (key_bits <= 64)
+            sort_by_packed_key<uint64_t>(coo, vals, nnz, dims, N, n, cyc, threads, hot, keep_src_pos, sc, start, out);
+        else
+            sort_by_packed_key<unsigned __int128>(coo, vals, nnz, dims, N, n, cyc, threads, hot, keep_src_pos, sc,
+                                                  start, out);
     } else {
+        // 1. Stable counting sort by output index: rows in increasing order,
+        //    caller's order inside each row.
+        start.assign(I + 1, 0);
+        for (uint64_t k = 0; k < nnz; ++k) start[coo[k * N + n] + 1]++;
+        for (uint64_t i = 0; i < I; ++i) start[i + 1] += start[i];
+        std::vector<uint32_t> perm(nnz);
+        {
+            std::vector<uint64_t> fill(start.begin(), start.end() - 1);
+            for (uint64_t k = 0; k < nnz; ++k) perm[fill[coo[k * N + n]]++] = (uint32_t)k;
+        }
+        // 2. Inside each row: by the other indices in cyclic order, then by input position.
         parallel_rows(start, threads, [&](uint64_t r0, uint64_t r1) {
             for (uint64_t i = r0; i < r1; ++i) {
                 if (start[i + 1] - start[i] < 2) continue;
@@ -169,25 +312,22 @@ void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const
                 });
             }
         });
-    }
-
-    // 3. Structure-of-arrays copy, zero padded to a multiple of 32.
-    out.idx.assign(n_in, std::vector<uint32_t>(out.nnz_pad, 0u));
-    out.val.assign(out.nnz_pad, 0.0f);
-    if (keep_src_pos) out.src_pos.resize(nnz);
-    parallel_for(nnz, threads, [&](uint64_t lo, uint64_t hi) {
-        for (uint64_t k = lo; k < hi; ++k) {
-            const uint64_t p = perm[k];
-            for (int j = 0; j < n_in; ++j) {
-                const int m = out.in_modes[j];
-                const uint32_t v = coo[p * N + m];
-                const int32_t sl = hot ? (*hot)[m].slot[v] : -1;
-                out.idx[j][k] = sl >= 0 ? (kHotBit | (uint32_t)sl) : v;
+        // 3. Structure-of-arrays copy gathered from the caller's coordinates.
+        const bool use_hot = hot && !hot->empty() && !(*hot)[0].slot.empty();
+        parallel_for(nnz, threads, [&](uint64_t lo, uint64_t hi) {
+            for (uint64_t k = lo; k < hi; ++k) {
+                const uint64_t p = perm[k];
+                for (int j = 0; j < n_in; ++j) {
+                    const int m = out.in_modes[j];
+                    const uint32_t v = coo[p * N + m];
+                    const int32_t sl = use_hot ? (*hot)[m].slot[v] : -1;
+                    out.idx[j][k] = sl >= 0 ? (kHotBit | (uint32_t)sl) : v;
+                }
+                out.val[k] = vals[p];
+                if (keep_src_pos) out.src_pos[k] = p;
             }
-            out.val[k] = vals[p];
-            if (keep_src_pos) out.src_pos[k] = p;
-        }
-    });
+        });
+    }
 
     // 4. Nonempty rows (row ordinal -> output row) and empty rows.
     for (uint64_t i = 0; i < I; ++i) {

@@ -3,10 +3,39 @@
 
 #include <stdint.h>
 
+#include <memory>
+#include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace mk {
+
+// An allocator that leaves trivially constructible elements uninitialised on
+// resize, so large buffers are first touched by the threads that fill them
+// instead of being zeroed by one thread.
+template <class T>
+struct UninitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = UninitAlloc<U>;
+    };
+    UninitAlloc() = default;
+    template <class U>
+    UninitAlloc(const UninitAlloc<U>&) noexcept {}
+    template <class U>
+    void construct(U* p) noexcept
+    {
+        ::new ((void*)p) U;
+    }
+    template <class U, class... A>
+    void construct(U* p, A&&... a)
+    {
+        ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using buf = std::vector<T, UninitAlloc<T>>;
 
 // One mode copy in host memory.  Nonzeros are ordered by (output index, then
 // the other indices in cyclic order n+1, ..., N-1, 0, ..., n-1, then position
@@ -17,12 +46,18 @@ struct HostMode {
     int mode = 0;
     std::vector<int> in_modes;                 // the N-1 input modes, increasing
     uint64_t nnz = 0, nnz_pad = 0, nrows_nz = 0, nempty = 0;
-    std::vector<std::vector<uint32_t>> idx;    // [n_in][nnz_pad]
-    std::vector<float> val;                    // [nnz_pad]
+    std::vector<buf<uint32_t>> idx;            // [n_in][nnz_pad]
+    buf<float> val;                            // [nnz_pad]
     std::vector<uint32_t> winfo;               // [2 * nnz_pad / 32]
     std::vector<uint32_t> row_id;              // [nrows_nz]
     std::vector<uint32_t> empty_rows;          // [nempty]
-    std::vector<uint64_t> src_pos;             // [nnz] (kept only on request)
+    buf<uint64_t> src_pos;                     // [nnz] (kept only on request)
+};
+
+// Sort buffers of a build, kept across its modes so their pages are mapped once.
+struct BuildScratch {
+    buf<unsigned __int128> key, tkey;   // packed coordinate keys (64-bit keys use the first half)
+    buf<uint32_t> pos, tpos;            // input positions carried with the keys
 };
 
 // Coordinates of rows served from the on-chip cache are stored as
@@ -42,9 +77,11 @@ std::vector<HotSet> select_hot_rows(const uint32_t* coo, uint64_t nnz, const uin
 // *range_error is set when the failure is a coordinate out of range.
 std::string validate_coo(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N, bool* range_error);
 
-// Build the copy for output mode `mode`.  `threads` host threads are used.
+// Build the copy for output mode `mode` into `out`, reusing its buffers.
+// `threads` host threads are used; `scratch` (may be null) is reused across calls.
 void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const uint32_t* dims, int N, int mode,
-                     bool keep_src_pos, int threads, const std::vector<HotSet>* hot, HostMode& out);
+                     bool keep_src_pos, int threads, const std::vector<HotSet>* hot, HostMode& out,
+                     BuildScratch* scratch = nullptr);
 
 // Bytes of one mode copy on the device (arrays only, without alignment padding).
 uint64_t mode_device_bytes(uint64_t nnz, int N, uint64_t I_mode);

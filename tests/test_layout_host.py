@@ -16,8 +16,8 @@ from tests import pins
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mttkrp.h")
 
 
-def host_layout(idx, val, dims):
-    return capi.mttkrp_layout_build(idx, val, dims, opts=dict(host_only=1))
+def host_layout(idx, val, dims, hot_rows=0):
+    return capi.mttkrp_layout_build(idx, val, dims, opts=dict(host_only=1, hot_rows=hot_rows))
 
 
 def row_of_each_nonzero(v):
@@ -139,7 +139,7 @@ def test_layout_empty_tensor():
 
 
 def test_layout_wide_keys():
-    """Other-mode indices wider than 64 bits in total: the generic comparison path."""
+    """Packed coordinate keys wider than 64 bits: the 128-bit key sort."""
     rng = np.random.default_rng(4)
     dims = (50, 100_000, 100_000, 100_000, 100_000)  # 4 x 17 bits > 64
     nnz = 400
@@ -149,6 +149,38 @@ def test_layout_wide_keys():
     h = host_layout(idx, val, dims)
     for n in range(5):
         check_view(idx, val, dims, capi.mttkrp_layout_view(h, n), n)
+
+
+def test_layout_keys_over_128_bits():
+    """Keys wider than 128 bits (8 modes of 2^17): the comparison sort."""
+    rng = np.random.default_rng(5)
+    dims = (1 << 17,) * 8
+    nnz = 300
+    idx = np.stack([rng.integers(0, 3 if m == 1 else d, nnz) for m, d in enumerate(dims)], axis=1).astype(np.uint32)
+    idx[::5, 2] = idx[0, 2]
+    val = rng.random(nnz).astype(np.float32)
+    h = host_layout(idx, val, dims)
+    for n in range(8):
+        check_view(idx, val, dims, capi.mttkrp_layout_view(h, n), n)
+
+
+@pytest.mark.parametrize("hot_rows", [0, 64])
+@pytest.mark.parametrize("dims", [(300, 200, 150), (9000, 70_000, 100_000, 120, 100_000)])
+def test_layout_threaded_sort(dims, hot_rows):
+    """Enough nonzeros for the multithreaded sort (64- and 128-bit keys):
+    Zipf-skewed rows, one row holding a quarter of the nonzeros, duplicates;
+    with and without hot-row slots in the decoded indices."""
+    rng = np.random.default_rng(6)
+    nnz = 150_000
+    idx = np.stack([np.minimum(rng.zipf(1.3, nnz) - 1, d - 1) for d in dims], axis=1).astype(np.uint32)
+    idx[: nnz // 4, 0] = 7
+    idx[1::97] = idx[0::97][: idx[1::97].shape[0]]
+    val = rng.random(nnz).astype(np.float32)
+    h = host_layout(idx, val, dims, hot_rows)
+    for n in range(len(dims)):
+        v = capi.mttkrp_layout_view(h, n)
+        assert (v["nhot"] > 0) == (hot_rows > 0)     # capped by LDS room at 5 modes
+        check_view(idx, val, dims, v, n)
 
 
 def test_errors():

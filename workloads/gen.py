@@ -103,10 +103,18 @@ def _keys(coords: np.ndarray, dims: Sequence[int]) -> np.ndarray:
 def distinct_coords(samplers, dims: Sequence[int], nnz: int, rng: np.random.Generator,
                     progress: Optional[Callable[[str], None]] = None) -> np.ndarray:
     """Draw-and-top-up until exactly ``nnz`` distinct coordinates remain.
-    ``progress`` (optional) receives a line after every draw round."""
+    ``progress`` (optional) receives a line after every draw round.
+
+    Each round draws the shortfall, keeps the first draw of every coordinate
+    not yet accepted, and appends those in draw order.  Accepted coordinates
+    are remembered in a bitmap over the linear index when the index space
+    fits in 2^33 bits (1 GiB), else in a sorted key array; both give the same
+    result, the bitmap in time proportional to each round's draws."""
     N = len(dims)
     accepted = []
-    seen = None  # sorted keys of accepted coordinates
+    space = math.prod(int(d) for d in dims)
+    bitmap = np.zeros((space + 7) // 8, dtype=np.uint8) if space <= (1 << 33) else None
+    seen = None  # sorted keys of accepted coordinates (no bitmap)
     need = nnz
     while need > 0:
         c = np.empty((need, N), dtype=np.int64)
@@ -116,19 +124,21 @@ def distinct_coords(samplers, dims: Sequence[int], nnz: int, rng: np.random.Gene
                 progress(f"drew {need} indices of mode {m}")
         k = _keys(c, dims)
         u, first = np.unique(k, return_index=True)
-        if seen is not None and seen.shape[0]:
-            pos = np.searchsorted(seen, u)
-            hit = np.zeros(u.shape[0], dtype=bool)
-            ok = pos < seen.shape[0]
-            hit[ok] = seen[pos[ok]] == u[ok]
-            u, first = u[~hit], first[~hit]
+        if bitmap is not None:
+            byte, bit = u >> np.uint64(3), (u & np.uint64(7)).astype(np.uint8)
+            fresh = (bitmap[byte] >> bit) & 1 == 0
+            u, first = u[fresh], first[fresh]
+            np.bitwise_or.at(bitmap, byte[fresh], np.left_shift(np.uint8(1), bit[fresh]))
+        else:
+            if seen is not None and seen.shape[0]:
+                pos = np.searchsorted(seen, u)
+                hit = np.zeros(u.shape[0], dtype=bool)
+                ok = pos < seen.shape[0]
+                hit[ok] = seen[pos[ok]] == u[ok]
+                u, first = u[~hit], first[~hit]
+            seen = u if seen is None else np.insert(seen, np.searchsorted(seen, u), u)
         first.sort()
         accepted.append(c[first])
-        if seen is None:
-            seen = np.sort(k[first])
-        else:
-            newk = np.sort(k[first])
-            seen = np.insert(seen, np.searchsorted(seen, newk), newk)
         need -= first.shape[0]
         if progress is not None:
             progress(f"distinct coordinates: {nnz - need} of {nnz}")

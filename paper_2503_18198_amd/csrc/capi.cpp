@@ -34,12 +34,6 @@ constexpr int kAlsBlocks = 512;         // row blocks of the CP-ALS reductions
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int host_threads()
-{
-    unsigned t = std::thread::hardware_concurrency();
-    return (int)std::max(1u, std::min(t, 32u));
-}
-
 bool r_supported(int R) { return R == 16 || R == 32 || R == 64; }
 
 struct Workspace {
@@ -217,7 +211,7 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     h->lds_limit = lds_limit;
     h->device = dev_id;
 
-    const int threads = host_threads();
+    const int threads = mk::host_threads();
     std::vector<mk::HotSet> hot = mk::select_hot_rows(coo_idx, nnz, dims, N, nhot);
     mk::BuildScratch scratch;
     if (h->host_only) {

@@ -3,8 +3,14 @@
 // of packed coordinate keys, one pass per 11 key bits.
 #include "layout.h"
 
+#include <sched.h>
+
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <deque>
 #include <functional>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <utility>
@@ -13,22 +19,118 @@
 
 namespace mk {
 
+int host_threads()
+{
+    int n = 0;
+    cpu_set_t set;
+    if (sched_getaffinity(0, sizeof(set), &set) == 0) n = CPU_COUNT(&set);
+    if (n <= 0) n = (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(n, 32));
+}
+
 namespace {
+
+// Host worker threads shared by every layout build in the process.  A caller
+// queues its tasks, runs the first itself and then runs queued tasks (its own
+// or a concurrent caller's) until all of its own have finished, so builds on
+// several caller threads share the workers and none waits idle on another's.
+class TaskPool {
+public:
+    static TaskPool& instance()
+    {
+        static TaskPool* pool = new TaskPool(host_threads() - 1);   // lives until the process ends
+        return *pool;
+    }
+
+    void run(int ntasks, const std::function<void(int)>& f)
+    {
+        if (ntasks <= 1 || workers_.empty()) {
+            for (int i = 0; i < ntasks; ++i) f(i);
+            return;
+        }
+        std::atomic<int> left(ntasks);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (int i = 1; i < ntasks; ++i) queue_.push_back(Task{&f, i, &left});
+        }
+        work_cv_.notify_all();
+        f(0);
+        finish(left);
+        while (left.load(std::memory_order_acquire) > 0) {
+            Task t;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                if (queue_.empty()) {
+                    done_cv_.wait(lk, [&] { return left.load(std::memory_order_acquire) == 0 || !queue_.empty(); });
+                    continue;
+                }
+                t = queue_.front();
+                queue_.pop_front();
+            }
+            (*t.f)(t.i);
+            finish(*t.left);
+        }
+    }
+
+private:
+    struct Task {
+        const std::function<void(int)>* f = nullptr;
+        int i = 0;
+        std::atomic<int>* left = nullptr;
+    };
+
+    explicit TaskPool(int nworkers)
+    {
+        for (int w = 0; w < nworkers; ++w) workers_.emplace_back([this] { work(); });
+        for (auto& t : workers_) t.detach();
+    }
+
+    void finish(std::atomic<int>& left)
+    {
+        if (left.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+            std::lock_guard<std::mutex> lk(mu_);   // the waiting caller checks `left` under this lock
+            done_cv_.notify_all();
+        }
+    }
+
+    void work()
+    {
+        for (;;) {
+            Task t;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                work_cv_.wait(lk, [&] { return !queue_.empty(); });
+                t = queue_.front();
+                queue_.pop_front();
+            }
+            (*t.f)(t.i);
+            finish(*t.left);
+        }
+    }
+
+    std::mutex mu_;
+    std::condition_variable work_cv_, done_cv_;
+    std::deque<Task> queue_;
+    std::vector<std::thread> workers_;
+};
+
+// Chunks of at least 32K items, at most one per thread.
+int chunks_for(uint64_t n, int threads)
+{
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)std::max(threads, 1), n >> 15));
+}
+
+// Chunk t of `chunks` equal ranges of [0, n); the same split in every call.
+void parallel_chunks(uint64_t n, int chunks, const std::function<void(int, uint64_t, uint64_t)>& f)
+{
+    TaskPool::instance().run(chunks, [&](int t) {
+        f(t, n * (uint64_t)t / (uint64_t)chunks, n * (uint64_t)(t + 1) / (uint64_t)chunks);
+    });
+}
 
 void parallel_for(uint64_t n, int threads, const std::function<void(uint64_t, uint64_t)>& f)
 {
-    if (threads <= 1 || n < (1u << 16)) {
-        f(0, n);
-        return;
-    }
-    std::vector<std::thread> ts;
-    ts.reserve(threads);
-    for (int t = 0; t < threads; ++t) {
-        const uint64_t lo = n * (uint64_t)t / (uint64_t)threads;
-        const uint64_t hi = n * (uint64_t)(t + 1) / (uint64_t)threads;
-        ts.emplace_back(f, lo, hi);
-    }
-    for (auto& t : ts) t.join();
+    parallel_chunks(n, chunks_for(n, threads), [&](int, uint64_t lo, uint64_t hi) { f(lo, hi); });
 }
 
 // Split rows [0, I) into `threads` ranges of about equal nonzero count.
@@ -37,21 +139,17 @@ void parallel_rows(const std::vector<uint64_t>& start, int threads,
 {
     const uint64_t I = start.size() - 1;
     const uint64_t nnz = start[I];
-    if (threads <= 1 || nnz < (1u << 16)) {
-        f(0, I);
-        return;
-    }
-    std::vector<uint64_t> cut(threads + 1, I);
+    const int T = chunks_for(nnz, threads);
+    std::vector<uint64_t> cut(T + 1, I);
     cut[0] = 0;
-    for (int t = 1; t < threads; ++t) {
-        const uint64_t target = nnz * (uint64_t)t / (uint64_t)threads;
+    for (int t = 1; t < T; ++t) {
+        const uint64_t target = nnz * (uint64_t)t / (uint64_t)T;
         cut[t] = (uint64_t)(std::upper_bound(start.begin(), start.end(), target) - start.begin()) - 1;
         cut[t] = std::max(cut[t], cut[t - 1]);
     }
-    std::vector<std::thread> ts;
-    for (int t = 0; t < threads; ++t)
-        if (cut[t + 1] > cut[t]) ts.emplace_back(f, cut[t], cut[t + 1]);
-    for (auto& t : ts) t.join();
+    TaskPool::instance().run(T, [&](int t) {
+        if (cut[t + 1] > cut[t]) f(cut[t], cut[t + 1]);
+    });
 }
 
 int bits_for(uint32_t d)
@@ -59,20 +157,6 @@ int bits_for(uint32_t d)
     int b = 0;
     while ((1ull << b) < (uint64_t)d) ++b;
     return b;
-}
-
-// Chunk t of `chunks` equal ranges of [0, n); the same split in every call.
-void parallel_chunks(uint64_t n, int chunks, const std::function<void(int, uint64_t, uint64_t)>& f)
-{
-    if (chunks <= 1) {
-        f(0, 0, n);
-        return;
-    }
-    std::vector<std::thread> ts;
-    ts.reserve(chunks);
-    for (int t = 0; t < chunks; ++t)
-        ts.emplace_back(f, t, n * (uint64_t)t / (uint64_t)chunks, n * (uint64_t)(t + 1) / (uint64_t)chunks);
-    for (auto& t : ts) t.join();
 }
 
 // Stable least-significant-digit radix sort of (key, pos) pairs on the low
@@ -85,7 +169,7 @@ bool radix_sort_pairs(K* key, uint32_t* pos, K* tkey, uint32_t* tpos, uint64_t n
 {
     constexpr int kDigit = 11;   // 2048 buckets: fewer passes than bytes, histograms still in L1
     constexpr uint32_t kBuckets = 1u << kDigit;
-    const int T = (threads <= 1 || n < (1u << 16)) ? 1 : threads;
+    const int T = chunks_for(n, threads);
     std::vector<uint64_t> hist((size_t)T * kBuckets);
     bool swapped = false;
     for (int shift = 0; shift < bits; shift += kDigit) {
@@ -200,8 +284,7 @@ std::string validate_coo(const uint32_t* coo, uint64_t nnz, const uint32_t* dims
     if (nnz >= (1ull << 32)) return "nnz must be below 2^32";
     if (nnz && !coo) return "coo_idx is NULL";
     // the first offending nonzero, found by chunks in parallel
-    const unsigned hw = std::thread::hardware_concurrency();
-    const int T = nnz < (1u << 16) ? 1 : (int)std::max(1u, std::min(hw, 32u));
+    const int T = chunks_for(nnz, host_threads());
     std::vector<uint64_t> bad(T, nnz);
     parallel_chunks(nnz, T, [&](int t, uint64_t lo, uint64_t hi) {
         for (uint64_t k = lo; k < hi && bad[t] == nnz; ++k)

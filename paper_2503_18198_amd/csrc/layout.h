@@ -73,6 +73,9 @@ struct HotSet {
 
 std::vector<HotSet> select_hot_rows(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N, uint32_t k);
 
+// Host threads for layout builds: the CPUs this process may run on, at most 32.
+int host_threads();
+
 // Validate a COO tensor.  Returns an empty string when valid, else a message;
 // *range_error is set when the failure is a coordinate out of range.
 std::string validate_coo(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N, bool* range_error);

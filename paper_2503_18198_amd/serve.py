@@ -5,16 +5,22 @@ Jobs (a sparse tensor, a rank, a stopping rule) arrive over time.  The loop
 * admits waiting jobs in arrival order while a slot is free and their device
   footprint (the N mode copies, workspace, factors; ``mttkrp_footprint``)
   fits in what is left of the HBM budget; state then stays on the device;
-* runs one scheduler step at a time: one CP-ALS sweep for every active job,
-  jobs with the same (N, R) grouped into one batch so their per-mode MTTKRPs
-  share one launch pair (``cpd_als_batch_iter_async``);
-* after each step reads every active job's fit, retires jobs whose fit
+* groups the active jobs by the executor's group key ((N, R) on the GPU, so
+  a group's per-mode MTTKRPs share one launch pair through
+  ``cpd_als_batch_iter_async``) and keeps at most one sweep of each group in
+  flight: a group whose sweep has completed is stepped again at once, without
+  waiting for slower groups;
+* when a group's sweep completes, reads its jobs' fits, retires jobs whose fit
   changed by less than ``tol`` or that reached ``max_iters``, releases their
   memory and admits waiting jobs into the freed room.
 
-Requests that arrive while others run are admitted at the next step, so new
-and old jobs share the GPU.  A tensor's results do not depend on which other
-jobs share its steps: the batched sweep is bitwise the single-tensor sweep.
+Requests that arrive while others run are admitted at once and join their
+group's next sweep, so new and old jobs share the GPU.  With
+``build_threads`` > 0 a job's device state (its layout build, a host sort)
+is made on a worker thread, so it overlaps the sweeps in flight; memory is
+reserved when the job is admitted, in arrival order.  A tensor's results do
+not depend on which other jobs share its sweeps: the batched sweep is bitwise
+the single-tensor sweep.
 
 The executor is an interface so the scheduling logic can be tested on the
 CPU with a fake one.  Latency = completion time - arrival time.
@@ -22,8 +28,10 @@ CPU with a fake one.  Latency = completion time - arrival time.
 
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import threading
 import time
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
@@ -69,6 +77,25 @@ class Executor:
         """One CP-ALS sweep for every slot; returns their fits (in order)."""
         raise NotImplementedError
 
+    def group_key(self, slot):
+        """Slots with equal keys are swept together; groups are stepped
+        independently.  By default every slot is in one group, so all
+        active jobs step in lockstep."""
+        return None
+
+    def launch(self, key, slots: Sequence):
+        """Start one sweep of one group's slots; returns a token for poll().
+        The default runs step() to completion."""
+        return self.step(slots)
+
+    def poll(self, token) -> Optional[List[float]]:
+        """The fits of a launched sweep (in slot order), or None while it runs."""
+        return token
+
+    def wait(self, tokens: Sequence, timeout_s: Optional[float]) -> None:
+        """Return once one of the launched sweeps has completed or timeout_s
+        (None: no limit) has passed.  Default: sweeps complete in launch()."""
+
     def release(self, slot):
         """Free the slot's device memory; returns the job's result."""
         raise NotImplementedError
@@ -83,8 +110,13 @@ def percentile(values: Sequence[float], q: float) -> float:
 
 class CpdServer:
     def __init__(self, executor: Executor, hbm_budget_bytes: int, max_slots: int = 64,
-                 clock: Optional[Callable[[], float]] = None, sleep: Optional[Callable[[float], None]] = None):
+                 clock: Optional[Callable[[], float]] = None, sleep: Optional[Callable[[float], None]] = None,
+                 build_threads: int = 0, on_retire: Optional[Callable[[ServeJob], None]] = None):
         self.ex = executor
+        self.on_retire = on_retire
+        self.build_threads = int(build_threads)
+        self.admit_s = 0.0              # host seconds spent in executor.admit, summed over jobs
+        self._admit_lock = threading.Lock()
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self.clock = clock or time.monotonic
@@ -94,20 +126,36 @@ class CpdServer:
         self.steps = 0
         self.log: List[Tuple[float, str, int]] = []
 
+    def _admit(self, job: ServeJob):
+        t = time.perf_counter()
+        slot = self.ex.admit(job)
+        with self._admit_lock:
+            self.admit_s += time.perf_counter() - t
+        return slot
+
     def run(self, jobs: Sequence[ServeJob]) -> Dict[str, object]:
+        if self.build_threads > 0:
+            with concurrent.futures.ThreadPoolExecutor(self.build_threads) as pool:
+                return self._run(jobs, pool)
+        return self._run(jobs, None)
+
+    def _run(self, jobs: Sequence[ServeJob], pool) -> Dict[str, object]:
         pending = sorted(jobs, key=lambda j: (j.arrival_s, j.job_id))
         waiting: List[ServeJob] = []
-        active: List[Tuple[ServeJob, object]] = []
+        ready: Dict[object, List[Tuple[ServeJob, object]]] = {}     # group -> members between sweeps
+        flight: Dict[object, Tuple[object, List[Tuple[ServeJob, object]]]] = {}   # group -> (token, members)
+        building: List[Tuple[ServeJob, concurrent.futures.Future]] = []
+        n_active = 0
         done: List[ServeJob] = []
         t0 = self.clock()
         pi = 0
-        while pi < len(pending) or waiting or active:
+        while pi < len(pending) or waiting or n_active:
             now = self.clock() - t0
             while pi < len(pending) and pending[pi].arrival_s <= now:
                 waiting.append(pending[pi])
                 pi += 1
             # admission in arrival order, by slot and by memory
-            while waiting and len(active) < self.max_slots:
+            while waiting and n_active < self.max_slots:
                 job = waiting[0]
                 need = self.ex.footprint(job)
                 if need > self.budget:
@@ -120,40 +168,81 @@ class CpdServer:
                 if self.in_use + need > self.budget:
                     break
                 waiting.pop(0)
-                slot = self.ex.admit(job)
-                job.admitted_s = self.clock() - t0
-                job.status = "running"
                 self.in_use += need
                 self.peak_in_use = max(self.peak_in_use, self.in_use)
-                active.append((job, slot))
+                n_active += 1
+                job.status = "running"
+                if pool is not None:
+                    job.admitted_s = self.clock() - t0
+                    building.append((job, pool.submit(self._admit, job)))
+                else:
+                    slot = self._admit(job)
+                    job.admitted_s = self.clock() - t0
+                    ready.setdefault(self.ex.group_key(slot), []).append((job, slot))
                 self.log.append((job.admitted_s, "admit", job.job_id))
-            if not active:
+            if building:
+                still_building = []
+                for job, fut in building:
+                    if fut.done():
+                        slot = fut.result()
+                        ready.setdefault(self.ex.group_key(slot), []).append((job, slot))
+                    else:
+                        still_building.append((job, fut))
+                building = still_building
+            if not n_active:
                 if pi < len(pending):
                     self.sleep(max(0.0, pending[pi].arrival_s - (self.clock() - t0)))
                 continue
-            fits = self.ex.step([s for _, s in active])
-            self.steps += 1
-            still = []
-            for (job, slot), f in zip(active, fits):
-                prev = job.fits[-1] if job.fits else None
-                job.fits.append(float(f))
-                job.iters += 1
-                converged = prev is not None and abs(f - prev) < job.tol
-                if not math.isfinite(f):
-                    job.status = "failed: non-finite fit"
-                elif converged:
-                    job.status = "converged"
-                elif job.iters >= job.max_iters:
-                    job.status = "max_iters"
-                if job.status != "running":
-                    job.result = self.ex.release(slot)
-                    self.in_use -= self.ex.footprint(job)
-                    job.finished_s = self.clock() - t0
-                    done.append(job)
-                    self.log.append((job.finished_s, "retire", job.job_id))
+            # every group with no sweep in flight starts its next one
+            for key in [k for k in ready if k not in flight]:
+                members = ready.pop(key)
+                flight[key] = (self.ex.launch(key, [s for _, s in members]), members)
+                self.steps += 1
+            completed = False
+            for key in list(flight):
+                token, members = flight[key]
+                fits = self.ex.poll(token)
+                if fits is None:
+                    continue
+                del flight[key]
+                completed = True
+                still = []
+                for (job, slot), f in zip(members, fits):
+                    prev = job.fits[-1] if job.fits else None
+                    job.fits.append(float(f))
+                    job.iters += 1
+                    converged = prev is not None and abs(f - prev) < job.tol
+                    if not math.isfinite(f):
+                        job.status = "failed: non-finite fit"
+                    elif converged:
+                        job.status = "converged"
+                    elif job.iters >= job.max_iters:
+                        job.status = "max_iters"
+                    if job.status != "running":
+                        job.result = self.ex.release(slot)
+                        self.in_use -= self.ex.footprint(job)
+                        n_active -= 1
+                        job.finished_s = self.clock() - t0
+                        done.append(job)
+                        self.log.append((job.finished_s, "retire", job.job_id))
+                        if self.on_retire is not None:
+                            self.on_retire(job)
+                    else:
+                        still.append((job, slot))
+                if still:
+                    # survivors keep their order ahead of jobs admitted meanwhile
+                    ready[key] = still + ready.get(key, [])
+            if not completed and (flight or building):
+                timeout = pending[pi].arrival_s - (self.clock() - t0) if pi < len(pending) else None
+                timeout = None if timeout is None else max(0.0, timeout)
+                if flight:
+                    if building:
+                        # builds finish on their own threads: look at them every 0.2 ms
+                        timeout = 2e-4 if timeout is None else min(timeout, 2e-4)
+                    self.ex.wait([t for t, _ in flight.values()], timeout)
                 else:
-                    still.append((job, slot))
-            active = still
+                    concurrent.futures.wait([f for _, f in building], timeout,
+                                            return_when=concurrent.futures.FIRST_COMPLETED)
         return self.metrics(done, self.clock() - t0)
 
     def metrics(self, done: Sequence[ServeJob], makespan: float) -> Dict[str, object]:
@@ -170,16 +259,19 @@ class CpdServer:
             "p99_latency_s": percentile(lat, 99),
             "mean_latency_s": float(np.mean(lat)) if lat else math.nan,
             "steps": self.steps,
+            "admit_s_total": self.admit_s,
             "peak_hbm_bytes": self.peak_in_use,
         }
 
 
 class GpuExecutor(Executor):
     """Device state per job: layout handle, fp32 factors, lambda and fit on
-    the GPU.  Each step groups the active jobs by (N, R) and runs one batched
-    CP-ALS sweep per group of two or more (a lone job runs its own sweep, with
-    no batch tables to rebuild); groups use their own streams.  A job's
-    results are bitwise the same either way."""
+    the GPU.  Jobs are grouped by (N, R); each group has its own stream and
+    runs one batched CP-ALS sweep for two or more members (a lone job runs
+    its own sweep, with no batch tables to rebuild).  A job's results are
+    bitwise the same either way.  A launched sweep ends with an asynchronous
+    copy of the group's fits to pinned host memory and an event; poll()
+    queries the event, so groups advance without waiting for each other."""
 
     def __init__(self, batched: bool = True):
         import torch
@@ -189,12 +281,7 @@ class GpuExecutor(Executor):
         self.capi = capi
         self.batched = batched
         self._batches: Dict[Tuple[int, int], Tuple[tuple, object]] = {}   # group -> (member ids, batch)
-        self._streams: Dict[Tuple[int, int], object] = {}
-        # Fits of a step are gathered on the device and copied to pinned host
-        # memory with one asynchronous copy (a pageable .cpu() costs ~1 ms).
-        self._fit_dev = torch.empty(0, dtype=torch.float64, device="cuda")
-        self._fit_host = torch.empty(0, dtype=torch.float64)
-        self._fit_event = torch.cuda.Event()
+        self._groups: Dict[Tuple[int, int], dict] = {}    # group -> stream, event, fit buffers
 
     def footprint(self, job: ServeJob) -> int:
         lib = self.capi.mttkrp_footprint(job.dims, job.nnz, opts=dict(max_R=job.R))
@@ -210,57 +297,86 @@ class GpuExecutor(Executor):
         self.capi.cpd_als_init(h, F, job.R)
         return {"job": job, "h": h, "F": F, "lam": lam, "fit": fit, "key": (len(job.dims), job.R)}
 
-    def _stream(self, key):
-        if key not in self._streams:
-            self._streams[key] = self.torch.cuda.Stream()
-        return self._streams[key]
+    def group_key(self, slot):
+        return slot["key"]
+
+    def _group(self, key):
+        g = self._groups.get(key)
+        if g is None:
+            torch = self.torch
+            g = {"stream": torch.cuda.Stream(), "event": torch.cuda.Event(),
+                 "dev": torch.empty(0, dtype=torch.float64, device="cuda"),
+                 "host": torch.empty(0, dtype=torch.float64)}
+            self._groups[key] = g
+        return g
+
+    def launch(self, key, slots):
+        torch = self.torch
+        g = self._group(key)
+        st = g["stream"]
+        # factors and state of newly admitted jobs were written on the current stream
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            if self.batched and len(slots) > 1:
+                ids = tuple(id(m["h"]) for m in slots)
+                old = self._batches.get(key)
+                if old is None or old[0] != ids:
+                    if old is not None:
+                        old[1].free()      # the group's previous sweep has completed
+                    self._batches[key] = (ids, self.capi.mttkrp_batch_create([m["h"] for m in slots], key[1]))
+                b = self._batches[key][1]
+                self.capi.cpd_als_batch_iter_async(b, [m["F"] for m in slots], [m["lam"] for m in slots],
+                                                   [m["fit"] for m in slots], stream=st)
+            else:
+                # one job (or no batching): its own sweep, no batch tables to build
+                old = self._batches.pop(key, None) if self.batched else None
+                if old is not None:
+                    old[1].free()
+                for m in slots:
+                    self.capi.cpd_als_iter_async(m["h"], m["F"], m["lam"], key[1], m["fit"], stream=st)
+            n = len(slots)
+            if g["dev"].numel() < n:
+                # the buffers are idle here: the group has no other sweep in flight
+                cap = max(16, 2 * n)
+                g["dev"] = torch.empty(cap, dtype=torch.float64, device="cuda")
+                g["host"] = torch.empty(cap, dtype=torch.float64, pin_memory=True)
+            torch.cat([s["fit"] for s in slots], out=g["dev"][:n])
+            g["host"][:n].copy_(g["dev"][:n], non_blocking=True)
+            g["event"].record(st)
+        return (key, n)
+
+    def poll(self, token):
+        key, n = token
+        g = self._groups[key]
+        if not g["event"].query():
+            return None
+        return g["host"][:n].tolist()
+
+    def wait(self, tokens, timeout_s):
+        end = None if timeout_s is None else time.monotonic() + timeout_s
+        events = [self._groups[key]["event"] for key, _ in tokens]
+        while not any(e.query() for e in events):
+            if end is not None and time.monotonic() >= end:
+                return
 
     def step(self, slots):
-        torch = self.torch
-        groups: Dict[Tuple[int, int], list] = {}
-        for s in slots:
-            groups.setdefault(s["key"], []).append(s)
-        cur = torch.cuda.current_stream()
-        for key, members in groups.items():
-            st = self._stream(key)
-            st.wait_stream(cur)
-            with torch.cuda.stream(st):
-                if self.batched and len(members) > 1:
-                    ids = tuple(id(m["h"]) for m in members)
-                    old = self._batches.get(key)
-                    if old is None or old[0] != ids:
-                        if old is not None:
-                            st.synchronize()
-                            old[1].free()
-                        self._batches[key] = (ids, self.capi.mttkrp_batch_create([m["h"] for m in members], key[1]))
-                    b = self._batches[key][1]
-                    self.capi.cpd_als_batch_iter_async(b, [m["F"] for m in members], [m["lam"] for m in members],
-                                                       [m["fit"] for m in members], stream=st)
-                else:
-                    # one job (or no batching): its own sweep, no batch tables to build
-                    old = self._batches.pop(key, None) if self.batched else None
-                    if old is not None:
-                        st.synchronize()
-                        old[1].free()
-                    for m in members:
-                        self.capi.cpd_als_iter_async(m["h"], m["F"], m["lam"], key[1], m["fit"], stream=st)
-        for key in groups:
-            cur.wait_stream(self._stream(key))
-        n = len(slots)
-        if self._fit_dev.numel() < n:
-            cap = max(64, 2 * n)
-            self._fit_dev = torch.empty(cap, dtype=torch.float64, device="cuda")
-            self._fit_host = torch.empty(cap, dtype=torch.float64, pin_memory=True)
-        torch.cat([s["fit"] for s in slots], out=self._fit_dev[:n])
-        self._fit_host[:n].copy_(self._fit_dev[:n], non_blocking=True)
-        self._fit_event.record(cur)
-        self._fit_event.synchronize()
-        return self._fit_host[:n].tolist()
+        order: Dict[Tuple[int, int], list] = {}
+        for i, s in enumerate(slots):
+            order.setdefault(s["key"], []).append(i)
+        tokens = {key: self.launch(key, [slots[i] for i in idx]) for key, idx in order.items()}
+        fits = [0.0] * len(slots)
+        for key, idx in order.items():
+            self._groups[key]["event"].synchronize()
+            for i, f in zip(idx, self.poll(tokens[key])):
+                fits[i] = f
+        return fits
 
     def release(self, slot):
         torch = self.torch
-        torch.cuda.synchronize()
-        res = {"factors": [f.cpu().numpy() for f in slot["F"]], "lambda": slot["lam"].cpu().numpy()}
+        st = self._group(slot["key"])["stream"]
+        st.synchronize()
+        with torch.cuda.stream(st):
+            res = {"factors": [f.cpu().numpy() for f in slot["F"]], "lambda": slot["lam"].cpu().numpy()}
         old = self._batches.get(slot["key"])
         if old is not None and id(slot["h"]) in old[0]:
             self._batches.pop(slot["key"])[1].free()

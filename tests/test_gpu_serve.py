@@ -26,10 +26,14 @@ SPECS = [((300, 250, 200), 20000, 16, 0.0), ((400, 300, 350), 30000, 16, 0.0), (
          ((350, 280, 260), 25000, 16, 0.05), ((250, 200, 150, 30), 12000, 32, 0.1), ((500, 400, 300), 40000, 32, 0.2)]
 
 
-def test_results_same_alone_and_in_the_mix():
-    print("case serve mix", flush=True)
+@pytest.mark.parametrize("build_threads", [0, 3])
+def test_results_same_alone_and_in_the_mix(build_threads):
+    """Also with layout builds on worker threads, overlapping the sweeps of
+    jobs already running."""
+    print(f"case serve mix, {build_threads} build threads", flush=True)
     mix = jobs(SPECS)
-    m = CpdServer(GpuExecutor(batched=True), hbm_budget_bytes=8 << 30, max_slots=16).run(mix)
+    m = CpdServer(GpuExecutor(batched=True), hbm_budget_bytes=8 << 30, max_slots=16,
+                  build_threads=build_threads).run(mix)
     assert m["completed"] == len(SPECS), m
     for i in range(len(SPECS)):
         alone = jobs([SPECS[i]], first=i)[0]

@@ -3,6 +3,8 @@ a virtual clock: admission by memory and slots in arrival order, retirement
 on convergence or iteration cap, memory accounting, and latency statistics."""
 
 import math
+import threading
+import time
 
 import numpy as np
 import pytest
@@ -144,3 +146,123 @@ def test_percentiles():
     rng = np.random.default_rng(0)
     x = rng.exponential(size=1001)
     assert percentile(x, 99) == pytest.approx(float(np.sort(x)[990]))
+
+
+class AsyncFakeExecutor(FakeExecutor):
+    """Jobs are grouped by rank; a group's sweep takes `dts[R]` of virtual
+    time from its launch, and sweeps of different groups overlap."""
+
+    def __init__(self, clock, dts):
+        super().__init__(clock)
+        self.dts = dts
+        self.launches = []          # (time, group, job ids)
+
+    def group_key(self, job):
+        return job.R
+
+    def launch(self, key, slots):
+        self.launches.append((self.clock.t, key, [j.job_id for j in slots]))
+        out = []
+        for job in slots:
+            self.live[job.job_id] += 1
+            rate = 0.3 + 0.05 * (job.job_id % 5)
+            out.append(1.0 - rate ** self.live[job.job_id])
+        return (self.clock.t + self.dts[key], out)
+
+    def poll(self, token):
+        end, out = token
+        return out if self.clock.t >= end - 1e-12 else None
+
+    def wait(self, tokens, timeout_s):
+        first = min(end for end, _ in tokens)
+        self.clock.t = max(self.clock.t, first if timeout_s is None else min(first, self.clock.t + timeout_s))
+
+
+def test_groups_step_independently():
+    """A fast group keeps sweeping while a slow group's sweep runs, so its jobs
+    finish in their own sweep count x their own sweep time; every job still
+    gets the same fits and iteration count as in lockstep."""
+    c = Clock()
+    ex = AsyncFakeExecutor(c, {16: 0.001, 64: 0.02})
+    jobs = [ServeJob(i, 0.0, (5, 5, 5), 16 if i % 2 else 64, nnz=10, tol=1e-4, max_iters=50) for i in range(6)]
+    srv = CpdServer(ex, 10 ** 9, 8, clock=c, sleep=c.sleep)
+    m = srv.run(jobs)
+    assert m["completed"] == 6
+    for j in jobs:
+        rate = 0.3 + 0.05 * (j.job_id % 5)
+        k = next(k for k in range(2, 60) if rate ** (k - 1) * (1 - rate) < 1e-4)
+        assert j.status == "converged" and j.iters == k
+        assert j.fits == pytest.approx([1.0 - rate ** i for i in range(1, k + 1)])
+        # each job's latency is its own group's sweeps back to back
+        assert j.finished_s == pytest.approx(k * ex.dts[j.R], abs=1e-9)
+    # at most one sweep per group in flight, and the groups overlap
+    for key in (16, 64):
+        t = [tt for tt, g, _ in ex.launches if g == key]
+        assert all(b - a >= ex.dts[key] - 1e-12 for a, b in zip(t, t[1:]))
+    slow_first_end = ex.dts[64]
+    assert sum(1 for tt, g, _ in ex.launches if g == 16 and tt < slow_first_end) >= 10
+
+
+def test_arrival_joins_busy_group_at_its_next_sweep():
+    c = Clock()
+    ex = AsyncFakeExecutor(c, {16: 0.01})
+    jobs = [ServeJob(0, 0.0, (5, 5, 5), 16, nnz=10, tol=1e-12, max_iters=10),
+            ServeJob(1, 0.015, (5, 5, 5), 16, nnz=10, tol=1e-12, max_iters=3)]
+    CpdServer(ex, 10 ** 9, 4, clock=c, sleep=c.sleep).run(jobs)
+    # job 1 is admitted mid-sweep and swept with job 0 from the sweep at t=0.02 on
+    assert jobs[1].admitted_s == pytest.approx(0.015)
+    assert [ids for tt, _, ids in ex.launches][:4] == [[0], [0], [0, 1], [0, 1]]
+    assert jobs[1].finished_s == pytest.approx(0.05) and jobs[0].finished_s == pytest.approx(0.1)
+
+
+class SlowBuildExecutor(FakeExecutor):
+    """Real-time executor: admit (the layout build) sleeps `build_s`, a step
+    sleeps `dt`; counts how many admits run at once."""
+
+    def __init__(self, build_s, dt, fail_id=None):
+        super().__init__(None, dt=dt)
+        self.build_s = build_s
+        self.fail_id = fail_id
+        self.running = 0
+        self.peak_running = 0
+        self.lock = threading.Lock()
+
+    def admit(self, job):
+        with self.lock:
+            self.running += 1
+            self.peak_running = max(self.peak_running, self.running)
+        time.sleep(self.build_s)
+        with self.lock:
+            self.running -= 1
+        if job.job_id == self.fail_id:
+            raise RuntimeError("build failed")
+        return super().admit(job)
+
+    def step(self, slots):
+        time.sleep(self.dt)
+        out = []
+        for job in slots:
+            self.live[job.job_id] += 1
+            rate = 0.3 + 0.05 * (job.job_id % 5)
+            out.append(1.0 - rate ** self.live[job.job_id])
+        return out
+
+
+def test_builds_on_worker_threads_overlap_and_give_the_same_results():
+    runs = {}
+    for threads in (0, 4):
+        ex = SlowBuildExecutor(build_s=0.02, dt=0.0005)
+        jobs = make_jobs(8, gap=0.0)
+        srv = CpdServer(ex, 10 ** 9, 8, build_threads=threads)
+        m = srv.run(jobs)
+        assert m["completed"] == 8 and srv.in_use == 0
+        assert m["admit_s_total"] >= 8 * 0.02 * 0.9
+        runs[threads] = (ex.peak_running, [(j.iters, j.fits) for j in jobs])
+    assert runs[0][0] == 1 and runs[4][0] >= 2
+    assert runs[0][1] == runs[4][1]
+
+
+def test_a_failed_build_is_raised():
+    ex = SlowBuildExecutor(build_s=0.001, dt=0.0005, fail_id=2)
+    with pytest.raises(RuntimeError, match="build failed"):
+        CpdServer(ex, 10 ** 9, 8, build_threads=2).run(make_jobs(4, gap=0.0))

@@ -97,7 +97,9 @@ def test_sweeps_bf16_factors():
 
 
 def test_fit_trajectory_vs_oracle():
-    """Same start, five sweeps: the GPU (fp32 storage) and the FP64 oracle fits agree closely."""
+    """Same start, five sweeps on the 1000x800x600, 100k-nonzero tensor at R=16:
+    the GPU (fp32 factors, FP64 normal equations) and the FP64 oracle fits agree
+    within 1e-5 absolute and, since these fits are near 1e-4, 1e-6 relative."""
     print("case als trajectory", flush=True)
     t = workloads.random_tensor((1000, 800, 600), 100_000, seed=1)
     R = 16
@@ -105,7 +107,10 @@ def test_fit_trajectory_vs_oracle():
     st = oracle.cp_als(t.idx, t.val, t.dims, workloads.random_factors(t.dims, R, seed=0), n_iter=5, threads=8)
     print("gpu fits", gpu)
     print("oracle fits", st.fits)
-    assert np.max(np.abs(np.array(gpu) - np.array(st.fits))) <= 1e-4
+    diff = np.abs(np.array(gpu) - np.array(st.fits))
+    print("max |dfit|", diff.max(), "relative", (diff / np.abs(st.fits)).max())
+    assert diff.max() <= 1e-5
+    assert (diff / np.abs(st.fits)).max() <= 1e-6
 
 
 def test_not_spd_reported():

@@ -40,7 +40,8 @@ class MttkrpError(RuntimeError):
 
 class mttkrp_opts(ctypes.Structure):
     _fields_ = [("parts_per_cu", ctypes.c_int), ("factor_dtype", ctypes.c_int), ("max_R", ctypes.c_int),
-                ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int), ("hot_rows", ctypes.c_int)]
+                ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int), ("hot_rows", ctypes.c_int),
+                ("build_on_host", ctypes.c_int)]
 
 
 class mttkrp_mode_view(ctypes.Structure):

@@ -133,6 +133,7 @@ void mttkrp_opts_default(mttkrp_opts* o)
     o->hbm_budget_bytes = 0;
     o->host_only = 0;
     o->hot_rows = 0;
+    o->build_on_host = 0;
 }
 
 const char* mttkrp_last_error(void) { return g_err.c_str(); }
@@ -278,51 +279,73 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
 
-    // Mode copies: built on the host one mode at a time into the same buffers, uploaded.
     double normX2 = 0.0;
-    mk::HostMode hm;
-    for (int n = 0; n < N && e == hipSuccess; ++n) {
-        mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, false, threads, &hot, hm, &scratch);
-        mk::DevMode& d = h->dev[n];
-        d.nnz = hm.nnz;
-        d.nnz_pad = hm.nnz_pad;
-        d.nrows_nz = hm.nrows_nz;
-        d.nempty = hm.nempty;
-        d.n_in = N - 1;
-        auto up = [&](const void* src, uint64_t bytes) -> void* {
-            void* dst = take(bytes ? bytes : 4);
-            if (bytes && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
-            return dst;
-        };
-        for (int j = 0; j < N - 1; ++j) {
-            d.in_modes[j] = hm.in_modes[j];
-            d.in_dims[j] = dims[hm.in_modes[j]];
-            d.idx[j] = static_cast<const uint32_t*>(up(hm.idx[j].data(), hm.nnz_pad * 4));
+    if (e == hipSuccess && !o.build_on_host && nhot == 0 && mk::device_build_applies(dims, N, nnz)) {
+        // Mode copies sorted and laid out on the device.
+        const uint64_t nnz_pad = (nnz + 31) / 32 * 32;
+        std::vector<mk::DeviceModeSlots> slots(N);
+        for (int n = 0; n < N; ++n) {
+            for (int j = 0; j < N - 1; ++j) slots[n].idx[j] = static_cast<uint32_t*>(take(nnz_pad * 4));
+            slots[n].val = static_cast<float*>(take(nnz_pad * 4));
+            slots[n].winfo = static_cast<uint2*>(take(nnz_pad / 32 * 8));
+            slots[n].rows = static_cast<uint32_t*>(take((uint64_t)dims[n] * 4));
         }
-        d.val = static_cast<const float*>(up(hm.val.data(), hm.nnz_pad * 4));
-        d.winfo = static_cast<const uint2*>(up(hm.winfo.data(), hm.winfo.size() * 4));
-        d.row_id = static_cast<const uint32_t*>(up(hm.row_id.data(), hm.row_id.size() * 4));
-        d.empty_rows = static_cast<const uint32_t*>(up(hm.empty_rows.data(), hm.empty_rows.size() * 4));
-        if (n == 0) {
-            // |X|^2 with duplicate coordinates merged: duplicates are adjacent in
-            // the sorted copy (no row start between them, same other indices).
-            uint64_t k = 0;
-            while (k < nnz) {
-                double v = hm.val[k];
-                uint64_t j = k + 1;
-                while (j < nnz && !((hm.winfo[2 * (j / 32)] >> (j % 32)) & 1u)) {
-                    bool same = true;
-                    for (int t = 0; t < N - 1 && same; ++t) same = hm.idx[t][j] == hm.idx[t][k];
-                    if (!same) break;
-                    v += hm.val[j];
-                    ++j;
-                }
-                normX2 += v * v;
-                k = j;
+        if (off > need) {
+            (void)hipFree(h->dmem);
+            delete h;
+            return fail(MTTKRP_EHIP, "internal: mode copies exceed the planned device footprint");
+        }
+        std::vector<mk::DevMode> modes;
+        e = mk::build_device_modes(coo_idx, vals, nnz, dims, N, slots, modes, &normX2, stream);
+        if (e == hipSuccess)
+            for (int n = 0; n < N; ++n) h->dev[n] = modes[n];
+    }
+    else {
+        // Mode copies: built on the host one mode at a time into the same buffers, uploaded.
+        mk::HostMode hm;
+        for (int n = 0; n < N && e == hipSuccess; ++n) {
+            mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, false, threads, &hot, hm, &scratch);
+            mk::DevMode& d = h->dev[n];
+            d.nnz = hm.nnz;
+            d.nnz_pad = hm.nnz_pad;
+            d.nrows_nz = hm.nrows_nz;
+            d.nempty = hm.nempty;
+            d.n_in = N - 1;
+            auto up = [&](const void* src, uint64_t bytes) -> void* {
+                void* dst = take(bytes ? bytes : 4);
+                if (bytes && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+                return dst;
+            };
+            for (int j = 0; j < N - 1; ++j) {
+                d.in_modes[j] = hm.in_modes[j];
+                d.in_dims[j] = dims[hm.in_modes[j]];
+                d.idx[j] = static_cast<const uint32_t*>(up(hm.idx[j].data(), hm.nnz_pad * 4));
             }
+            d.val = static_cast<const float*>(up(hm.val.data(), hm.nnz_pad * 4));
+            d.winfo = static_cast<const uint2*>(up(hm.winfo.data(), hm.winfo.size() * 4));
+            d.row_id = static_cast<const uint32_t*>(up(hm.row_id.data(), hm.row_id.size() * 4));
+            d.empty_rows = static_cast<const uint32_t*>(up(hm.empty_rows.data(), hm.empty_rows.size() * 4));
+            if (n == 0) {
+                // |X|^2 with duplicate coordinates merged: duplicates are adjacent in
+                // the sorted copy (no row start between them, same other indices).
+                uint64_t k = 0;
+                while (k < nnz) {
+                    double v = hm.val[k];
+                    uint64_t j = k + 1;
+                    while (j < nnz && !((hm.winfo[2 * (j / 32)] >> (j % 32)) & 1u)) {
+                        bool same = true;
+                        for (int t = 0; t < N - 1 && same; ++t) same = hm.idx[t][j] == hm.idx[t][k];
+                        if (!same) break;
+                        v += hm.val[j];
+                        ++j;
+                    }
+                    normX2 += v * v;
+                    k = j;
+                }
+            }
+            // The next mode overwrites the host arrays; wait for the copies that read them.
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
         }
-        // The next mode overwrites the host arrays; wait for the copies that read them.
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
     }
     h->normX2 = normX2;
     if (e != hipSuccess) {

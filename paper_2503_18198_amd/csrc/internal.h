@@ -2,6 +2,8 @@
 #pragma once
 
 #include <stdint.h>
+
+#include <vector>
 #include <hip/hip_runtime.h>
 
 #include "mttkrp.h"
@@ -129,5 +131,26 @@ hipError_t als_gram_jobs(const DenseJob& single, const DenseJob* jobs, const uin
 hipError_t als_fit_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
                         int R, hipStream_t s);
 hipError_t cast_bf16(const float* A, uint64_t n, uint16_t* out, hipStream_t s);
+
+// Device memory of one mode copy, sized for nnz_pad nonzeros and I_n rows:
+// N-1 index arrays, values, per-word row info, and the row lists (nonempty
+// rows first, then the empty rows, I_n entries in all).
+struct DeviceModeSlots {
+    uint32_t* idx[kMaxIn] = {};
+    float* val = nullptr;
+    uint2* winfo = nullptr;
+    uint32_t* rows = nullptr;
+};
+
+// Whether the copies of this tensor can be built on the device: 1 <= nnz < 2^31
+// and the packed coordinate key (all N indices) fits 64 bits.
+bool device_build_applies(const uint32_t* dims, int N, uint64_t nnz);
+
+// Build all N mode copies on the device into `slots` (same arrays and order as
+// the host build) and the duplicate-merged |X|^2; uploads the COO tensor to a
+// scratch allocation that is freed before returning.  Synchronises `s`.
+hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, uint64_t nnz, const uint32_t* dims,
+                              int N, const std::vector<DeviceModeSlots>& slots, std::vector<DevMode>& modes,
+                              double* normX2, hipStream_t s);
 
 }  // namespace mk

@@ -72,9 +72,9 @@ typedef struct {
     int hot_rows;              /* rows of each input factor kept in LDS during a run: the most frequently
                                   gathered ones.  -1 = as many as fit, 0 = none (default), k > 0 = at most k */
     int build_on_host;         /* 1: sort the mode copies on the host.  0 (default): on the device when the
-                                  packed coordinate key of all N indices fits 64 bits, 1 <= nnz < 2^31 and
+                                  packed coordinate key of all N indices fits 128 bits, 1 <= nnz < 2^31 and
                                   hot_rows is 0 (the copies are identical either way; the device build
-                                  holds a transient scratch of about nnz * (4N + 40) bytes) */
+                                  holds a transient scratch of about nnz * (4N + 48) bytes) */
 } mttkrp_opts;
 
 /* Fill `o` with the defaults listed above. */

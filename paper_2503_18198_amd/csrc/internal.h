@@ -143,7 +143,7 @@ struct DeviceModeSlots {
 };
 
 // Whether the copies of this tensor can be built on the device: 1 <= nnz < 2^31
-// and the packed coordinate key (all N indices) fits 64 bits.
+// and the packed coordinate key (all N indices) fits 128 bits.
 bool device_build_applies(const uint32_t* dims, int N, uint64_t nnz);
 
 // Build all N mode copies on the device into `slots` (same arrays and order as

@@ -1,10 +1,11 @@
 // Device construction of the mode-specific copies (Sec. III-B scheme 2 order,
 // Sec. III-C COO copies): the same arrays, in the same order, as the host
-// build, for tensors whose packed coordinate keys fit 64 bits.
+// build, for tensors whose packed coordinate keys fit 128 bits.
 //
 // Per mode: a packed key per nonzero (output index in the top bits, then the
 // other indices in cyclic order), a stable radix sort of (key, position)
-// pairs, so equal coordinates keep their input order, then the
+// pairs (keys over 64 bits: by the low word, then stably by the high word),
+// so equal coordinates keep their input order, then the
 // structure-of-arrays copy decoded from the sorted keys, the row-start bits
 // with the per-word row ordinals, and the lists of nonempty and empty rows.
 #include <hipcub/hipcub.hpp>
@@ -29,27 +30,47 @@ struct DecodeOut {
     float* val;
 };
 
-__device__ __forceinline__ uint64_t row_of(uint64_t key, const KeyFields& kf)
+using u128 = unsigned __int128;
+
+// Key k from its low and high words (no high words: keys of at most 64 bits).
+__device__ __forceinline__ u128 key_at(const uint64_t* __restrict__ lo, const uint64_t* __restrict__ hi, uint64_t k)
 {
-    return kf.row_bits ? key >> kf.row_shift : 0;
+    u128 v = lo[k];
+    if (hi) v |= (u128)hi[k] << 64;
+    return v;
+}
+
+__device__ __forceinline__ uint64_t row_of(u128 key, const KeyFields& kf)
+{
+    return kf.row_bits ? (uint64_t)(key >> kf.row_shift) : 0;
 }
 
 __global__ void pack_keys_kernel(const uint32_t* __restrict__ coo, uint64_t nnz, int N, KeyFields kf,
-                                 uint64_t* __restrict__ key, uint32_t* __restrict__ pos)
+                                 uint64_t* __restrict__ lo, uint64_t* __restrict__ hi, uint32_t* __restrict__ pos)
 {
     const uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (k >= nnz) return;
     const uint32_t* p = coo + k * (uint64_t)N;
-    uint64_t v = p[kf.row_mode];
+    u128 v = p[kf.row_mode];
     for (int f = 0; f < kf.nf; ++f)
         if (kf.bits[f]) v = (v << kf.bits[f]) | p[kf.mode[f]];
-    key[k] = v;
+    lo[k] = (uint64_t)v;
+    if (hi) hi[k] = (uint64_t)(v >> 64);
     pos[k] = (uint32_t)k;
+}
+
+// dst[k] = src[pos[k]]
+__global__ void gather_u64_kernel(const uint64_t* __restrict__ src, const uint32_t* __restrict__ pos, uint64_t n,
+                                  uint64_t* __restrict__ dst)
+{
+    const uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[pos[k]];
 }
 
 // Input-mode coordinates from the sorted keys, values gathered by position;
 // the padding up to a multiple of 32 is zero.
-__global__ void decode_kernel(const uint64_t* __restrict__ key, const uint32_t* __restrict__ pos,
+__global__ void decode_kernel(const uint64_t* __restrict__ lo, const uint64_t* __restrict__ hi,
+                              const uint32_t* __restrict__ pos,
                               const float* __restrict__ val_in, uint64_t nnz, uint64_t nnz_pad, KeyFields kf,
                               DecodeOut out)
 {
@@ -60,7 +81,7 @@ __global__ void decode_kernel(const uint64_t* __restrict__ key, const uint32_t* 
         out.val[k] = 0.0f;
         return;
     }
-    const uint64_t x = key[k];
+    const u128 x = key_at(lo, hi, k);
     for (int f = 0; f < kf.nf; ++f) {
         const uint32_t mask = kf.bits[f] ? (uint32_t)((1ull << kf.bits[f]) - 1ull) : 0u;
         out.idx[kf.slot[f]][k] = (uint32_t)(x >> kf.shift[f]) & mask;
@@ -69,16 +90,17 @@ __global__ void decode_kernel(const uint64_t* __restrict__ key, const uint32_t* 
 }
 
 // Per 32 nonzeros: a bit per nonzero that starts an output row, and the count.
-__global__ void row_bits_kernel(const uint64_t* __restrict__ key, uint64_t nnz, uint64_t nwords, KeyFields kf,
+__global__ void row_bits_kernel(const uint64_t* __restrict__ lo, const uint64_t* __restrict__ hi, uint64_t nnz,
+                                uint64_t nwords, KeyFields kf,
                                 uint32_t* __restrict__ bits_out, uint32_t* __restrict__ count_out)
 {
     const uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (w >= nwords) return;
     uint32_t bits = 0;
     const uint64_t k0 = w * 32;
-    uint64_t prev = k0 ? row_of(key[k0 - 1], kf) : ~0ull;
+    uint64_t prev = k0 ? row_of(key_at(lo, hi, k0 - 1), kf) : ~0ull;
     for (int b = 0; b < 32 && k0 + b < nnz; ++b) {
-        const uint64_t r = row_of(key[k0 + b], kf);
+        const uint64_t r = row_of(key_at(lo, hi, k0 + b), kf);
         if (r != prev) bits |= 1u << b;
         prev = r;
     }
@@ -88,7 +110,8 @@ __global__ void row_bits_kernel(const uint64_t* __restrict__ key, uint64_t nnz, 
 
 // winfo = {row-start bits, ordinal of the row holding the word's first
 // nonzero}; row_id[ordinal] = output row; marks the rows that are present.
-__global__ void row_lists_kernel(const uint64_t* __restrict__ key, const uint32_t* __restrict__ bits_in,
+__global__ void row_lists_kernel(const uint64_t* __restrict__ lo, const uint64_t* __restrict__ hi,
+                                 const uint32_t* __restrict__ bits_in,
                                  const uint32_t* __restrict__ before, uint64_t nwords, KeyFields kf,
                                  uint2* __restrict__ winfo, uint32_t* __restrict__ row_id,
                                  uint8_t* __restrict__ empty_flag)
@@ -102,7 +125,7 @@ __global__ void row_lists_kernel(const uint64_t* __restrict__ key, const uint32_
     while (m) {
         const int b = __ffs(m) - 1;
         m &= m - 1;
-        const uint32_t row = (uint32_t)row_of(key[w * 32 + b], kf);
+        const uint32_t row = (uint32_t)row_of(key_at(lo, hi, w * 32 + b), kf);
         row_id[b0 + (uint32_t)__popc(bits & ((1u << b) - 1u))] = row;
         empty_flag[row] = 0;
     }
@@ -116,17 +139,18 @@ __global__ void fill_u8_kernel(uint8_t* p, uint64_t n, uint8_t v)
 
 // Squared value of every run of equal coordinates (duplicates summed first),
 // at the run's first nonzero; zero elsewhere.
-__global__ void run_squares_kernel(const uint64_t* __restrict__ key, const float* __restrict__ val, uint64_t nnz,
-                                   double* __restrict__ sq)
+__global__ void run_squares_kernel(const uint64_t* __restrict__ lo, const uint64_t* __restrict__ hi,
+                                   const float* __restrict__ val, uint64_t nnz, double* __restrict__ sq)
 {
     const uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (k >= nnz) return;
-    if (k > 0 && key[k - 1] == key[k]) {
+    const u128 key = key_at(lo, hi, k);
+    if (k > 0 && key_at(lo, hi, k - 1) == key) {
         sq[k] = 0.0;
         return;
     }
     double v = val[k];
-    for (uint64_t j = k + 1; j < nnz && key[j] == key[k]; ++j) v += val[j];
+    for (uint64_t j = k + 1; j < nnz && key_at(lo, hi, j) == key; ++j) v += val[j];
     sq[k] = v * v;
 }
 
@@ -146,7 +170,7 @@ bool device_build_applies(const uint32_t* dims, int N, uint64_t nnz)
     if (nnz == 0 || nnz >= (1ull << 31)) return false;
     int bits = 0;
     for (int m = 0; m < N; ++m) bits += bits_for(dims[m]);
-    return bits <= 64;   // the key of every mode holds all N fields
+    return bits <= 128;   // the key of every mode holds all N fields
 }
 
 hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, uint64_t nnz, const uint32_t* dims,
@@ -180,7 +204,8 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
     const uint64_t o_val = o_coo + al(nnz * N * 4);
     const uint64_t o_key = o_val + al(nnz * 4);
     const uint64_t o_tkey = o_key + al(nnz * 8);
-    const uint64_t o_pos = o_tkey + al(nnz * 8);
+    const uint64_t o_hi = o_tkey + al(nnz * 8);
+    const uint64_t o_pos = o_hi + al(nnz * 8);
     const uint64_t o_tpos = o_pos + al(nnz * 4);
     const uint64_t o_sq = o_tpos + al(nnz * 4);
     const uint64_t o_bits = o_sq + al(nnz * 8);
@@ -197,6 +222,7 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
     float* d_val = (float*)(base + o_val);
     uint64_t* d_key = (uint64_t*)(base + o_key);
     uint64_t* d_tkey = (uint64_t*)(base + o_tkey);
+    uint64_t* d_hi = (uint64_t*)(base + o_hi);
     uint32_t* d_pos = (uint32_t*)(base + o_pos);
     uint32_t* d_tpos = (uint32_t*)(base + o_tpos);
     double* d_sq = (double*)(base + o_sq);
@@ -231,21 +257,39 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
         kf.row_shift = below;
         const int key_bits = below + kf.row_bits;
 
-        pack_keys_kernel<<<blocks_for(nnz, T), T, 0, s>>>(d_coo, nnz, N, kf, d_key, d_pos);
+        // Sorted keys end in (lo, hi) with positions in pos.
+        const bool wide = key_bits > 64;
+        const uint64_t* lo = d_tkey;
+        const uint64_t* hi = nullptr;
+        const uint32_t* pos = d_tpos;
+        pack_keys_kernel<<<blocks_for(nnz, T), T, 0, s>>>(d_coo, nnz, N, kf, d_key, wide ? d_hi : nullptr, d_pos);
         size_t b = cub_b;
         e = hipcub::DeviceRadixSort::SortPairs(d_cub, b, d_key, d_tkey, d_pos, d_tpos, (int)nnz, 0,
-                                               std::max(key_bits, 1), s);
+                                               wide ? 64 : std::max(key_bits, 1), s);
         if (e != hipSuccess) break;
+        if (wide) {
+            // then stably by the high word: the high words in low-word order go
+            // to d_tkey, are sorted into d_hi with positions into d_pos, and the
+            // low words are gathered by the final positions into d_tkey
+            gather_u64_kernel<<<blocks_for(nnz, T), T, 0, s>>>(d_hi, d_tpos, nnz, d_tkey);
+            b = cub_b;
+            e = hipcub::DeviceRadixSort::SortPairs(d_cub, b, d_tkey, d_hi, d_tpos, d_pos, (int)nnz, 0,
+                                                   key_bits - 64, s);
+            if (e != hipSuccess) break;
+            gather_u64_kernel<<<blocks_for(nnz, T), T, 0, s>>>(d_key, d_pos, nnz, d_tkey);
+            hi = d_hi;
+            pos = d_pos;
+        }
         DecodeOut out{};
         for (int j = 0; j < N - 1; ++j) out.idx[j] = sl.idx[j];
         out.val = sl.val;
-        decode_kernel<<<blocks_for(nnz_pad, T), T, 0, s>>>(d_tkey, d_tpos, d_val, nnz, nnz_pad, kf, out);
-        row_bits_kernel<<<blocks_for(nwords, T), T, 0, s>>>(d_tkey, nnz, nwords, kf, d_bits, d_cnt);
+        decode_kernel<<<blocks_for(nnz_pad, T), T, 0, s>>>(lo, hi, pos, d_val, nnz, nnz_pad, kf, out);
+        row_bits_kernel<<<blocks_for(nwords, T), T, 0, s>>>(lo, hi, nnz, nwords, kf, d_bits, d_cnt);
         b = cub_b;
         e = hipcub::DeviceScan::ExclusiveSum(d_cub, b, d_cnt, d_before, (int)nwords, s);
         if (e != hipSuccess) break;
         fill_u8_kernel<<<blocks_for(dims[n], T), T, 0, s>>>(d_flag, dims[n], 1);
-        row_lists_kernel<<<blocks_for(nwords, T), T, 0, s>>>(d_tkey, d_bits, d_before, nwords, kf, sl.winfo,
+        row_lists_kernel<<<blocks_for(nwords, T), T, 0, s>>>(lo, hi, d_bits, d_before, nwords, kf, sl.winfo,
                                                             sl.rows, d_flag);
         // row counts: the scan's last entry plus the last word's count
         uint32_t tail[2] = {0, 0};
@@ -286,7 +330,7 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
 
         if (n == 0) {
             // |X|^2 with duplicate coordinates merged (equal keys are adjacent)
-            run_squares_kernel<<<blocks_for(nnz, T), T, 0, s>>>(d_tkey, sl.val, nnz, d_sq);
+            run_squares_kernel<<<blocks_for(nnz, T), T, 0, s>>>(lo, hi, sl.val, nnz, d_sq);
             b = cub_b;
             e = hipcub::DeviceReduce::Sum(d_cub, b, d_sq, (double*)d_small, (int)nnz, s);
             if (e == hipSuccess) e = hipMemcpyAsync(normX2, d_small, 8, hipMemcpyDeviceToHost, s);

@@ -38,7 +38,10 @@ CASES = {
     "five_modes": ((100, 50, 40, 30, 20), 40_000, "uniform", 0, None),
     "dim_one": ((1, 500, 70), 20_000, "uniform", 0, None),
     "key_exactly_64_bits": ((65_536,) * 4, 20_000, "uniform", 0, None),
-    "key_over_64_bits_host_path": ((1 << 20,) * 4, 20_000, "uniform", 0, None),
+    "key_80_bits": ((1 << 20,) * 4, 20_000, "uniform", 0, None),
+    "key_72_bits_zipf_5_modes": ((9000, 70_000, 100_000, 120, 100_000), 200_000, "zipf", 300, None),
+    "key_exactly_128_bits": ((1 << 16,) * 8, 20_000, "uniform", 0, None),
+    "key_over_128_bits_host_path": ((1 << 17,) * 8, 20_000, "uniform", 0, None),
 }
 
 

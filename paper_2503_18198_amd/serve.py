@@ -16,8 +16,8 @@ Jobs (a sparse tensor, a rank, a stopping rule) arrive over time.  The loop
 
 Requests that arrive while others run are admitted at once and join their
 group's next sweep, so new and old jobs share the GPU.  With
-``build_threads`` > 0 a job's device state (its layout build, a host sort)
-is made on a worker thread, so it overlaps the sweeps in flight; memory is
+``build_threads`` > 0 a job's device state (its layout build and initial
+factors) is made on a worker thread, so it overlaps the sweeps in flight; memory is
 reserved when the job is admitted, in arrival order.  A tensor's results do
 not depend on which other jobs share its sweeps: the batched sweep is bitwise
 the single-tensor sweep.
@@ -290,8 +290,10 @@ class GpuExecutor(Executor):
     def admit(self, job: ServeJob):
         torch = self.torch
         h = self.capi.mttkrp_layout_build(job.idx, job.val, job.dims, opts=dict(max_R=job.R))
-        rng = np.random.default_rng(job.seed)
-        F = [torch.from_numpy(rng.random((d, job.R)).astype(np.float32)).cuda() for d in job.dims]
+        # initial factors U(0,1) drawn on the device from the job's seed
+        g = torch.Generator(device="cuda")
+        g.manual_seed(int(job.seed))
+        F = [torch.rand((d, job.R), generator=g, device="cuda", dtype=torch.float32) for d in job.dims]
         lam = torch.zeros(job.R, dtype=torch.float64, device="cuda")
         fit = torch.zeros(1, dtype=torch.float64, device="cuda")
         self.capi.cpd_als_init(h, F, job.R)

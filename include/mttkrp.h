@@ -95,8 +95,13 @@ mttkrp_status mttkrp_footprint(const uint32_t* dims /* host, N */, int N, uint64
  *   dims:    host, N
  * The inputs are borrowed for the call only (validated and copied).  Duplicate
  * coordinates are allowed and add up.  nnz == 0 is valid (all outputs zero).
- * Sorting and partitioning run on the host; the copies are then uploaded on
- * `stream` and the call returns after the upload has completed.
+ * Each copy is ordered by (output index, other indices in cyclic order,
+ * input position).  The sort runs on the device, on `stream`, when the
+ * packed key of all N indices fits 128 bits (see opts->build_on_host); the
+ * COO tensor is then uploaded to a transient scratch allocation that is freed
+ * before returning.  Otherwise it runs on the host and the copies are
+ * uploaded on `stream`.  Either way the call returns once the copies are on
+ * the device, and the copies are identical.
  * On success *out receives a handle to release with mttkrp_layout_free. */
 mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, uint64_t nnz,
                                   const uint32_t* dims, int N, const mttkrp_opts* opts,

@@ -90,3 +90,17 @@ def test_batch_and_jobs_shapes():
     assert all(j.R in (16, 32, 64) for j in jobs)
     assert all(jobs[i].arrival_s < jobs[i + 1].arrival_s for i in range(19))
     assert math.isfinite(jobs[-1].arrival_s)
+
+
+@pytest.mark.parametrize("dims,nnz", [((300, 200, 100), 200_000), ((40, 30, 20, 10), 20_000)])
+def test_distinct_coords_bitmap_and_sorted_paths_agree(dims, nnz):
+    """Remembering accepted coordinates in a bitmap or in a sorted key array
+    gives the same coordinates in the same order, with heavy Zipf collisions
+    (many top-up rounds) and with the cap nearly reached."""
+    out = []
+    for use_bitmap in (True, False):
+        r_idx = gen._streams(9)[0]
+        samplers = [gen._make_sampler(d, "zipf", 1.2, r_idx) for d in dims]
+        out.append(gen.distinct_coords(samplers, dims, nnz, r_idx, use_bitmap=use_bitmap))
+    assert np.array_equal(out[0], out[1])
+    assert np.unique(out[0], axis=0).shape[0] == nnz

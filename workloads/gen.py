@@ -101,7 +101,8 @@ def _keys(coords: np.ndarray, dims: Sequence[int]) -> np.ndarray:
 
 
 def distinct_coords(samplers, dims: Sequence[int], nnz: int, rng: np.random.Generator,
-                    progress: Optional[Callable[[str], None]] = None) -> np.ndarray:
+                    progress: Optional[Callable[[str], None]] = None, use_bitmap: Optional[bool] = None
+                    ) -> np.ndarray:
     """Draw-and-top-up until exactly ``nnz`` distinct coordinates remain.
     ``progress`` (optional) receives a line after every draw round.
 
@@ -109,11 +110,14 @@ def distinct_coords(samplers, dims: Sequence[int], nnz: int, rng: np.random.Gene
     not yet accepted, and appends those in draw order.  Accepted coordinates
     are remembered in a bitmap over the linear index when the index space
     fits in 2^33 bits (1 GiB), else in a sorted key array; both give the same
-    result, the bitmap in time proportional to each round's draws."""
+    result, the bitmap in time proportional to each round's draws.
+    ``use_bitmap`` forces one of the two (None: by the size of the space)."""
     N = len(dims)
     accepted = []
     space = math.prod(int(d) for d in dims)
-    bitmap = np.zeros((space + 7) // 8, dtype=np.uint8) if space <= (1 << 33) else None
+    if use_bitmap is None:
+        use_bitmap = space <= (1 << 33)
+    bitmap = np.zeros((space + 7) // 8, dtype=np.uint8) if use_bitmap else None
     seen = None  # sorted keys of accepted coordinates (no bitmap)
     need = nnz
     while need > 0:

@@ -542,7 +542,7 @@ def bench_serve(args, rhos=(0.5, 0.8, 0.95, 2.0)):
         srv.run(js)
         return timed_metrics(srv, js)
 
-    budget = 8 << 30
+    budget = int(args.serve_budget_gib * (1 << 30))
     # warm-up (allocations, first launches), then the plain method's capacity:
     # every job present at time 0, one at a time
     CpdServer(GpuExecutor(batched=True), budget, max_slots=64, build_threads=args.serve_build_threads).run(
@@ -577,7 +577,7 @@ def bench_serve(args, rhos=(0.5, 0.8, 0.95, 2.0)):
         "config": {"workload": f"serve-poisson: {n_warm} warm-up + {n_timed} timed Poisson CP-ALS jobs, 3-5 modes, "
                                f"dims log-U[1e2,1e5], nnz log-U[1e4,1e7] ({nnzs.sum() / 1e6:.0f}M in all), "
                                f"Zipf(1.2), R in {{16,32,64}}, stop at |dfit|<1e-4 or 50 sweeps, offered load "
-                               f"rho x plain capacity for rho in {list(rhos)}, HBM budget 8 GiB, slots "
+                               f"rho x plain capacity for rho in {list(rhos)}, HBM budget {args.serve_budget_gib:g} GiB, slots "
                                f"{args.serve_slots}, {args.serve_build_threads} layout-build threads; value = "
                                f"served jobs/s at the highest load with {args.serve_slots[0]} slots; "
                                f"ms_per_step = ms per served job"},
@@ -604,6 +604,8 @@ def main(argv=None):
                     help="concurrent job slots of the continuous-batching server (serve-poisson)")
     ap.add_argument("--serve-jobs", type=int, default=200, help="timed jobs of serve-poisson")
     ap.add_argument("--serve-warmup-jobs", type=int, default=20, help="warm-up jobs ahead of them")
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0,
+                    help="device memory the serving loop may admit jobs into (serve-poisson)")
     ap.add_argument("--serve-build-threads", type=int, default=4,
                     help="worker threads for layout builds in the continuous-batching server")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

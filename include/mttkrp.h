@@ -177,6 +177,27 @@ typedef struct {
 
 mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
 
+/* Launch plan of the per-mode MTTKRP for a tensor of nnz nonzeros and N modes
+ * (host only, no device needed): the nonzero-balanced partitions of the
+ * paper's load-balancing scheme 2 (Sec. III-B), one workgroup each.  Every
+ * lane group adds at most 4096 consecutive nonzeros in one FP32 register
+ * chain, for any nnz < 2^32, so rounding grows with at most 4096 terms per
+ * chain; partials beyond that are combined in LDS and in FP64.
+ *   parts_per_cu: the target number of partitions per compute unit (<= 0: 8)
+ *   cu_count:     compute units of the device (0: 256, the MI355X) */
+typedef struct {
+    uint32_t wg_threads;          /* threads per partition workgroup */
+    uint32_t lane_groups;         /* lane groups per workgroup (one 16-byte row slice per lane) */
+    uint32_t lanes_per_group;     /* lanes that share one factor row */
+    uint32_t nonzeros_per_group;  /* consecutive nonzeros one lane group adds in registers (<= 4096) */
+    uint64_t nonzeros_per_part;   /* nonzeros per workgroup partition */
+    uint32_t nparts;              /* workgroups of the launch */
+    uint64_t carry_bytes;         /* carry rows the handle reserves for rows cut by partitions (at max_R = R) */
+} mttkrp_plan;
+
+mttkrp_status mttkrp_launch_plan(uint64_t nnz, int N, int R, int factor_dtype, int parts_per_cu, uint32_t cu_count,
+                                 mttkrp_plan* out);
+
 /* ---- Batching: many small tensors per launch ----
  * A batch groups handles of tensors with the same N.  mttkrp_batch_run runs
  * the MTTKRP along one mode for every tensor of the batch with one

@@ -29,7 +29,7 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
             "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create", "mttkrp_batch_run",
             "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
-            "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2"]
+            "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan"]
 
 
 class MttkrpError(RuntimeError):
@@ -58,6 +58,12 @@ class mttkrp_mode_view(ctypes.Structure):
 class mttkrp_info(ctypes.Structure):
     _fields_ = [("cu_count", ctypes.c_uint32), ("lds_per_workgroup", ctypes.c_uint32), ("hot_rows", ctypes.c_uint32),
                 ("wg_threads", ctypes.c_uint32), ("parts_per_cu", ctypes.c_uint32)]
+
+
+class mttkrp_plan(ctypes.Structure):
+    _fields_ = [("wg_threads", ctypes.c_uint32), ("lane_groups", ctypes.c_uint32),
+                ("lanes_per_group", ctypes.c_uint32), ("nonzeros_per_group", ctypes.c_uint32),
+                ("nonzeros_per_part", ctypes.c_uint64), ("nparts", ctypes.c_uint32), ("carry_bytes", ctypes.c_uint64)]
 
 
 def _load():
@@ -97,10 +103,12 @@ def _load():
     lib.cpd_als_batch_iter_async.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.mttkrp_batch_free.argtypes = [vp]
     lib.mttkrp_batch_free.restype = None
+    lib.mttkrp_launch_plan.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_uint32, ctypes.POINTER(mttkrp_plan)]
     for name in ("mttkrp_footprint", "mttkrp_layout_build", "mttkrp_run", "mttkrp_run_bf16", "cpd_als_init",
                  "cpd_als_iter", "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create",
                  "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
-                 "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2"):
+                 "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -205,6 +213,14 @@ def mttkrp_layout_info(h: Layout) -> dict:
     i = mttkrp_info()
     _check(_lib.mttkrp_layout_info(ctypes.c_void_p(h.ptr), ctypes.byref(i)))
     return {k: int(getattr(i, k)) for k, _ in mttkrp_info._fields_}
+
+
+def mttkrp_launch_plan(nnz: int, N: int, R: int, factor_dtype: int = MTTKRP_FP32, parts_per_cu: int = 0,
+                       cu_count: int = 0) -> dict:
+    p = mttkrp_plan()
+    _check(_lib.mttkrp_launch_plan(int(nnz), int(N), int(R), int(factor_dtype), int(parts_per_cu), int(cu_count),
+                                   ctypes.byref(p)))
+    return {k: int(getattr(p, k)) for k, _ in mttkrp_plan._fields_}
 
 
 def mttkrp_layout_free(h: Layout):

@@ -29,10 +29,21 @@ mttkrp_status hip_fail(hipError_t e, const char* what)
 }
 
 constexpr uint64_t kAlign = 256;
-constexpr uint32_t kMaxParts = 8192;    // partitions per launch at most (sizes the carry buffer)
+constexpr uint32_t kMaxParts = 8192;    // partitions per launch at most, below kMaxChain-bound tensors
+constexpr uint64_t kMaxChain = 4096;    // nonzeros one lane group adds in one FP32 register chain, at most
 constexpr int kAlsBlocks = 512;         // row blocks of the CP-ALS reductions
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Partition cap of a tensor with nnz nonzeros (sizes its carry buffer): the
+// default cap, raised where it would make a lane group's run (gsz) longer than
+// kMaxChain nonzeros.  The fewest lane groups per workgroup of any launch are
+// 16 (R = 64 fp32 rows, 256-thread workgroups).
+uint32_t max_parts_for(uint64_t nnz)
+{
+    const uint64_t need = (nnz + 16 * kMaxChain - 1) / (16 * kMaxChain);
+    return (uint32_t)std::max<uint64_t>(kMaxParts, need);
+}
 
 bool r_supported(int R) { return R == 16 || R == 32 || R == 64; }
 
@@ -41,7 +52,7 @@ struct Workspace {
     uint64_t total = 0;
 };
 
-Workspace plan_workspace(const uint32_t* dims, int N, int maxR, int dtype)
+Workspace plan_workspace(const uint32_t* dims, int N, uint64_t nnz, int maxR, int dtype)
 {
     Workspace w;
     uint64_t maxI = 0, sumI = 0;
@@ -50,7 +61,7 @@ Workspace plan_workspace(const uint32_t* dims, int N, int maxR, int dtype)
         sumI += dims[m];
     }
     const uint64_t R = (uint64_t)maxR;
-    w.carry = align_up(kMaxParts * 2ull * R * 4ull);
+    w.carry = align_up((uint64_t)max_parts_for(nnz) * 2ull * R * 4ull);
     w.grams = align_up((uint64_t)N * R * R * 8ull);
     w.V = align_up(R * R * 8ull);
     w.W = align_up(R * R * 8ull);
@@ -160,7 +171,7 @@ mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const 
     mttkrp_opts o;
     mttkrp_status s = check_opts(opts, &o);
     if (s) return s;
-    *bytes = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total +
+    *bytes = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
              hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows));
     return MTTKRP_OK;
 }
@@ -183,7 +194,7 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     // Admission first, before any device call (the hot tables are sized for the
     // largest LDS, an upper bound).
     {
-        const uint64_t bound = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total +
+        const uint64_t bound = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
                                hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows));
         if (!o.host_only && o.hbm_budget_bytes && bound > o.hbm_budget_bytes)
             return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(bound) + " B exceeds the budget of " +
@@ -199,7 +210,7 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
             lds_limit = (uint32_t)v;
     }
     const uint32_t nhot = hot_rows_for(N, o.max_R, lds_limit, o.hot_rows);
-    const uint64_t need = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, o.max_R, o.factor_dtype).total +
+    const uint64_t need = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
                           hot_bytes(N, nhot);
 
     auto* h = new mttkrp_layout();
@@ -251,7 +262,7 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
         return p;
     };
     // Workspace.
-    const Workspace ws = plan_workspace(dims, N, o.max_R, o.factor_dtype);
+    const Workspace ws = plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype);
     h->carry = static_cast<float*>(take(ws.carry));
     h->als.grams = static_cast<double*>(take(ws.grams));
     h->als.V = static_cast<double*>(take(ws.V));
@@ -372,6 +383,30 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info)
     return MTTKRP_OK;
 }
 
+mttkrp_status mttkrp_launch_plan(uint64_t nnz, int N, int R, int factor_dtype, int parts_per_cu, uint32_t cu_count,
+                                 mttkrp_plan* out)
+{
+    g_err.clear();
+    if (!out) return fail(MTTKRP_EINVAL, "NULL out");
+    if (N < 3 || N > MTTKRP_MAX_MODES) return fail(MTTKRP_EUNSUPPORTED, "N must be between 3 and 8");
+    if (!r_supported(R)) return fail(MTTKRP_EUNSUPPORTED, "R must be 16, 32 or 64");
+    if (factor_dtype != MTTKRP_FP32 && factor_dtype != MTTKRP_BF16)
+        return fail(MTTKRP_EINVAL, "factor_dtype must be MTTKRP_FP32 or MTTKRP_BF16");
+    if (nnz >= (1ull << 32)) return fail(MTTKRP_EINVAL, "nnz must be below 2^32");
+    if (parts_per_cu <= 0) parts_per_cu = 8;
+    if (cu_count == 0) cu_count = 256;
+    const mk::Geometry g =
+        mk::plan_geometry(nnz, N - 1, R, factor_dtype, parts_per_cu * (int)cu_count, max_parts_for(nnz), kMaxChain);
+    out->wg_threads = (uint32_t)mk::partition_wg_threads(N - 1);
+    out->lane_groups = (uint32_t)g.groups;
+    out->lanes_per_group = (uint32_t)g.lanes;
+    out->nonzeros_per_group = g.gsz;
+    out->nonzeros_per_part = g.wgc;
+    out->nparts = nnz ? g.nparts : 0;
+    out->carry_bytes = (uint64_t)max_parts_for(nnz) * 2ull * (uint64_t)R * 4ull;
+    return MTTKRP_OK;
+}
+
 void mttkrp_layout_free(mttkrp_handle h)
 {
     if (!h) return;
@@ -440,7 +475,7 @@ static mttkrp_status run_mode(mttkrp_handle h, int mode, const void* const* fact
         fac[j] = factors[d.in_modes[j]];
         hot[j] = h->hot_rows[d.in_modes[j]];
     }
-    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, dtype, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, dtype, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz), kMaxChain);
     hipError_t e = mk::launch_mttkrp(d, R, dtype, fac, hot, h->nhot, out, h->carry, g, stream);
     if (e != hipSuccess) return hip_fail(e, "MTTKRP launch");
     return MTTKRP_OK;
@@ -478,7 +513,7 @@ mttkrp_status mttkrp_run_scheme2(mttkrp_handle h, int mode, const float* const* 
         hot[j] = h->hot_rows[d.in_modes[j]];
     }
     const mk::Geometry g =
-        mk::plan_geometry(d.nnz, d.n_in, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+        mk::plan_geometry(d.nnz, d.n_in, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz), kMaxChain);
     hipError_t e = mk::launch_mttkrp(d, R, MTTKRP_FP32, fac, hot, h->nhot, out, h->carry, g, stream, true,
                                      h->dims[mode]);
     if (e != hipSuccess) return hip_fail(e, "MTTKRP (scheme 2) launch");
@@ -501,7 +536,7 @@ mttkrp_status mttkrp_gather_probe(mttkrp_handle h, int mode, const void* const* 
     const void* fac[mk::kMaxIn];
     for (int j = 0; j < d.n_in; ++j) fac[j] = factors[d.in_modes[j]];
     const mk::Geometry g =
-        mk::plan_geometry(d.nnz, d.n_in, R, factor_dtype, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+        mk::plan_geometry(d.nnz, d.n_in, R, factor_dtype, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz), kMaxChain);
     hipError_t e = mk::launch_gather_probe(d, R, factor_dtype, fac, h->carry, g, what, stream);
     if (e != hipSuccess) return hip_fail(e, "gather probe launch");
     return MTTKRP_OK;
@@ -702,6 +737,9 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
         if (!h || h->host_only) return fail(MTTKRP_EINVAL, "layout " + std::to_string(t) + " is NULL or host-only");
         if (h->N != N) return fail(MTTKRP_EINVAL, "all layouts of a batch need the same N");
         if (R > h->opts.max_R) return fail(MTTKRP_EINVAL, "R exceeds the max_R of layout " + std::to_string(t));
+        if (h->nhot)
+            return fail(MTTKRP_EUNSUPPORTED, "layout " + std::to_string(t) +
+                                                 " keeps hot rows in LDS; batches take layouts built with hot_rows = 0");
         for (int m = 0; m < N; ++m)
             if ((uint64_t)h->dims[m] * (uint64_t)R * 4ull >= 0xFFFFFFF0ull)
                 return fail(MTTKRP_EUNSUPPORTED, "a factor of layout " + std::to_string(t) + " is 4 GiB or larger");
@@ -722,7 +760,7 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
         for (int t = 0; t < count; ++t) {
             const mttkrp_handle h = b->hs[t];
             b->geo[n][t] =
-                mk::plan_geometry(h->nnz, N - 1, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count, kMaxParts);
+                mk::plan_geometry(h->nnz, N - 1, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz), kMaxChain);
             max_parts[t] = std::max(max_parts[t], b->geo[n][t].nparts);
         }
     // Work lists (largest tensors first, which balances the resident grid).

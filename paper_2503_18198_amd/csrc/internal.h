@@ -37,7 +37,11 @@ struct Geometry {
     uint32_t nparts;    // workgroups
 };
 
-Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts);
+// Partitions of about nnz / target_parts nonzeros, with at most max_parts
+// partitions and, unless max_parts forbids it, at most max_gsz nonzeros per
+// lane group (the length of its FP32 accumulation chain).
+Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts,
+                       uint32_t max_gsz);
 
 // Threads per partition workgroup for n_in input modes.
 int partition_wg_threads(int n_in);

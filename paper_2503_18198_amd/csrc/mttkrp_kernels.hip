@@ -153,15 +153,17 @@ __global__ __launch_bounds__(kWG) void mttkrp_batch_fixup_kernel(const FixArgs* 
 
 }  // namespace
 
-Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts)
+Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts, uint32_t max_gsz)
 {
     Geometry g;
     g.lanes = lanes_per_row(R, dtype);
     g.groups = part_wg(n_in) / g.lanes;
     if (target_parts < 1) target_parts = 1;
+    max_gsz = max_gsz < 32 ? 32 : max_gsz / 32 * 32;
     uint64_t per_group = (nnz + (uint64_t)target_parts * g.groups - 1) / ((uint64_t)target_parts * g.groups);
     uint64_t gsz = (per_group + 31) / 32 * 32;
     if (gsz < 32) gsz = 32;
+    if (gsz > max_gsz) gsz = max_gsz;   // bound every lane group's FP32 accumulation chain
     uint64_t wgc = gsz * g.groups;
     uint64_t parts = (nnz + wgc - 1) / wgc;
     if (parts > max_parts) {

@@ -205,5 +205,27 @@ def pin_invariants(f, seed=4, tol=1e-12):
         assert np.all(np.isfinite(f(idx, val, dims, Az, n)))
 
 
+def pin_large_dense_and_slices(f, seed=5, tol=1e-12):
+    """P1 and P3 on tensors of 6,000 to 9,000 nonzeros (duplicates included), so
+    that an implementation which switches strategy above a few thousand
+    nonzeros (the oracle goes multi-threaded at 4,096) is pinned there too."""
+    rng = np.random.default_rng(seed)
+    for dims in [(20, 18, 16), (9, 8, 7, 6)]:
+        nnz = 6000 if len(dims) == 3 else 2800
+        idx, val = rand_coo(rng, dims, nnz=nnz, dup=3000)
+        assert idx.shape[0] >= 5000
+        R = 3
+        A = rand_factors(rng, dims, R)
+        X = dense(idx, val, dims)
+        for n in range(len(dims)):
+            ref = unfold(X, n) @ khatri_rao([A[m] for m in cyclic_order(n, len(dims))])
+            e = rel_fro(f(idx, val, dims, A, n), ref)
+            assert e <= tol, f"large dense-KR pin: dims={dims} mode={n} rel={e:.3e}"
+            ones = [np.ones((d, R)) for d in dims]
+            s = np.bincount(idx[:, n].astype(np.int64), weights=val, minlength=dims[n])
+            e = rel_fro(f(idx, val, dims, ones, n), np.repeat(s[:, None], R, axis=1))
+            assert e <= tol, f"large slice-sum pin: dims={dims} mode={n} rel={e:.3e}"
+
+
 ALL_PINS = [pin_dense_khatri_rao, pin_rank1_closed_form, pin_slice_sums, pin_matrix_case, pin_handworked,
-            pin_invariants]
+            pin_invariants, pin_large_dense_and_slices]

@@ -232,3 +232,36 @@ def test_header_symbols_exported():
     lib = ctypes.CDLL(capi.LIB_PATH)
     for name in declared:
         assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("N,R,dtype", [(3, 32, capi.MTTKRP_FP32), (3, 64, capi.MTTKRP_FP32), (4, 64, capi.MTTKRP_FP32),
+                                       (5, 16, capi.MTTKRP_FP32), (4, 64, capi.MTTKRP_BF16), (8, 16, capi.MTTKRP_FP32)])
+@pytest.mark.parametrize("nnz", [0, 1, 33, 20_000_000, 100_000_000, 2_200_000_000, 4_000_000_000, 2**32 - 1])
+def test_launch_plan_bounds_every_chain(N, R, dtype, nnz):
+    """For every nnz the header accepts, each lane group's FP32 register chain
+    is at most 4096 nonzeros (sequential FP32 sums past a few thousand terms
+    lose the 1e-5 bar), the partitions cover every nonzero once, and the carry
+    buffer holds two rows per partition."""
+    p = capi.mttkrp_launch_plan(nnz, N, R, dtype)
+    assert p["nonzeros_per_group"] % 32 == 0 and 32 <= p["nonzeros_per_group"] <= 4096
+    assert p["nonzeros_per_part"] == p["nonzeros_per_group"] * p["lane_groups"]
+    assert p["lane_groups"] * p["lanes_per_group"] == p["wg_threads"]
+    if nnz:
+        assert (p["nparts"] - 1) * p["nonzeros_per_part"] < nnz <= p["nparts"] * p["nonzeros_per_part"]
+    else:
+        assert p["nparts"] == 0
+    assert p["carry_bytes"] >= p["nparts"] * 2 * R * 4
+    # the default target: about 8 partitions per CU of a 256-CU device (fewer by
+    # the round-up of each run to whole 32-nonzero batches) while chains allow it
+    if 20_000_000 <= nnz <= 100_000_000 and N == 3:
+        assert 0.8 * 2048 <= p["nparts"] <= 2048 + 256
+
+
+def test_launch_plan_errors():
+    for args in [(10, 2, 32), (10, 9, 32), (10, 3, 48)]:
+        with pytest.raises(capi.MttkrpError) as e:
+            capi.mttkrp_launch_plan(*args)
+        assert e.value.status == capi.MTTKRP_EUNSUPPORTED
+    with pytest.raises(capi.MttkrpError) as e:
+        capi.mttkrp_launch_plan(2**32, 3, 32)
+    assert e.value.status == capi.MTTKRP_EINVAL

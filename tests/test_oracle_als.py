@@ -60,6 +60,27 @@ def test_fit_formula_equals_dense_residual():
         assert abs(fit - fit_dense) <= 1e-10, (fit, fit_dense)
 
 
+def test_fit_with_duplicate_coordinates_equals_dense_residual():
+    """Duplicate coordinates are one entry of X holding their sum (linearity of
+    the elementwise definition), so |X|^2 must be taken after merging them.
+    X is built densely with np.add.at, independently of the oracle's merge;
+    the fit after each sweep must equal 1 - |X - Xhat| / |X| on it."""
+    rng = np.random.default_rng(12)
+    dims = (9, 8, 7)
+    idx, val = pins.rand_coo(rng, dims, 120, dup=60)
+    val = np.abs(val) + 0.1
+    A0 = [rng.uniform(0.0, 1.0, (d, 4)) for d in dims]
+    X = pins.dense(idx, val, dims)
+    assert abs(np.sum(X * X) - np.sum(val * val)) > 1.0   # the merge matters here
+    st = oracle.als_init(idx, val, dims, A0)
+    assert abs(st.normX2 - float(np.sum(X * X))) <= 1e-12 * float(np.sum(X * X))
+    for _ in range(3):
+        fit = oracle.als_iteration(st, idx, val, dims)
+        Xh = dense_reconstruction(st.factors, st.lam)
+        fit_dense = 1.0 - np.linalg.norm(X - Xh) / np.linalg.norm(X)
+        assert abs(fit - fit_dense) <= 1e-10, (fit, fit_dense)
+
+
 def test_solve_mode_is_least_squares_solution():
     """A_n = M V^{-1} is the normal-equation solution: compare with lstsq on
     the explicit Khatri-Rao system (tiny dense case)."""
@@ -147,6 +168,10 @@ def _check_all():
     except (AssertionError, np.linalg.LinAlgError):
         failed.append("dense-residual")
     try:
+        test_fit_with_duplicate_coordinates_equals_dense_residual()
+    except (AssertionError, np.linalg.LinAlgError):
+        failed.append("duplicates")
+    try:
         fit, fms = run_recovery(seeds=range(2), iters=60)
         assert fit >= 0.99 and fms >= 0.95
     except (AssertionError, np.linalg.LinAlgError):
@@ -159,7 +184,7 @@ def test_checks_pass_for_correct_oracle():
 
 
 @pytest.mark.parametrize("kind", ["own_gram_in_V", "no_inverse", "lam_not_squared_out", "stale_gram",
-                                  "inner_sign"])
+                                  "inner_sign", "no_merge"])
 def test_checks_catch_planted_als_mistake(kind, monkeypatch):
     if kind == "own_gram_in_V":
         orig = als.hadamard_of_grams
@@ -171,6 +196,9 @@ def test_checks_catch_planted_als_mistake(kind, monkeypatch):
         monkeypatch.setattr(als, "normalize_columns", lambda A: (orig(A)[0], np.sqrt(orig(A)[1])))
     elif kind == "stale_gram":
         monkeypatch.setattr(als, "gram", lambda A: np.eye(np.asarray(A).shape[1]) * 0 + np.asarray(A)[:1].T @ np.asarray(A)[:1] + np.eye(np.asarray(A).shape[1]))
+    elif kind == "no_merge":
+        # |X|^2 as the sum of the squared entries as given, duplicates not merged
+        monkeypatch.setattr(als, "coalesce", lambda idx, val: (np.asarray(idx), np.asarray(val, dtype=np.float64)))
     elif kind == "inner_sign":
         orig = als.fit_from_parts
         monkeypatch.setattr(als, "fit_from_parts",

@@ -26,9 +26,25 @@ def test_oracle_passes_pin(pin):
     pin(oracle_f)
 
 
-@pytest.mark.parametrize("pin", [pins.pin_dense_khatri_rao, pins.pin_invariants], ids=lambda p: p.__name__)
+@pytest.mark.parametrize("pin", [pins.pin_dense_khatri_rao, pins.pin_invariants, pins.pin_large_dense_and_slices],
+                         ids=lambda p: p.__name__)
 def test_threaded_oracle_passes_pin(pin):
     pin(oracle_f_threads)
+
+
+def test_large_pin_reaches_threaded_branch():
+    """The large pin's tensors are above the oracle's serial cut-off (4,096
+    nonzeros), so with threads > 1 they run the thread-private branch; a
+    planted mistake confined to that branch (one thread's slice dropped) is
+    caught by it."""
+    def drop_last_thread_slice(idx, val, dims, factors, mode):
+        idx = np.asarray(idx)
+        if idx.shape[0] >= 4096:
+            keep = idx.shape[0] - idx.shape[0] // 3
+            idx, val = idx[:keep], np.asarray(val)[:keep]
+        return oracle.mttkrp(idx, val, dims, factors, mode, threads=3)
+    with pytest.raises(AssertionError):
+        pins.pin_large_dense_and_slices(drop_last_thread_slice)
 
 
 def test_threaded_matches_serial_large():

@@ -107,6 +107,33 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
                                   const uint32_t* dims, int N, const mttkrp_opts* opts,
                                   hipStream_t stream, mttkrp_handle* out);
 
+/* Device scratch bytes mttkrp_layout_build_in needs beside the handle's own
+ * memory, for these dims, nnz and opts: the sort and decode buffers of the
+ * device build (about nnz * (4N + 48) bytes), or 0 when the copies will be
+ * built on the host (opts->build_on_host, hot rows, keys over 128 bits).
+ * Host only; opts may be NULL. */
+mttkrp_status mttkrp_build_scratch_bytes(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts* opts,
+                                         uint64_t* bytes /* host, out */);
+
+/* As mttkrp_layout_build, but in caller-owned device memory, for callers that
+ * must not allocate or free device memory from the library (a serving loop
+ * whose other streams must keep running: freeing device memory synchronises
+ * the whole device).
+ *   dev_mem:     device, 256-byte aligned, dev_bytes >= mttkrp_footprint(...);
+ *                the handle borrows it: keep it until mttkrp_layout_free and
+ *                until every enqueued call that uses the handle has completed
+ *   dev_scratch: device, 256-byte aligned, scratch_bytes >=
+ *                mttkrp_build_scratch_bytes(...), used only during this call;
+ *                may be NULL (then the copies are built on the host)
+ * The copies are identical to mttkrp_layout_build's.  The call synchronises
+ * `stream` (only) before it returns.  mttkrp_layout_free of such a handle
+ * releases host state only and never waits on the device.  Errors as
+ * mttkrp_layout_build; MTTKRP_EINVAL when dev_bytes is too small. */
+mttkrp_status mttkrp_layout_build_in(const uint32_t* coo_idx, const float* vals, uint64_t nnz,
+                                     const uint32_t* dims, int N, const mttkrp_opts* opts, void* dev_mem,
+                                     uint64_t dev_bytes, void* dev_scratch, uint64_t scratch_bytes,
+                                     hipStream_t stream, mttkrp_handle* out);
+
 /* Device bytes held by the handle (0 for a host-only handle). */
 uint64_t mttkrp_layout_bytes(mttkrp_handle h);
 
@@ -220,7 +247,7 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
  * outs:    host array of count device pointers, tensor t's I_mode x R fp32
  *          output (overwritten).
  * When the pointers differ from the previous call's, the descriptor tables
- * are re-uploaded, which synchronises the stream first. */
+ * are re-uploaded on `stream`, which is then synchronised (only it). */
 mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* const* factors, float* const* outs,
                                hipStream_t stream);
 
@@ -252,8 +279,24 @@ mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int
                                     int n_candidates, const float* const* factors, float* const* outs, int reps,
                                     hipStream_t stream, int* best_ppc, float* times_ms);
 
-/* Release a batch (not its layouts).  NULL is ignored. */
+/* Release a batch (not its layouts).  A batch that allocated its own device
+ * memory synchronises the device first; one from mttkrp_batch_create_in
+ * releases host state only.  NULL is ignored. */
 void mttkrp_batch_free(mttkrp_batch_handle b);
+
+/* Device bytes mttkrp_batch_create_in needs for these layouts and R (host
+ * only; the same checks as mttkrp_batch_create). */
+mttkrp_status mttkrp_batch_bytes(const mttkrp_handle* layouts, int count, int R, uint64_t* bytes /* host, out */);
+
+/* As mttkrp_batch_create, in caller-owned device memory (dev_mem: 256-byte
+ * aligned, dev_bytes >= mttkrp_batch_bytes), for callers that must not make
+ * the library allocate or free device memory.  The tables are uploaded on
+ * `stream`, which is synchronised (only it) before the call returns.  Keep
+ * dev_mem until mttkrp_batch_free and until every enqueued call using the
+ * batch has completed. */
+mttkrp_status mttkrp_batch_create_in(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
+                                     void* dev_mem, uint64_t dev_bytes, hipStream_t stream,
+                                     mttkrp_batch_handle* out);
 
 /* As cpd_als_iter, but only enqueued: nothing is read back and the stream is
  * not synchronised, so sweeps can be captured into a HIP graph and replayed.
@@ -267,8 +310,9 @@ mttkrp_status cpd_als_iter_async(mttkrp_handle h, float* const* factors, double*
  * stream. */
 mttkrp_status cpd_als_status(mttkrp_handle h, hipStream_t stream);
 
-/* Release a handle and all of its device memory (synchronises the device).
- * NULL is ignored. */
+/* Release a handle.  A handle from mttkrp_layout_build frees its device
+ * memory and synchronises the device first; one from mttkrp_layout_build_in
+ * releases host state only (the caller owns the memory).  NULL is ignored. */
 void mttkrp_layout_free(mttkrp_handle h);
 
 /* Message of the last failed call on this thread ("" if none). */

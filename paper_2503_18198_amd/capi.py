@@ -29,7 +29,8 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_run_bf16", "cpd_als_init", "cpd_als_iter", "mttkrp_layout_free", "mttkrp_last_error",
             "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create", "mttkrp_batch_run",
             "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
-            "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan"]
+            "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
+            "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes", "mttkrp_batch_create_in"]
 
 
 class MttkrpError(RuntimeError):
@@ -105,10 +106,20 @@ def _load():
     lib.mttkrp_batch_free.restype = None
     lib.mttkrp_launch_plan.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_uint32, ctypes.POINTER(mttkrp_plan)]
+    lib.mttkrp_build_scratch_bytes.argtypes = [u32p, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(mttkrp_opts),
+                                               ctypes.POINTER(ctypes.c_uint64)]
+    lib.mttkrp_layout_build_in.argtypes = [u32p, f32p, ctypes.c_uint64, u32p, ctypes.c_int,
+                                           ctypes.POINTER(mttkrp_opts), vp, ctypes.c_uint64, vp, ctypes.c_uint64,
+                                           vp, ctypes.POINTER(vp)]
+    lib.mttkrp_batch_bytes.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+    lib.mttkrp_batch_create_in.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(mttkrp_opts), vp, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
     for name in ("mttkrp_footprint", "mttkrp_layout_build", "mttkrp_run", "mttkrp_run_bf16", "cpd_als_init",
                  "cpd_als_iter", "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create",
                  "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
-                 "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan"):
+                 "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
+                 "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes",
+                 "mttkrp_batch_create_in"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -164,11 +175,12 @@ def mttkrp_footprint(dims: Sequence[int], nnz: int, opts=None) -> int:
 class Layout:
     """Owns an ``mttkrp_handle``; released by ``mttkrp_layout_free`` or on collection."""
 
-    def __init__(self, ptr: int, dims, nnz: int, host_only: bool):
+    def __init__(self, ptr: int, dims, nnz: int, host_only: bool, dev_mem=None):
         self._ptr = ptr
         self.dims = tuple(int(x) for x in dims)
         self.nnz = int(nnz)
         self.host_only = host_only
+        self.dev_mem = dev_mem      # caller-owned device memory the handle borrows (mttkrp_layout_build_in)
 
     @property
     def ptr(self) -> int:
@@ -180,6 +192,7 @@ class Layout:
         if self._ptr:
             _lib.mttkrp_layout_free(ctypes.c_void_p(self._ptr))
             self._ptr = 0
+        self.dev_mem = None
 
     def __del__(self):
         try:
@@ -203,6 +216,39 @@ def mttkrp_layout_build(idx: np.ndarray, vals: np.ndarray, dims: Sequence[int], 
                                     ctypes.byref(o) if o is not None else None,
                                     ctypes.c_void_p(0 if host_only else _stream(stream)), ctypes.byref(h)))
     return Layout(h.value, dims, idx.shape[0], host_only)
+
+
+def mttkrp_build_scratch_bytes(dims: Sequence[int], nnz: int, opts=None) -> int:
+    d = _dims(dims)
+    out = ctypes.c_uint64()
+    o = _opts(opts)
+    _check(_lib.mttkrp_build_scratch_bytes(d.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), d.shape[0], int(nnz),
+                                           ctypes.byref(o) if o is not None else None, ctypes.byref(out)))
+    return int(out.value)
+
+
+def mttkrp_layout_build_in(idx: np.ndarray, vals: np.ndarray, dims: Sequence[int], dev_mem, dev_scratch=None,
+                           opts=None, stream=None) -> Layout:
+    """Build into caller-owned device memory: ``dev_mem`` (a uint8 device
+    tensor of at least ``mttkrp_footprint`` bytes) is kept by the returned
+    layout until it is freed; ``dev_scratch`` (``mttkrp_build_scratch_bytes``,
+    or None for a host build) is used during the call only."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    vals = np.ascontiguousarray(vals, dtype=np.float32).reshape(-1)
+    d = _dims(dims)
+    if idx.ndim != 2 or idx.shape[1] != d.shape[0] or idx.shape[0] != vals.shape[0]:
+        raise MttkrpError(MTTKRP_EINVAL, "idx must be (nnz, N) with N = len(dims) and len(vals) = nnz")
+    o = _opts(opts)
+    h = ctypes.c_void_p()
+    nb = lambda t: 0 if t is None else int(t.numel() * t.element_size())
+    _check(_lib.mttkrp_layout_build_in(idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                       vals.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), idx.shape[0],
+                                       d.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), d.shape[0],
+                                       ctypes.byref(o) if o is not None else None,
+                                       ctypes.c_void_p(int(dev_mem.data_ptr())), nb(dev_mem),
+                                       ctypes.c_void_p(0 if dev_scratch is None else int(dev_scratch.data_ptr())),
+                                       nb(dev_scratch), ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+    return Layout(h.value, dims, idx.shape[0], False, dev_mem=dev_mem)
 
 
 def mttkrp_layout_bytes(h: Layout) -> int:
@@ -358,10 +404,11 @@ def mttkrp_layout_view(h: Layout, mode: int) -> dict:
 class Batch:
     """Owns an ``mttkrp_batch_handle``; keeps its layouts alive."""
 
-    def __init__(self, ptr: int, layouts, R: int):
+    def __init__(self, ptr: int, layouts, R: int, dev_mem=None):
         self._ptr = ptr
         self.layouts = list(layouts)
         self.R = R
+        self.dev_mem = dev_mem      # caller-owned device memory (mttkrp_batch_create_in)
 
     @property
     def ptr(self) -> int:
@@ -373,6 +420,7 @@ class Batch:
         if self._ptr:
             _lib.mttkrp_batch_free(ctypes.c_void_p(self._ptr))
             self._ptr = 0
+        self.dev_mem = None
 
     def __del__(self):
         try:
@@ -388,6 +436,25 @@ def mttkrp_batch_create(layouts, R: int, opts=None) -> Batch:
     _check(_lib.mttkrp_batch_create(arr, len(layouts), int(R), ctypes.byref(o) if o is not None else None,
                                     ctypes.byref(b)))
     return Batch(b.value, layouts, R)
+
+
+def mttkrp_batch_bytes(layouts, R: int) -> int:
+    arr = (ctypes.c_void_p * len(layouts))(*[h.ptr for h in layouts])
+    out = ctypes.c_uint64()
+    _check(_lib.mttkrp_batch_bytes(arr, len(layouts), int(R), ctypes.byref(out)))
+    return int(out.value)
+
+
+def mttkrp_batch_create_in(layouts, R: int, dev_mem, opts=None, stream=None) -> Batch:
+    """A batch whose tables live in ``dev_mem`` (a uint8 device tensor of at
+    least ``mttkrp_batch_bytes``), kept by the returned batch until freed."""
+    arr = (ctypes.c_void_p * len(layouts))(*[h.ptr for h in layouts])
+    o = _opts(opts)
+    b = ctypes.c_void_p()
+    _check(_lib.mttkrp_batch_create_in(arr, len(layouts), int(R), ctypes.byref(o) if o is not None else None,
+                                       ctypes.c_void_p(int(dev_mem.data_ptr())), int(dev_mem.numel()),
+                                       ctypes.c_void_p(_stream(stream)), ctypes.byref(b)))
+    return Batch(b.value, layouts, R, dev_mem=dev_mem)
 
 
 def mttkrp_batch_autotune(layouts, R: int, factors, outs, candidates=None, reps: int = 3, stream=None):

@@ -126,6 +126,7 @@ struct mttkrp_layout {
     mk::DevMode dev[MTTKRP_MAX_MODES];
     void* dmem = nullptr;
     uint64_t dbytes = 0;
+    bool owns_mem = true;                              // false: dmem is the caller's (mttkrp_layout_build_in)
     float* carry = nullptr;
     mk::AlsWork als;
     mk::InvJob inv_job_host{};                         // host source of als.job (kept alive for the copy)
@@ -176,10 +177,15 @@ mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const 
     return MTTKRP_OK;
 }
 
-mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, uint64_t nnz, const uint32_t* dims,
-                                  int N, const mttkrp_opts* opts, hipStream_t stream, mttkrp_handle* out)
+}  // extern "C"
+
+// The build behind mttkrp_layout_build (ext_mem == NULL: the handle allocates
+// and owns its device memory, and a device build allocates its own scratch)
+// and mttkrp_layout_build_in (the caller's memory and scratch; no allocation).
+static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint64_t nnz, const uint32_t* dims, int N,
+                                const mttkrp_opts* opts, void* ext_mem, uint64_t ext_bytes, void* ext_scratch,
+                                uint64_t ext_scratch_bytes, hipStream_t stream, mttkrp_handle* out)
 {
-    g_err.clear();
     if (!out) return fail(MTTKRP_EINVAL, "out handle pointer is NULL");
     *out = nullptr;
     if (N < 3 || N > MTTKRP_MAX_MODES) return fail(MTTKRP_EUNSUPPORTED, "N must be between 3 and 8");
@@ -240,20 +246,35 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
         h->cu_count = cus;
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b) {
-        delete h;
-        return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(need) + " B exceeds free device memory (" +
-                                       std::to_string(free_b) + " B)");
-    }
-    e = hipMalloc(&h->dmem, need);
-    if (e != hipSuccess) {
-        h->dmem = nullptr;
-        delete h;
-        (void)hipGetLastError();
-        return fail(MTTKRP_ENOMEM, "hipMalloc of " + std::to_string(need) + " B failed");
+    if (ext_mem) {
+        if (ext_bytes < need) {
+            delete h;
+            return fail(MTTKRP_EINVAL, "dev_mem holds " + std::to_string(ext_bytes) + " B; the layout needs " +
+                                           std::to_string(need) + " B (mttkrp_footprint)");
+        }
+        h->dmem = ext_mem;
+        h->owns_mem = false;
+    } else {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b) {
+            delete h;
+            return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(need) + " B exceeds free device memory (" +
+                                           std::to_string(free_b) + " B)");
+        }
+        e = hipMalloc(&h->dmem, need);
+        if (e != hipSuccess) {
+            h->dmem = nullptr;
+            delete h;
+            (void)hipGetLastError();
+            return fail(MTTKRP_ENOMEM, "hipMalloc of " + std::to_string(need) + " B failed");
+        }
     }
     h->dbytes = need;
+    // Releases the device memory of a handle that failed to build (the caller's is left alone).
+    auto drop = [&]() {
+        if (h->owns_mem) (void)hipFree(h->dmem);
+        delete h;
+    };
     char* base = static_cast<char*>(h->dmem);
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) -> void* {
@@ -291,7 +312,10 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
 
     double normX2 = 0.0;
-    if (e == hipSuccess && !o.build_on_host && nhot == 0 && mk::device_build_applies(dims, N, nnz)) {
+    // With the caller's memory the device build runs only in the caller's scratch.
+    const bool dev_build = !o.build_on_host && nhot == 0 && mk::device_build_applies(dims, N, nnz) &&
+                           (!ext_mem || (ext_scratch && ext_scratch_bytes >= mk::device_build_scratch_bytes(dims, N, nnz)));
+    if (e == hipSuccess && dev_build) {
         // Mode copies sorted and laid out on the device.
         const uint64_t nnz_pad = (nnz + 31) / 32 * 32;
         std::vector<mk::DeviceModeSlots> slots(N);
@@ -302,12 +326,12 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
             slots[n].rows = static_cast<uint32_t*>(take((uint64_t)dims[n] * 4));
         }
         if (off > need) {
-            (void)hipFree(h->dmem);
-            delete h;
+            drop();
             return fail(MTTKRP_EHIP, "internal: mode copies exceed the planned device footprint");
         }
         std::vector<mk::DevMode> modes;
-        e = mk::build_device_modes(coo_idx, vals, nnz, dims, N, slots, modes, &normX2, stream);
+        e = mk::build_device_modes(coo_idx, vals, nnz, dims, N, slots, modes, &normX2, ext_mem ? ext_scratch : nullptr,
+                                   ext_mem ? ext_scratch_bytes : 0, stream);
         if (e == hipSuccess)
             for (int n = 0; n < N; ++n) h->dev[n] = modes[n];
     }
@@ -361,12 +385,48 @@ mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, ui
     h->normX2 = normX2;
     if (e != hipSuccess) {
         mttkrp_status st = hip_fail(e, "uploading the mode copies");
-        (void)hipFree(h->dmem);
-        delete h;
+        drop();
         return st;
     }
     *out = h;
     return MTTKRP_OK;
+}
+
+extern "C" {
+
+mttkrp_status mttkrp_layout_build(const uint32_t* coo_idx, const float* vals, uint64_t nnz, const uint32_t* dims,
+                                  int N, const mttkrp_opts* opts, hipStream_t stream, mttkrp_handle* out)
+{
+    g_err.clear();
+    return build_impl(coo_idx, vals, nnz, dims, N, opts, nullptr, 0, nullptr, 0, stream, out);
+}
+
+mttkrp_status mttkrp_build_scratch_bytes(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts* opts,
+                                         uint64_t* bytes)
+{
+    g_err.clear();
+    if (!dims || !bytes) return fail(MTTKRP_EINVAL, "dims and bytes must not be NULL");
+    if (N < 3 || N > MTTKRP_MAX_MODES) return fail(MTTKRP_EUNSUPPORTED, "N must be between 3 and 8");
+    for (int m = 0; m < N; ++m)
+        if (dims[m] == 0 || dims[m] > 0x7fffffffu) return fail(MTTKRP_EINVAL, "dims must be in [1, 2^31-1]");
+    mttkrp_opts o;
+    mttkrp_status s = check_opts(opts, &o);
+    if (s) return s;
+    *bytes = (!o.build_on_host && o.hot_rows == 0) ? mk::device_build_scratch_bytes(dims, N, nnz) : 0;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_layout_build_in(const uint32_t* coo_idx, const float* vals, uint64_t nnz, const uint32_t* dims,
+                                     int N, const mttkrp_opts* opts, void* dev_mem, uint64_t dev_bytes,
+                                     void* dev_scratch, uint64_t scratch_bytes, hipStream_t stream, mttkrp_handle* out)
+{
+    g_err.clear();
+    if (!dev_mem || reinterpret_cast<uintptr_t>(dev_mem) % kAlign)
+        return fail(MTTKRP_EINVAL, "dev_mem must be a 256-byte aligned device pointer");
+    if (dev_scratch && reinterpret_cast<uintptr_t>(dev_scratch) % kAlign)
+        return fail(MTTKRP_EINVAL, "dev_scratch must be 256-byte aligned");
+    if (opts && opts->host_only) return fail(MTTKRP_EINVAL, "host_only layouts hold no device memory");
+    return build_impl(coo_idx, vals, nnz, dims, N, opts, dev_mem, dev_bytes, dev_scratch, scratch_bytes, stream, out);
 }
 
 uint64_t mttkrp_layout_bytes(mttkrp_handle h) { return h ? h->dbytes : 0; }
@@ -410,7 +470,7 @@ mttkrp_status mttkrp_launch_plan(uint64_t nnz, int N, int R, int factor_dtype, i
 void mttkrp_layout_free(mttkrp_handle h)
 {
     if (!h) return;
-    if (h->dmem) {
+    if (h->dmem && h->owns_mem) {
         (void)hipDeviceSynchronize();
         (void)hipFree(h->dmem);
     }
@@ -689,6 +749,7 @@ struct mttkrp_batch {
     int count = 0, N = 0, R = 0;
     std::vector<mttkrp_handle> hs;
     void* dmem = nullptr;
+    bool owns_mem = true;                                 // false: dmem is the caller's (mttkrp_batch_create_in)
     float* carry = nullptr;
     std::vector<uint64_t> carry_off;                      // per tensor, in floats
     std::vector<std::vector<mk::Geometry>> geo;           // [mode][tensor]
@@ -712,19 +773,25 @@ extern "C" {
 void mttkrp_batch_free(mttkrp_batch_handle b)
 {
     if (!b) return;
-    if (b->dmem) {
+    if (b->dmem && b->owns_mem) {
         (void)hipDeviceSynchronize();
         (void)hipFree(b->dmem);
     }
     delete b;
 }
 
-mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
-                                  mttkrp_batch_handle* out)
+}  // extern "C"
+
+// The batch set-up behind mttkrp_batch_create (ext_mem == NULL: allocate,
+// upload with blocking copies), mttkrp_batch_create_in (the caller's memory,
+// uploads on `stream`, then that stream is synchronised) and
+// mttkrp_batch_bytes (bytes_only: report the device bytes, build nothing).
+static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
+                                void* ext_mem, uint64_t ext_bytes, hipStream_t stream, bool bytes_only,
+                                uint64_t* bytes_out, mttkrp_batch_handle* out)
 {
-    g_err.clear();
-    if (!out) return fail(MTTKRP_EINVAL, "NULL out");
-    *out = nullptr;
+    if (!out && !bytes_only) return fail(MTTKRP_EINVAL, "NULL out");
+    if (out) *out = nullptr;
     if (!layouts || count <= 0) return fail(MTTKRP_EINVAL, "need at least one layout");
     if (!r_supported(R)) return fail(MTTKRP_EUNSUPPORTED, "R must be 16, 32 or 64");
     mttkrp_opts o;
@@ -798,13 +865,34 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
     for (int n = 0; n < N; ++n)
         need += align_up((uint64_t)count * pdb) + align_up((uint64_t)count * fdb) + align_up(pw[n].size() * 8 + 8) +
                 align_up(fw[n].size() * 8 + 8);
-    hipError_t e = hipMalloc(&b->dmem, need);
-    if (e != hipSuccess) {
-        b->dmem = nullptr;
+    if (bytes_only) {
         delete b;
-        (void)hipGetLastError();
-        return fail(MTTKRP_ENOMEM, "hipMalloc of " + std::to_string(need) + " B for the batch failed");
+        *bytes_out = need;
+        return MTTKRP_OK;
     }
+    hipError_t e = hipSuccess;
+    if (ext_mem) {
+        if (ext_bytes < need) {
+            delete b;
+            return fail(MTTKRP_EINVAL, "dev_mem holds " + std::to_string(ext_bytes) + " B; the batch needs " +
+                                           std::to_string(need) + " B (mttkrp_batch_bytes)");
+        }
+        b->dmem = ext_mem;
+        b->owns_mem = false;
+    } else {
+        e = hipMalloc(&b->dmem, need);
+        if (e != hipSuccess) {
+            b->dmem = nullptr;
+            delete b;
+            (void)hipGetLastError();
+            return fail(MTTKRP_ENOMEM, "hipMalloc of " + std::to_string(need) + " B for the batch failed");
+        }
+    }
+    // Host-to-device copies of the tables: blocking, or on the caller's stream.
+    auto upload = [&](void* dst, const void* src, uint64_t n) -> hipError_t {
+        return ext_mem ? hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, stream)
+                       : hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
+    };
     char* base = static_cast<char*>(b->dmem);
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) -> char* {
@@ -814,16 +902,14 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
     };
     b->carry = reinterpret_cast<float*>(take(carry_floats * 4));
     b->inv_jobs = reinterpret_cast<mk::InvJob*>(take((uint64_t)count * sizeof(mk::InvJob)));
-    {
-        std::vector<mk::InvJob> jobs(count);
-        for (int t = 0; t < count; ++t) jobs[t] = b->hs[t]->inv_job_host;
-        e = hipMemcpy(b->inv_jobs, jobs.data(), jobs.size() * sizeof(mk::InvJob), hipMemcpyHostToDevice);
-    }
+    std::vector<mk::InvJob> inv_jobs(count);   // kept until the copies are done (end of this function)
+    for (int t = 0; t < count; ++t) inv_jobs[t] = b->hs[t]->inv_job_host;
+    e = upload(b->inv_jobs, inv_jobs.data(), inv_jobs.size() * sizeof(mk::InvJob));
     for (int n = 0; n <= N; ++n) b->dense_jobs[n] = reinterpret_cast<mk::DenseJob*>(take((uint64_t)count * sizeof(mk::DenseJob)));
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         b->dense_work[n] = reinterpret_cast<uint2*>(take(dw[n].size() * 8 + 8));
         b->ndense_work[n] = (uint32_t)dw[n].size();
-        if (!dw[n].empty()) e = hipMemcpy(b->dense_work[n], dw[n].data(), dw[n].size() * 8, hipMemcpyHostToDevice);
+        if (!dw[n].empty()) e = upload(b->dense_work[n], dw[n].data(), dw[n].size() * 8);
     }
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         b->part_desc[n] = take((uint64_t)count * pdb);
@@ -832,10 +918,13 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
         b->fix_work[n] = reinterpret_cast<uint2*>(take(fw[n].size() * 8 + 8));
         b->npart_work[n] = (uint32_t)pw[n].size();
         b->nfix_work[n] = (uint32_t)fw[n].size();
-        if (!pw[n].empty())
-            e = hipMemcpy(b->part_work[n], pw[n].data(), pw[n].size() * 8, hipMemcpyHostToDevice);
-        if (e == hipSuccess && !fw[n].empty())
-            e = hipMemcpy(b->fix_work[n], fw[n].data(), fw[n].size() * 8, hipMemcpyHostToDevice);
+        if (!pw[n].empty()) e = upload(b->part_work[n], pw[n].data(), pw[n].size() * 8);
+        if (e == hipSuccess && !fw[n].empty()) e = upload(b->fix_work[n], fw[n].data(), fw[n].size() * 8);
+    }
+    if (ext_mem) {
+        // the host tables above go out of scope: wait for their copies (this stream only)
+        const hipError_t es = hipStreamSynchronize(stream);
+        if (e == hipSuccess) e = es;
     }
     if (e != hipSuccess) {
         mttkrp_status s2 = hip_fail(e, "mttkrp_batch_create");
@@ -846,6 +935,31 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
     b->grid_fix = (uint32_t)cus * 8u;
     *out = b;
     return MTTKRP_OK;
+}
+
+extern "C" {
+
+mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
+                                  mttkrp_batch_handle* out)
+{
+    g_err.clear();
+    return batch_impl(layouts, count, R, opts, nullptr, 0, nullptr, false, nullptr, out);
+}
+
+mttkrp_status mttkrp_batch_bytes(const mttkrp_handle* layouts, int count, int R, uint64_t* bytes)
+{
+    g_err.clear();
+    if (!bytes) return fail(MTTKRP_EINVAL, "NULL bytes");
+    return batch_impl(layouts, count, R, nullptr, nullptr, 0, nullptr, true, bytes, nullptr);
+}
+
+mttkrp_status mttkrp_batch_create_in(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
+                                     void* dev_mem, uint64_t dev_bytes, hipStream_t stream, mttkrp_batch_handle* out)
+{
+    g_err.clear();
+    if (!dev_mem || reinterpret_cast<uintptr_t>(dev_mem) % kAlign)
+        return fail(MTTKRP_EINVAL, "dev_mem must be a 256-byte aligned device pointer");
+    return batch_impl(layouts, count, R, opts, dev_mem, dev_bytes, stream, false, nullptr, out);
 }
 
 mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* const* factors, float* const* outs,
@@ -884,9 +998,11 @@ mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* con
             mk::fill_part_desc(pd.data() + (size_t)t * pdb, d, R, MTTKRP_FP32, fac, outs[t], carry, g.gsz);
             mk::fill_fix_desc(fd.data() + (size_t)t * fdb, d, g, carry, outs[t], R);
         }
-        e = hipStreamSynchronize(stream);
-        if (e == hipSuccess) e = hipMemcpy(b->part_desc[mode], pd.data(), pd.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(b->fix_desc[mode], fd.data(), fd.size(), hipMemcpyHostToDevice);
+        // Stream-ordered after the launches that read the old tables; the host
+        // copies are waited for before they go out of scope (this stream only).
+        e = hipMemcpyAsync(b->part_desc[mode], pd.data(), pd.size(), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b->fix_desc[mode], fd.data(), fd.size(), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "uploading batch descriptors");
         b->last_ptrs[mode] = std::move(ptrs);
     }
@@ -1007,9 +1123,9 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
         }
         if (jobs.size() != b->last_jobs[n].size() ||
             std::memcmp(jobs.data(), b->last_jobs[n].data(), jobs.size() * sizeof(mk::DenseJob)) != 0) {
-            e = hipStreamSynchronize(stream);
-            if (e == hipSuccess)
-                e = hipMemcpy(b->dense_jobs[n], jobs.data(), jobs.size() * sizeof(mk::DenseJob), hipMemcpyHostToDevice);
+            e = hipMemcpyAsync(b->dense_jobs[n], jobs.data(), jobs.size() * sizeof(mk::DenseJob), hipMemcpyHostToDevice,
+                               stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
             if (e == hipSuccess) b->last_jobs[n] = std::move(jobs);
         }
     }

@@ -150,11 +150,16 @@ struct DeviceModeSlots {
 // and the packed coordinate key (all N indices) fits 128 bits.
 bool device_build_applies(const uint32_t* dims, int N, uint64_t nnz);
 
+// Device scratch bytes of build_device_modes (0 when the device build does not apply).
+uint64_t device_build_scratch_bytes(const uint32_t* dims, int N, uint64_t nnz);
+
 // Build all N mode copies on the device into `slots` (same arrays and order as
 // the host build) and the duplicate-merged |X|^2; uploads the COO tensor to a
-// scratch allocation that is freed before returning.  Synchronises `s`.
+// scratch region: ext_scratch (256-byte aligned, at least
+// device_build_scratch_bytes) or, when that is NULL, an allocation freed
+// before returning.  Synchronises `s`.
 hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, uint64_t nnz, const uint32_t* dims,
                               int N, const std::vector<DeviceModeSlots>& slots, std::vector<DevMode>& modes,
-                              double* normX2, hipStream_t s);
+                              double* normX2, void* ext_scratch, uint64_t ext_scratch_bytes, hipStream_t s);
 
 }  // namespace mk

@@ -173,16 +173,22 @@ bool device_build_applies(const uint32_t* dims, int N, uint64_t nnz)
     return bits <= 128;   // the key of every mode holds all N fields
 }
 
-hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, uint64_t nnz, const uint32_t* dims,
-                              int N, const std::vector<DeviceModeSlots>& slots, std::vector<DevMode>& modes,
-                              double* normX2, hipStream_t s)
+namespace {
+
+// Byte offsets of the device build's scratch arrays in one allocation.
+struct ScratchPlan {
+    uint64_t o_coo, o_val, o_key, o_tkey, o_hi, o_pos, o_tpos, o_sq, o_bits, o_cnt, o_before, o_flag, o_small, o_cub;
+    uint64_t cub_b, total;
+};
+
+hipError_t plan_scratch(const uint32_t* dims, int N, uint64_t nnz, ScratchPlan& p)
 {
     const uint64_t nnz_pad = (nnz + 31) / 32 * 32;
     const uint64_t nwords = nnz_pad / 32;
     uint32_t max_dim = 0;
     for (int m = 0; m < N; ++m) max_dim = std::max(max_dim, dims[m]);
-
-    // hipCUB scratch sizes
+    // hipCUB scratch sizes (size queries only: nothing is enqueued)
+    hipStream_t s = nullptr;
     size_t sort_b = 0, scan_b = 0, sel_b = 0, red_b = 0;
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                                                       (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)nnz, 0, 64, s);
@@ -196,28 +202,61 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
     if (e == hipSuccess)
         e = hipcub::DeviceReduce::Sum(nullptr, red_b, (const double*)nullptr, (double*)nullptr, (int)nnz, s);
     if (e != hipSuccess) return e;
-    const size_t cub_b = std::max(std::max(sort_b, scan_b), std::max(sel_b, red_b));
-
-    // one scratch allocation, freed before returning
+    p.cub_b = std::max(std::max(sort_b, scan_b), std::max(sel_b, red_b));
     auto al = [](uint64_t b) { return (b + 255) / 256 * 256; };
-    const uint64_t o_coo = 0;
-    const uint64_t o_val = o_coo + al(nnz * N * 4);
-    const uint64_t o_key = o_val + al(nnz * 4);
-    const uint64_t o_tkey = o_key + al(nnz * 8);
-    const uint64_t o_hi = o_tkey + al(nnz * 8);
-    const uint64_t o_pos = o_hi + al(nnz * 8);
-    const uint64_t o_tpos = o_pos + al(nnz * 4);
-    const uint64_t o_sq = o_tpos + al(nnz * 4);
-    const uint64_t o_bits = o_sq + al(nnz * 8);
-    const uint64_t o_cnt = o_bits + al(nwords * 4);
-    const uint64_t o_before = o_cnt + al(nwords * 4);
-    const uint64_t o_flag = o_before + al(nwords * 4);
-    const uint64_t o_small = o_flag + al(max_dim);
-    const uint64_t o_cub = o_small + 256;
-    const uint64_t total = o_cub + al(cub_b);
-    char* base = nullptr;
-    e = hipMalloc(&base, total);
+    p.o_coo = 0;
+    p.o_val = p.o_coo + al(nnz * N * 4);
+    p.o_key = p.o_val + al(nnz * 4);
+    p.o_tkey = p.o_key + al(nnz * 8);
+    p.o_hi = p.o_tkey + al(nnz * 8);
+    p.o_pos = p.o_hi + al(nnz * 8);
+    p.o_tpos = p.o_pos + al(nnz * 4);
+    p.o_sq = p.o_tpos + al(nnz * 4);
+    p.o_bits = p.o_sq + al(nnz * 8);
+    p.o_cnt = p.o_bits + al(nwords * 4);
+    p.o_before = p.o_cnt + al(nwords * 4);
+    p.o_flag = p.o_before + al(nwords * 4);
+    p.o_small = p.o_flag + al(max_dim);
+    p.o_cub = p.o_small + 256;
+    p.total = p.o_cub + al(p.cub_b);
+    return hipSuccess;
+}
+
+}  // namespace
+
+uint64_t device_build_scratch_bytes(const uint32_t* dims, int N, uint64_t nnz)
+{
+    if (!device_build_applies(dims, N, nnz)) return 0;
+    ScratchPlan p;
+    if (plan_scratch(dims, N, nnz, p) != hipSuccess) return 0;
+    return p.total;
+}
+
+hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, uint64_t nnz, const uint32_t* dims,
+                              int N, const std::vector<DeviceModeSlots>& slots, std::vector<DevMode>& modes,
+                              double* normX2, void* ext_scratch, uint64_t ext_scratch_bytes, hipStream_t s)
+{
+    const uint64_t nnz_pad = (nnz + 31) / 32 * 32;
+    const uint64_t nwords = nnz_pad / 32;
+    uint32_t max_dim = 0;
+    for (int m = 0; m < N; ++m) max_dim = std::max(max_dim, dims[m]);
+    ScratchPlan sp;
+    hipError_t e = plan_scratch(dims, N, nnz, sp);
     if (e != hipSuccess) return e;
+    const size_t cub_b = sp.cub_b;
+    const uint64_t o_coo = sp.o_coo, o_val = sp.o_val, o_key = sp.o_key, o_tkey = sp.o_tkey, o_hi = sp.o_hi,
+                   o_pos = sp.o_pos, o_tpos = sp.o_tpos, o_sq = sp.o_sq, o_bits = sp.o_bits, o_cnt = sp.o_cnt,
+                   o_before = sp.o_before, o_flag = sp.o_flag, o_small = sp.o_small, o_cub = sp.o_cub;
+    // One scratch region: the caller's, or an allocation freed before returning.
+    char* base = nullptr;
+    const bool own = ext_scratch == nullptr;
+    if (own) {
+        e = hipMalloc(&base, sp.total);
+        if (e != hipSuccess) return e;
+    } else {
+        if (ext_scratch_bytes < sp.total || reinterpret_cast<uintptr_t>(ext_scratch) % 256) return hipErrorInvalidValue;
+        base = static_cast<char*>(ext_scratch);
+    }
     uint32_t* d_coo = (uint32_t*)(base + o_coo);
     float* d_val = (float*)(base + o_val);
     uint64_t* d_key = (uint64_t*)(base + o_key);
@@ -338,7 +377,10 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
         }
     }
     if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // The scratch is released (or handed back) only once every kernel above is done.
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
+    if (!own) return e;
     const hipError_t ef = hipFree(base);
     return e != hipSuccess ? e : ef;
 }

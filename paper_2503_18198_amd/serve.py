@@ -69,6 +69,11 @@ class Executor:
     def footprint(self, job: ServeJob) -> int:
         raise NotImplementedError
 
+    def build_bytes(self, job: ServeJob) -> int:
+        """Transient device bytes admit() holds while it builds the job's state
+        (returned to the budget once the build is done)."""
+        return 0
+
     def admit(self, job: ServeJob):
         """Build the job's device state; returns an opaque slot."""
         raise NotImplementedError
@@ -127,8 +132,13 @@ class CpdServer:
         self.log: List[Tuple[float, str, int]] = []
 
     def _admit(self, job: ServeJob):
+        """The job's device state, or the exception that stopped its build
+        (a failed build fails that job only)."""
         t = time.perf_counter()
-        slot = self.ex.admit(job)
+        try:
+            slot = self.ex.admit(job)
+        except Exception as e:      # noqa: BLE001 - reported as the job's status
+            slot = e
         with self._admit_lock:
             self.admit_s += time.perf_counter() - t
         return slot
@@ -149,6 +159,22 @@ class CpdServer:
         done: List[ServeJob] = []
         t0 = self.clock()
         pi = 0
+
+        def built(job: ServeJob, slot):
+            """A build has ended: hand back its transient bytes; a failed one
+            also hands back the job's reservation and slot."""
+            nonlocal n_active
+            self.in_use -= self.ex.build_bytes(job)
+            if isinstance(slot, Exception):
+                self.in_use -= self.ex.footprint(job)
+                n_active -= 1
+                job.status = f"failed: build: {slot}"
+                job.finished_s = self.clock() - t0
+                done.append(job)
+                self.log.append((job.finished_s, "fail", job.job_id))
+                return
+            ready.setdefault(self.ex.group_key(slot), []).append((job, slot))
+
         while pi < len(pending) or waiting or n_active:
             now = self.clock() - t0
             while pi < len(pending) and pending[pi].arrival_s <= now:
@@ -157,7 +183,7 @@ class CpdServer:
             # admission in arrival order, by slot and by memory
             while waiting and n_active < self.max_slots:
                 job = waiting[0]
-                need = self.ex.footprint(job)
+                need = self.ex.footprint(job) + self.ex.build_bytes(job)
                 if need > self.budget:
                     waiting.pop(0)
                     job.status = "rejected: footprint over the whole budget"
@@ -174,18 +200,18 @@ class CpdServer:
                 job.status = "running"
                 if pool is not None:
                     job.admitted_s = self.clock() - t0
+                    self.log.append((job.admitted_s, "admit", job.job_id))
                     building.append((job, pool.submit(self._admit, job)))
                 else:
                     slot = self._admit(job)
                     job.admitted_s = self.clock() - t0
-                    ready.setdefault(self.ex.group_key(slot), []).append((job, slot))
-                self.log.append((job.admitted_s, "admit", job.job_id))
+                    self.log.append((job.admitted_s, "admit", job.job_id))
+                    built(job, slot)
             if building:
                 still_building = []
                 for job, fut in building:
                     if fut.done():
-                        slot = fut.result()
-                        ready.setdefault(self.ex.group_key(slot), []).append((job, slot))
+                        built(job, fut.result())
                     else:
                         still_building.append((job, fut))
                 building = still_building
@@ -271,7 +297,15 @@ class GpuExecutor(Executor):
     its own sweep, with no batch tables to rebuild).  A job's results are
     bitwise the same either way.  A launched sweep ends with an asynchronous
     copy of the group's fits to pinned host memory and an event; poll()
-    queries the event, so groups advance without waiting for each other."""
+    queries the event, so groups advance without waiting for each other.
+
+    Layouts and batch tables live in device memory from torch's caching
+    allocator (``mttkrp_layout_build_in``, ``mttkrp_batch_create_in``): the
+    library neither allocates nor frees it, and memory handed back after a
+    job retires is reused in stream order (``record_stream``), so admitting
+    and retiring jobs never synchronises the whole device.  The only host
+    waits are on one stream: a retiring group's stream before its results are
+    read back, and the build's own stream."""
 
     def __init__(self, batched: bool = True):
         import torch
@@ -287,9 +321,21 @@ class GpuExecutor(Executor):
         lib = self.capi.mttkrp_footprint(job.dims, job.nnz, opts=dict(max_R=job.R))
         return lib + sum(int(d) * job.R * 4 for d in job.dims) + 16 * job.R
 
+    def build_bytes(self, job: ServeJob) -> int:
+        return self.capi.mttkrp_build_scratch_bytes(job.dims, job.nnz, opts=dict(max_R=job.R))
+
+    def _bytes(self, n: int):
+        # 256-byte aligned by torch's allocator
+        return self.torch.empty(max(int(n), 1), dtype=self.torch.uint8, device="cuda")
+
     def admit(self, job: ServeJob):
         torch = self.torch
-        h = self.capi.mttkrp_layout_build(job.idx, job.val, job.dims, opts=dict(max_R=job.R))
+        opts = dict(max_R=job.R)
+        mem = self._bytes(self.capi.mttkrp_footprint(job.dims, job.nnz, opts=opts))
+        nscr = self.capi.mttkrp_build_scratch_bytes(job.dims, job.nnz, opts=opts)
+        scratch = self._bytes(nscr) if nscr else None
+        h = self.capi.mttkrp_layout_build_in(job.idx, job.val, job.dims, mem, scratch, opts=opts)
+        del scratch       # back to torch's cache; the build synchronised its stream
         # initial factors U(0,1) drawn on the device from the job's seed
         g = torch.Generator(device="cuda")
         g.manual_seed(int(job.seed))
@@ -318,14 +364,22 @@ class GpuExecutor(Executor):
         st = g["stream"]
         # factors and state of newly admitted jobs were written on the current stream
         st.wait_stream(torch.cuda.current_stream())
+        for m in slots:
+            if not m.get("recorded"):
+                # memory made on another stream, used on the group's: reused only after the group's work
+                for t in [m["h"].dev_mem, m["lam"], m["fit"], *m["F"]]:
+                    t.record_stream(st)
+                m["recorded"] = True
         with torch.cuda.stream(st):
             if self.batched and len(slots) > 1:
                 ids = tuple(id(m["h"]) for m in slots)
                 old = self._batches.get(key)
                 if old is None or old[0] != ids:
                     if old is not None:
-                        old[1].free()      # the group's previous sweep has completed
-                    self._batches[key] = (ids, self.capi.mttkrp_batch_create([m["h"] for m in slots], key[1]))
+                        old[1].free()      # host state only; its memory returns to torch's cache
+                    hs = [m["h"] for m in slots]
+                    mem = self._bytes(self.capi.mttkrp_batch_bytes(hs, key[1]))
+                    self._batches[key] = (ids, self.capi.mttkrp_batch_create_in(hs, key[1], mem, stream=st))
                 b = self._batches[key][1]
                 self.capi.cpd_als_batch_iter_async(b, [m["F"] for m in slots], [m["lam"] for m in slots],
                                                    [m["fit"] for m in slots], stream=st)

@@ -262,7 +262,49 @@ def test_builds_on_worker_threads_overlap_and_give_the_same_results():
     assert runs[0][1] == runs[4][1]
 
 
-def test_a_failed_build_is_raised():
+@pytest.mark.parametrize("threads", [0, 2])
+def test_a_failed_build_fails_that_job_only(threads):
+    """A build that raises (say, out of device memory near the budget) marks
+    its job failed and hands back its reservation; the other jobs run on."""
     ex = SlowBuildExecutor(build_s=0.001, dt=0.0005, fail_id=2)
-    with pytest.raises(RuntimeError, match="build failed"):
-        CpdServer(ex, 10 ** 9, 8, build_threads=2).run(make_jobs(4, gap=0.0))
+    srv = CpdServer(ex, 10 ** 9, 8, build_threads=threads)
+    jobs = make_jobs(4, gap=0.0)
+    m = srv.run(jobs)
+    assert m["failed"] == 1 and m["completed"] == 3
+    assert jobs[2].status.startswith("failed: build") and "build failed" in jobs[2].status
+    assert all(j.status in ("converged", "max_iters") for j in jobs if j.job_id != 2)
+    assert srv.in_use == 0
+
+
+class ScratchExecutor(SlowBuildExecutor):
+    """Each build holds `scratch` transient bytes beside the job's footprint;
+    records the server's reservation while builds run."""
+
+    def __init__(self, scratch, **kw):
+        super().__init__(**kw)
+        self.scratch = scratch
+        self.seen = []
+
+    def build_bytes(self, job):
+        return self.scratch
+
+    def admit(self, job):
+        self.seen.append(self.srv.in_use)
+        return super().admit(job)
+
+
+def test_build_scratch_is_reserved_while_building():
+    """Admission counts a job's footprint plus its build scratch; the scratch
+    is handed back once the build ends, so afterwards only footprints stay
+    reserved, and a budget that fits two builds at once never holds three."""
+    fp = 100 * 10 + 10 * 10     # largest footprint of make_jobs(6): nnz * 10
+    ex = ScratchExecutor(scratch=5000, build_s=0.01, dt=0.0005)
+    budget = 2 * (fp + 5000) + fp // 2
+    srv = CpdServer(ex, budget, 8, build_threads=4)
+    ex.srv = srv
+    jobs = make_jobs(6, gap=0.0)
+    m = srv.run(jobs)
+    assert m["completed"] == 6 and srv.in_use == 0
+    assert ex.peak_running <= 2
+    assert srv.peak_in_use <= budget
+    assert max(ex.seen) >= 5000   # some build ran while another build's scratch was reserved

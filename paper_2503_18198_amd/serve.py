@@ -290,6 +290,16 @@ class CpdServer:
         }
 
 
+def initial_factors(dims, R: int, seed: int):
+    """A job's starting factors: U(0,1) fp32, drawn on the current GPU from
+    the job's seed (torch's device generator), one (I_m, R) matrix per mode in
+    mode order.  The same seed gives the same bits."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed))
+    return [torch.rand((int(d), int(R)), generator=g, device="cuda", dtype=torch.float32) for d in dims]
+
+
 class GpuExecutor(Executor):
     """Device state per job: layout handle, fp32 factors, lambda and fit on
     the GPU.  Jobs are grouped by (N, R); each group has its own stream and
@@ -336,10 +346,7 @@ class GpuExecutor(Executor):
         scratch = self._bytes(nscr) if nscr else None
         h = self.capi.mttkrp_layout_build_in(job.idx, job.val, job.dims, mem, scratch, opts=opts)
         del scratch       # back to torch's cache; the build synchronised its stream
-        # initial factors U(0,1) drawn on the device from the job's seed
-        g = torch.Generator(device="cuda")
-        g.manual_seed(int(job.seed))
-        F = [torch.rand((d, job.R), generator=g, device="cuda", dtype=torch.float32) for d in job.dims]
+        F = initial_factors(job.dims, job.R, job.seed)
         lam = torch.zeros(job.R, dtype=torch.float64, device="cuda")
         fit = torch.zeros(1, dtype=torch.float64, device="cuda")
         self.capi.cpd_als_init(h, F, job.R)

@@ -140,3 +140,89 @@ def test_iter_requires_init():
         capi.cpd_als_iter(h, dF, lam, 16)
     assert e.value.status == capi.MTTKRP_EINVAL
     h.free()
+
+
+def _with_duplicates(t, frac, seed):
+    """The tensor plus `frac` of its nonzeros again, each copy at the same
+    coordinate with a fresh value, all shuffled: a COO list whose coordinates
+    repeat, which the library must merge by adding (linearity of Eq. (1))."""
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(t.nnz, int(frac * t.nnz), replace=False)
+    idx = np.concatenate([t.idx, t.idx[pick]])
+    val = np.concatenate([t.val, rng.uniform(0.0, 1.0, pick.size).astype(np.float32)])
+    perm = rng.permutation(idx.shape[0])
+    return workloads.SparseTensor(idx=np.ascontiguousarray(idx[perm]), val=np.ascontiguousarray(val[perm]),
+                                  dims=tuple(t.dims), nnz_requested=int(idx.shape[0]))
+
+
+@pytest.mark.parametrize("build_on_host", [0, 1])
+def test_fit_with_duplicate_coordinates_vs_oracle(build_on_host):
+    """Repeated coordinates are one entry holding their sum, so |X|^2 (and the
+    fit) must be taken after merging.  Same start, four sweeps: the GPU fits
+    (device and host layout builds) against the FP64 oracle, which merges the
+    duplicates before |X|^2, within 1e-6 absolute."""
+    print("case als duplicates, host build", build_on_host, flush=True)
+    base = workloads.random_tensor((700, 500, 300), 60_000, dist="zipf", s=1.2, seed=21)
+    t = _with_duplicates(base, 0.3, seed=22)
+    R = 16
+    F0 = workloads.random_factors(t.dims, R, seed=23)
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, build_on_host=build_on_host))
+    dF = gu.dev_factors(F0)
+    lam = torch.empty(R, dtype=torch.float64, device="cuda")
+    fit = torch.empty(1, dtype=torch.float64, device="cuda")
+    capi.cpd_als_init(h, dF, R)
+    gpu = []
+    for _ in range(4):
+        capi.cpd_als_iter(h, dF, lam, R, fit)
+        torch.cuda.synchronize()
+        gpu.append(float(fit.item()))
+    h.free()
+    st = oracle.cp_als(t.idx, t.val, t.dims, F0, n_iter=4, threads=8)
+    # the merged tensor's |X|^2 differs from the sum of squares of the raw list
+    _, merged = oracle.coalesce(t.idx, t.val)
+    raw = float(np.sum(t.val.astype(np.float64) ** 2))
+    assert abs(float(np.sum(merged * merged)) - raw) > 1e-3 * raw
+    print("gpu fits", gpu, "oracle fits", st.fits, flush=True)
+    assert np.max(np.abs(np.array(gpu) - np.array(st.fits))) <= 1e-6
+
+
+def test_ill_conditioned_normal_equations():
+    """Nearly collinear factor columns make V = Hadamard of the Grams SPD but
+    ill-conditioned (cond ~ 6e6 here).  The GPU update (FP64 sweep-operator
+    inverse, FP32 store) must satisfy the normal equations of the first mode
+    it updates, and agree with the oracle's Cholesky solve of the same M (the
+    GPU's own FP32 MTTKRP, bitwise the one the sweep uses) to the accuracy the
+    conditioning allows: |dA| / |A| <= cond(V) * 1e-14 + 1e-6.  Solving from
+    the FP64 M instead would compare the MTTKRP's rounding amplified by
+    cond(V), not the solve."""
+    print("case als ill-conditioned V", flush=True)
+    t = workloads.random_tensor((900, 700, 500), 50_000, seed=31)
+    R = 16
+    rng = np.random.default_rng(32)
+    F0 = []
+    for d in t.dims:
+        base = rng.uniform(0.5, 1.0, (d, 1))
+        F0.append((base + 1e-3 * rng.standard_normal((d, R))).astype(np.float32))
+    F64 = [f.astype(np.float64) for f in F0]
+    V = oracle.hadamard_of_grams([oracle.gram(f) for f in F64], skip=0)
+    cond = float(np.linalg.cond(V))
+    print(f"  cond(V) = {cond:.2e}", flush=True)
+    assert 1e5 < cond < 1e11
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R))
+    dF = gu.dev_factors(F0)
+    M = gu.gpu_mttkrp(h, 0, dF, R).astype(np.float64)
+    M64 = oracle.mttkrp(t.idx, t.val.astype(np.float64), t.dims, F64, 0, threads=8)
+    assert gu.rel_fro(M, M64) <= 1e-5
+    A_ref, _ = oracle.normalize_columns(oracle.solve_mode(M, V))
+    lam = torch.empty(R, dtype=torch.float64, device="cuda")
+    capi.cpd_als_init(h, dF, R)
+    capi.cpd_als_iter(h, dF, lam, R)
+    torch.cuda.synchronize()
+    h.free()
+    # mode 0 is updated first, from the starting factors of modes 1 and 2
+    A0 = dF[0].cpu().numpy().astype(np.float64)
+    res, _ = normal_eq_residual(A0, V, M)
+    err = float(np.linalg.norm(A0 - A_ref) / np.linalg.norm(A_ref))
+    print(f"  normal-equation residual {res:.2e}, |dA|/|A| vs Cholesky {err:.2e}", flush=True)
+    assert res <= 2e-5
+    assert err <= cond * 1e-14 + 1e-6

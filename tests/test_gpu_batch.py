@@ -15,27 +15,31 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-def make_batch(count=12, seed=3, R=16, empty=True):
+def make_batch(count=12, seed=3, R=16, empty=True, nmodes=3, dist="uniform"):
     rng = np.random.default_rng(seed)
     ts = []
     for i in range(count):
-        dims = tuple(int(x) for x in rng.integers(100, 600, size=3))
+        dims = tuple(int(x) for x in rng.integers(100, 600, size=nmodes))
         nnz = int(np.exp(rng.uniform(np.log(50), np.log(60_000))))
         if empty and i == count // 2:
             nnz = 0
-        ts.append(workloads.random_tensor(dims, nnz, seed=1000 + i))
+        ts.append(workloads.random_tensor(dims, nnz, dist=dist, s=1.2 if dist == "zipf" else None, seed=1000 + i))
     hs = [capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R)) for t in ts]
     F = [workloads.random_factors(t.dims, R, seed=2000 + i) for i, t in enumerate(ts)]
     dF = [gu.dev_factors(f) for f in F]
     return ts, hs, F, dF
 
 
-@pytest.mark.parametrize("R", [16, 32])
-def test_batch_matches_oracle_and_single(R):
-    print("case batch R", R, flush=True)
-    ts, hs, F, dF = make_batch(R=R)
+@pytest.mark.parametrize("nmodes,R,dist", [(3, 16, "uniform"), (3, 32, "uniform"), (3, 64, "zipf"),
+                                           (4, 32, "zipf"), (5, 16, "uniform"), (5, 64, "zipf")])
+def test_batch_matches_oracle_and_single(nmodes, R, dist):
+    """Every mode count and rank the serving mix uses (3-5 modes, R = 16, 32,
+    64), each batched instantiation against the oracle and bitwise against
+    the single-tensor run."""
+    print("case batch N", nmodes, "R", R, dist, flush=True)
+    ts, hs, F, dF = make_batch(R=R, nmodes=nmodes, dist=dist)
     b = capi.mttkrp_batch_create(hs, R)
-    for n in range(3):
+    for n in range(nmodes):
         outs = [torch.full((t.dims[n], R), float("nan"), device="cuda") for t in ts]
         capi.mttkrp_batch_run(b, n, dF, outs)
         torch.cuda.synchronize()
@@ -138,5 +142,40 @@ def test_autotune_picks_a_candidate_and_keeps_results():
     b.free()
     with pytest.raises(capi.MttkrpError):
         capi.mttkrp_batch_autotune(hs, R, dF, outs, candidates=[0])
+    for h in hs:
+        h.free()
+
+
+def test_batch256_workload_every_tensor():
+    """The batching workload at its stated shape: 256 3-mode tensors, dims
+    uniform in [100, 5000], nnz log-uniform in [1e3, 1e6] (35.3M nonzeros in
+    all), R = 16, launched with the autotuned partition count.  Every output
+    of every tensor and mode against the FP64 oracle (<= 1e-5 relative
+    Frobenius per tensor and mode) and bitwise against its single-tensor
+    run."""
+    print("case batch256 full workload", flush=True)
+    R = 16
+    ts = workloads.batch_tensors(256)
+    hs = [capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R)) for t in ts]
+    F = [workloads.random_factors(t.dims, R, seed=3000 + i) for i, t in enumerate(ts)]
+    dF = [gu.dev_factors(f) for f in F]
+    outs = [[torch.empty((d, R), device="cuda") for d in t.dims] for t in ts]
+    best, _ = capi.mttkrp_batch_autotune(hs, R, dF, outs, reps=2)
+    print("  autotuned parts_per_cu", best, flush=True)
+    b = capi.mttkrp_batch_create(hs, R)
+    worst = 0.0
+    for n in range(3):
+        o = [torch.full((t.dims[n], R), float("nan"), device="cuda") for t in ts]
+        capi.mttkrp_batch_run(b, n, dF, o)
+        torch.cuda.synchronize()
+        for i, t in enumerate(ts):
+            got = o[i].cpu().numpy()
+            e = gu.rel_fro(got, gu.oracle_mttkrp(t.idx, t.val, t.dims, F[i], n, threads=16))
+            worst = max(worst, e)
+            assert e <= TOL, f"tensor {i} mode {n}: rel err {e:.3e}"
+            assert np.array_equal(got.view(np.uint32), gu.gpu_mttkrp(hs[i], n, dF[i], R).view(np.uint32)), \
+                f"tensor {i} mode {n}: batched result differs from the single-tensor run"
+    print(f"  worst rel fro {worst:.2e}", flush=True)
+    b.free()
     for h in hs:
         h.free()

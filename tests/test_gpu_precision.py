@@ -2,11 +2,10 @@
 accumulation; FP64 Gram matrices and normal-equation solve), both against the
 FP64 oracle, on the 4-mode Zipf(1.1) lognormal-valued workload.
 
-Default size: the 50000 x 40000 x 30000 x 2000, 100M-nonzero workload scaled
-by 0.1 in every dimension and in nnz (same nonzeros per output row, so the
-same accumulation lengths); MTTKRP_PRECISION_SCALE=1 runs it at full size.
-With MTTKRP_PRECISION_REPORT=<path> the measured errors are written there as
-JSON.
+Default size: the full 50000 x 40000 x 30000 x 2000, 100M-nonzero workload
+(MTTKRP_PRECISION_SCALE=0.1 scales every dimension and nnz by 0.1 for a quick
+run).  With MTTKRP_PRECISION_REPORT=<path> the measured errors are written
+there as JSON.
 
 Bars, per mode and sampled output row (the heaviest rows and random ones):
 FP32 relative Frobenius error <= 1e-5.  BF16: every term val * prod(A_m) is
@@ -14,8 +13,13 @@ positive here (lognormal values, U(0,1) factors), so rounding each of the 3
 factor values to bfloat16 (relative error <= 2^-8 each) moves every term,
 and hence every sum, by a relative amount <= (1 + 2^-8)^3 - 1; plus 1e-5 for
 the FP32 accumulation.  CP-ALS: three sweeps from the same start, FP32 and
-BF16 fits against the FP64 oracle's fits; FP32 within 1e-4, BF16 within 1e-2
-(a sanity bound; the measured gap is reported)."""
+BF16 fits against the FP64 oracle's fits; FP32 within 1e-4.  BF16 within a
+first-order bound: the fit is 1 - |X - Xhat| / |X| and its sensitivity to the
+model inner product <X, Xhat> is <X, Xhat> / (|X| |X - Xhat|) per unit of
+relative error; rounding the N-1 input factors of every term to bfloat16
+moves <X, Xhat> by at most (N-1) 2^-8 relative when the rounding errors all
+align, so |fit_bf16 - fit| <= (N-1) 2^-8 <X, Xhat> / (|X| |X - Xhat|),
+evaluated on the oracle's final state."""
 
 import json
 import os
@@ -31,7 +35,7 @@ from tests import gpu_util as gu
 
 pytestmark = pytest.mark.gpu
 
-SCALE = float(os.environ.get("MTTKRP_PRECISION_SCALE", "0.1"))
+SCALE = float(os.environ.get("MTTKRP_PRECISION_SCALE", "1"))
 BF16_BOUND = (1 + 2.0 ** -8) ** 3 - 1 + 1e-5
 
 
@@ -105,9 +109,15 @@ def test_als_fits_fp32_bf16_vs_oracle(tensor):
     gap32 = max(abs(a - b) for a, b in zip(fits["fp32"], fits["oracle_fp64"]))
     gap16 = max(abs(a - b) for a, b in zip(fits["bf16"], fits["oracle_fp64"]))
     print(f"  fits {json.dumps(fits)}; max |fit - oracle|: fp32 {gap32:.2e}, bf16 {gap16:.2e}", flush=True)
-    _write({"als_R32": fits, "max_fit_gap": {"fp32": gap32, "bf16": gap16}}, "als")
+    N = len(t.dims)
+    xhat2 = float(st.lam @ oracle.hadamard_of_grams(st.grams) @ st.lam)
+    res = (1.0 - st.fits[-1]) * np.sqrt(st.normX2)
+    inner = 0.5 * (st.normX2 + xhat2 - res * res)
+    bound16 = (N - 1) * 2.0 ** -8 * inner / (np.sqrt(st.normX2) * res)
+    print(f"  bf16 fit bound {bound16:.2e} (<X,Xhat>/|X|^2 = {inner / st.normX2:.3f})", flush=True)
+    _write({"als_R32": fits, "max_fit_gap": {"fp32": gap32, "bf16": gap16}, "bf16_bound": bound16}, "als")
     assert gap32 <= 1e-4
-    assert gap16 <= 1e-2
+    assert gap16 <= bound16
 
 
 def _write(obj, key):

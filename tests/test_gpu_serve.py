@@ -1,12 +1,15 @@
 """The CP-ALS server on the GPU: jobs of different shapes and ranks arrive
 over time and share steps; every job's final factors must be bitwise the
-same as when it runs alone, and the FIFO one-at-a-time executor must agree."""
+same as when it runs alone, the FIFO one-at-a-time executor must agree, and
+every served job's fit trajectory must match the FP64 oracle's CP-ALS from
+the same starting factors."""
 
 import numpy as np
 import pytest
 
+import oracle
 import workloads
-from paper_2503_18198_amd.serve import CpdServer, GpuExecutor, ServeJob
+from paper_2503_18198_amd.serve import CpdServer, GpuExecutor, ServeJob, initial_factors
 
 pytestmark = pytest.mark.gpu
 
@@ -22,8 +25,12 @@ def jobs(specs, first=0):
     return out
 
 
+# 3, 4 and 5 modes at R = 16, 32 and 64: every (N, R) group the serving mix
+# has, with two jobs in most groups so their sweeps are batched.
 SPECS = [((300, 250, 200), 20000, 16, 0.0), ((400, 300, 350), 30000, 16, 0.0), ((200, 150, 120, 40), 15000, 32, 0.0),
-         ((350, 280, 260), 25000, 16, 0.05), ((250, 200, 150, 30), 12000, 32, 0.1), ((500, 400, 300), 40000, 32, 0.2)]
+         ((350, 280, 260), 25000, 16, 0.05), ((250, 200, 150, 30), 12000, 32, 0.1), ((500, 400, 300), 40000, 32, 0.2),
+         ((120, 100, 90, 80, 70), 15000, 64, 0.0), ((110, 95, 85, 75, 66), 12000, 64, 0.05),
+         ((300, 200, 150), 20000, 64, 0.1), ((90, 80, 70, 60, 50), 10000, 16, 0.15)]
 
 
 @pytest.mark.parametrize("build_threads", [0, 3])
@@ -64,3 +71,27 @@ def test_budget_limits_concurrency():
     srv = CpdServer(ex, hbm_budget_bytes=int(one * 1.5), max_slots=16)
     m = srv.run(js)
     assert m["completed"] == 4 and srv.peak_in_use <= int(one * 1.5)
+
+
+def test_served_fits_match_oracle():
+    """Each served job (run in the mix, batched with the others of its (N, R)
+    group) against the FP64 oracle's CP-ALS from the same starting factors for
+    the same number of sweeps: every fit of the trajectory within 1e-5
+    absolute and its final factors within 1e-3 relative Frobenius."""
+    print("case serve vs oracle", flush=True)
+    mix = jobs(SPECS)
+    m = CpdServer(GpuExecutor(batched=True), hbm_budget_bytes=8 << 30, max_slots=16).run(mix)
+    assert m["completed"] == len(SPECS), m
+    worst = 0.0
+    for j in mix:
+        F0 = [f.cpu().numpy() for f in initial_factors(j.dims, j.R, j.seed)]
+        st = oracle.cp_als(j.idx, j.val, j.dims, F0, n_iter=j.iters, threads=8)
+        gap = float(np.max(np.abs(np.array(j.fits) - np.array(st.fits))))
+        worst = max(worst, gap)
+        print(f"  job {j.job_id} N={len(j.dims)} R={j.R} sweeps {j.iters}: fit {j.fits[-1]:.6f} "
+              f"oracle {st.fits[-1]:.6f} max gap {gap:.1e}", flush=True)
+        assert len(j.fits) == len(st.fits) and gap <= 1e-5, f"job {j.job_id}"
+        for a, b in zip(j.result["factors"], st.factors):
+            e = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            assert e <= 1e-3, f"job {j.job_id}: factor rel err {e:.2e}"
+    print(f"  worst fit gap {worst:.1e}", flush=True)

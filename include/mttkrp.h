@@ -145,6 +145,24 @@ uint64_t mttkrp_layout_bytes(mttkrp_handle h);
 mttkrp_status mttkrp_run(mttkrp_handle h, int mode, const float* const* factors, float* out, int R,
                          hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): mttkrp_run
+ * with its carry rows (partials of rows cut by partition boundaries) in a
+ * fixed device array of mttkrp_noalloc_scratch_bytes() = 4 MiB that the
+ * library holds on each device it runs on until the process ends, instead
+ * of the handle's workspace.  The call allocates and frees nothing.  Same
+ * arguments, result (bitwise mttkrp_run's), layout and errors as
+ * mttkrp_run; in addition MTTKRP_EINVAL when the current device is not the
+ * handle's, and MTTKRP_ENOMEM when the launch needs more carry rows than the
+ * array holds (more than 8192 partitions at R = 64, 16384 at R = 32).  The
+ * array needs no clearing: every carry row the fix-up reads is written by the
+ * same call first.  All calls on one device share the array, so calls that
+ * overlap on one device (different streams, or different host threads) race
+ * and must be ordered by the caller. */
+mttkrp_status mttkrp_run_noalloc(mttkrp_handle h, int mode, const float* const* factors, float* out, int R,
+                                 hipStream_t stream);
+uint64_t mttkrp_noalloc_scratch_bytes(void);
+
 /* Same, with bfloat16 factor rows (uint16 bit patterns, I_m x R) gathered and
  * multiplied in FP32 with FP32 accumulation. */
 mttkrp_status mttkrp_run_bf16(mttkrp_handle h, int mode, const uint16_t* const* factors, float* out, int R,

@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libmttkrp_hip.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["capi.cpp", "layout.cpp", "layout_device.hip", "mttkrp_kernels.hip", "als_kernels.hip", "probe_kernels.hip"] + [
+SOURCES = ["capi.cpp", "layout.cpp", "layout_device.hip", "mttkrp_kernels.hip", "als_kernels.hip", "probe_kernels.hip",
+           "noalloc.hip"] + [
     f"part_n{n}.hip" for n in range(3, 9)
 ]
 

@@ -30,7 +30,8 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_layout_view", "mttkrp_layout_info", "mttkrp_batch_create", "mttkrp_batch_run",
             "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
             "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
-            "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes", "mttkrp_batch_create_in"]
+            "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes", "mttkrp_batch_create_in",
+            "mttkrp_run_noalloc", "mttkrp_noalloc_scratch_bytes"]
 
 
 class MttkrpError(RuntimeError):
@@ -84,6 +85,9 @@ def _load():
     lib.mttkrp_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
     lib.mttkrp_run_bf16.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
     lib.mttkrp_run_scheme2.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
+    lib.mttkrp_run_noalloc.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
+    lib.mttkrp_noalloc_scratch_bytes.argtypes = []
+    lib.mttkrp_noalloc_scratch_bytes.restype = ctypes.c_uint64
     lib.cpd_als_init.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
     lib.cpd_als_iter.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.c_int, vp, vp]
     lib.mttkrp_layout_free.argtypes = [vp]
@@ -119,7 +123,7 @@ def _load():
                  "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
                  "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
                  "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes",
-                 "mttkrp_batch_create_in"):
+                 "mttkrp_batch_create_in", "mttkrp_run_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -291,6 +295,17 @@ def mttkrp_run(h: Layout, mode: int, factors, out, R: Optional[int] = None, stre
     """out <- MTTKRP of the layout along ``mode`` with fp32 ``factors`` (list of N
     device tensors; the entry at ``mode`` may be None)."""
     _run(_lib.mttkrp_run, "fp32", h, mode, factors, out, R, stream)
+
+
+def mttkrp_run_noalloc(h: Layout, mode: int, factors, out, R: Optional[int] = None, stream=None):
+    """As mttkrp_run, with the carry rows in the library's fixed per-device
+    scratch array: allocates nothing.  Calls that overlap on one device race."""
+    _run(_lib.mttkrp_run_noalloc, "fp32", h, mode, factors, out, R, stream)
+
+
+def mttkrp_noalloc_scratch_bytes() -> int:
+    """Bytes of the fixed per-device scratch array mttkrp_run_noalloc uses."""
+    return int(_lib.mttkrp_noalloc_scratch_bytes())
 
 
 def mttkrp_run_scheme2(h: Layout, mode: int, factors, out, R: Optional[int] = None, stream=None):

@@ -550,6 +550,40 @@ mttkrp_status mttkrp_run(mttkrp_handle h, int mode, const float* const* factors,
     return run_mode(h, mode, reinterpret_cast<const void* const*>(factors), MTTKRP_FP32, out, R, stream);
 }
 
+}  // extern "C"
+
+mttkrp_status mk::set_error(mttkrp_status s, const char* msg) { return fail(s, msg); }
+
+mttkrp_status mk::run_fp32_with_carry(mttkrp_handle h, int mode, const float* const* factors, float* out, int R,
+                                      int device, float* carry, uint64_t carry_bytes, hipStream_t stream)
+{
+    g_err.clear();
+    mttkrp_status s = check_run(h, mode, reinterpret_cast<const void* const*>(factors), out, R);
+    if (s) return s;
+    if (h->device != device)
+        return fail(MTTKRP_EINVAL, "the current device (" + std::to_string(device) + ") is not the handle's (" +
+                                       std::to_string(h->device) + ")");
+    const mk::DevMode& d = h->dev[mode];
+    const void* fac[mk::kMaxIn];
+    const uint32_t* hot[mk::kMaxIn];
+    for (int j = 0; j < d.n_in; ++j) {
+        fac[j] = factors[d.in_modes[j]];
+        hot[j] = h->hot_rows[d.in_modes[j]];
+    }
+    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count,
+                                             max_parts_for(h->nnz), kMaxChain);
+    const uint64_t need = (uint64_t)g.nparts * 2ull * (uint64_t)R * sizeof(float);
+    if (need > carry_bytes)
+        return fail(MTTKRP_ENOMEM, "this launch needs " + std::to_string(need) + " B of carry rows (" +
+                                       std::to_string(g.nparts) + " partitions at R=" + std::to_string(R) +
+                                       "); the static scratch holds " + std::to_string(carry_bytes) + " B");
+    hipError_t e = mk::launch_mttkrp(d, R, MTTKRP_FP32, fac, hot, h->nhot, out, carry, g, stream);
+    if (e != hipSuccess) return hip_fail(e, "MTTKRP launch");
+    return MTTKRP_OK;
+}
+
+extern "C" {
+
 mttkrp_status mttkrp_run_bf16(mttkrp_handle h, int mode, const uint16_t* const* factors, float* out, int R,
                               hipStream_t stream)
 {

@@ -162,4 +162,14 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
                               int N, const std::vector<DeviceModeSlots>& slots, std::vector<DevMode>& modes,
                               double* normX2, void* ext_scratch, uint64_t ext_scratch_bytes, hipStream_t s);
 
+// Record `msg` as this thread's last error and return `s`.
+mttkrp_status set_error(mttkrp_status s, const char* msg);
+
+// mttkrp_run (fp32 factors) with the carry rows of partition-cut rows in
+// `carry` (device memory of `device`, carry_bytes long) instead of the
+// handle's workspace.  MTTKRP_EINVAL when `device` is not the handle's,
+// MTTKRP_ENOMEM when the launch needs more than carry_bytes.
+mttkrp_status run_fp32_with_carry(mttkrp_handle h, int mode, const float* const* factors, float* out, int R,
+                                  int device, float* carry, uint64_t carry_bytes, hipStream_t stream);
+
 }  // namespace mk

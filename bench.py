@@ -5,8 +5,12 @@ nonzeros with Zipf(1.2) index skew per mode, values U(0,1) fp32, rank 32, fp32
 factors.  One step = the MTTKRP along every mode in turn (the paper's total
 execution time sums the per-mode MTTKRP times), with the mode copies and
 factors resident in HBM before timing starts.  The CP-ALS sweep (MTTKRPs plus
-the FP64 normal-equation updates) and the host layout build are timed
-separately and reported in the same JSON line.
+the FP64 normal-equation updates) and the layout build are timed separately
+and reported in the same JSON line, and so are the second half of the metric:
+`batch` (256 small tensors: batched vs per-tensor launches, 20 CP-ALS sweeps
+in a HIP graph) and `serve` (Poisson CP-ALS jobs at 0.95 and 2 x the plain
+method's capacity: jobs/s and p50/p99 latency, continuous batching vs one job
+at a time).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one
 GPU.
@@ -30,6 +34,7 @@ if ROOT not in sys.path:
 METRIC = "all-mode spMTTKRP GFLOP/s & HBM % peak; batched req/s + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 
+DEFAULT_WORKLOAD = "zipf1.2-20M-R32"
 WORKLOADS = {
     "zipf1.2-20M-R32": dict(tensor="zipf1.2-20M", R=32),
     "precision-100M-4mode": dict(tensor="zipf1.1-100M-4mode", R=32),
@@ -165,7 +170,8 @@ def cpu_baseline(t, R, F, budget_s=20.0):
 
 def bench_batch(args, R=16, count=256):
     """Many small uneven tensors: all tensors' MTTKRP along each mode in one
-    batched launch pair vs one launch pair per tensor (the plain method)."""
+    batched launch pair vs one launch pair per tensor (the plain method).
+    Returns the result line as a dict."""
     import torch
 
     import workloads
@@ -314,8 +320,9 @@ def bench_batch(args, R=16, count=256):
         "build_s": round(build_s, 2),
     }
     b.free()
-    print(json.dumps(res))
-    return 0
+    for h in hs:
+        h.free()
+    return res
 
 
 def bench_precision(args):
@@ -482,19 +489,14 @@ def _serve_tensor(spec):
     return t.idx, t.val, t.dims, t.nnz
 
 
-def bench_serve(args, rhos=(0.5, 0.8, 0.95, 2.0)):
-    """Poisson CP-ALS jobs (3-5 modes, dims log-U[1e2,1e5], nnz log-U[1e4,1e7],
-    Zipf(1.2), R in {16,32,64}, fit change < 1e-4 or 50 sweeps) served with
-    continuous batching, against the plain method (one job at a time, FIFO),
-    at offered loads of rho x the plain method's measured capacity.  The
-    first jobs of the stream are warm-up: they run but are not counted."""
+def serve_jobs(args):
+    """The serving workload's jobs, generated in forked worker processes; call
+    before this process touches the GPU."""
     import concurrent.futures
     import multiprocessing
 
-    import torch
-
     import workloads
-    from paper_2503_18198_amd.serve import CpdServer, GpuExecutor, ServeJob
+    from paper_2503_18198_amd.serve import ServeJob
 
     n_warm, n_timed = args.serve_warmup_jobs, args.serve_jobs
     n_jobs = n_warm + n_timed
@@ -514,6 +516,24 @@ def bench_serve(args, rhos=(0.5, 0.8, 0.95, 2.0)):
     nnzs = np.array([j.nnz for j in base])
     print(f"[bench] generated {n_jobs} jobs, {nnzs.sum() / 1e6:.0f}M nonzeros, in {time.perf_counter() - t0:.1f}s "
           f"on {workers} processes", file=sys.stderr, flush=True)
+    return base
+
+
+def bench_serve(args, base, rhos=(0.5, 0.8, 0.95, 2.0), slot_list=None):
+    """Poisson CP-ALS jobs (3-5 modes, dims log-U[1e2,1e5], nnz log-U[1e4,1e7],
+    Zipf(1.2), R in {16,32,64}, fit change < 1e-4 or 50 sweeps) served with
+    continuous batching, against the plain method (one job at a time, FIFO),
+    at offered loads of rho x the plain method's measured capacity.  The
+    first jobs of the stream are warm-up: they run but are not counted.
+    Returns the result line as a dict."""
+    import torch
+
+    from paper_2503_18198_amd.serve import CpdServer, GpuExecutor, ServeJob
+
+    n_warm, n_timed = args.serve_warmup_jobs, args.serve_jobs
+    n_jobs = n_warm + n_timed
+    slot_list = list(slot_list or args.serve_slots)
+    nnzs = np.array([j.nnz for j in base])
     torch.cuda.set_device(0)
 
     def clone(js, scale):
@@ -562,13 +582,13 @@ def bench_serve(args, rhos=(0.5, 0.8, 0.95, 2.0)):
         loads[str(rho)] = {"plain_fifo": plain}
         print(f"[bench] rho {rho}: plain {plain['jobs_per_s']:.2f} jobs/s p50 {plain['p50_latency_s']:.3f}s "
               f"p99 {plain['p99_latency_s']:.3f}s", file=sys.stderr, flush=True)
-        for slots in args.serve_slots:
+        for slots in slot_list:
             served = serve(clone(base, scale), True, slots, args.serve_build_threads)
             loads[str(rho)][f"continuous_batching_{slots}_slots"] = served
             print(f"[bench] rho {rho}: {slots} slots {served['jobs_per_s']:.2f} jobs/s "
                   f"p50 {served['p50_latency_s']:.3f}s p99 {served['p99_latency_s']:.3f}s",
                   file=sys.stderr, flush=True)
-    top = loads[str(max(rhos))][f"continuous_batching_{args.serve_slots[0]}_slots"]
+    top = loads[str(max(rhos))][f"continuous_batching_{slot_list[0]}_slots"]
     res = {
         "metric": "served CP-ALS jobs/s with p50/p99 latency (continuous batching vs one job at a time)",
         "value": top["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "steps": top["steps"],
@@ -578,14 +598,13 @@ def bench_serve(args, rhos=(0.5, 0.8, 0.95, 2.0)):
                                f"dims log-U[1e2,1e5], nnz log-U[1e4,1e7] ({nnzs.sum() / 1e6:.0f}M in all), "
                                f"Zipf(1.2), R in {{16,32,64}}, stop at |dfit|<1e-4 or 50 sweeps, offered load "
                                f"rho x plain capacity for rho in {list(rhos)}, HBM budget {args.serve_budget_gib:g} GiB, slots "
-                               f"{args.serve_slots}, {args.serve_build_threads} layout-build threads; value = "
-                               f"served jobs/s at the highest load with {args.serve_slots[0]} slots; "
+                               f"{slot_list}, {args.serve_build_threads} layout-build threads; value = "
+                               f"served jobs/s at the highest load with {slot_list[0]} slots; "
                                f"ms_per_step = ms per served job"},
         "by_offered_load": loads,
         "plain_capacity_jobs_per_s": round(1.0 / mean_service, 3),
     }
-    print(json.dumps(res))
-    return 0
+    return res
 
 
 def main(argv=None):
@@ -593,7 +612,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf1.2-20M-R32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-side-workloads", action="store_true",
+                    help="default workload only: leave out the batch and serve sub-objects")
     ap.add_argument("--parts-per-cu", type=int, default=0)
     ap.add_argument("--hot-rows", type=int, default=0, help="rows per input factor cached in LDS (-1: as many as fit)")
     ap.add_argument("--als-iters", type=int, default=10)
@@ -624,10 +645,14 @@ def main(argv=None):
     from paper_2503_18198_amd import capi
 
     if args.workload == "serve-poisson":
-        return bench_serve(args)        # sets the device after generating its jobs
+        print(json.dumps(bench_serve(args, serve_jobs(args))))   # jobs generated before the GPU is touched
+        return 0
+    side = args.workload == DEFAULT_WORKLOAD and not args.no_side_workloads
+    jobs = serve_jobs(args) if side else None
     torch.cuda.set_device(0)
     if args.workload == "batch256-R16":
-        return bench_batch(args)
+        print(json.dumps(bench_batch(args)))
+        return 0
     if args.workload == "precision-100M-4mode":
         return bench_precision(args)
     if args.workload == "paper-shapes":
@@ -778,8 +803,24 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(t, R, F)
     h.free()
+    del dF, outs
+    if side:
+        # The second half of the metric: batched requests/s and served p50/p99
+        # latency, on the batching and serving workloads, as sub-objects.
+        result["batch"] = _sub(bench_batch(args), ("metric", "value", "unit", "ms_per_step", "config",
+                                                   "partition_size", "plain_ms_per_step", "batched_speedup_vs_plain",
+                                                   "eager_launch_ms_per_step", "gflops", "hbm_pct_peak",
+                                                   "als_20_sweeps", "build_s"))
+        torch.cuda.empty_cache()
+        sv = bench_serve(args, jobs, rhos=(0.95, 2.0), slot_list=args.serve_slots[:1])
+        result["serve"] = _sub(sv, ("metric", "value", "unit", "config", "plain_capacity_jobs_per_s",
+                                    "by_offered_load"))
     print(json.dumps(result))
     return 0
+
+
+def _sub(d, keys):
+    return {k: d[k] for k in keys if k in d}
 
 
 if __name__ == "__main__":

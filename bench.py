@@ -46,8 +46,8 @@ WORKLOADS = {
 
 # Shapes and nonzero counts of the paper's evaluation tensors (its Table III),
 # for synthetic stand-ins (seeded, Zipf(1.2) per mode).  The 3-mode
-# 2.9M x 2.1M x 25.5M, 143.6M-nonzero one is left out: generating it alone
-# would take several minutes.
+# 2.9M x 2.1M x 25.5M, 143.6M-nonzero one takes a few minutes to generate and
+# is kept apart (--skip-large-shape leaves it out).
 PAPER_SHAPES = {
     "chicago-like": ((6200, 24, 77, 32), 5_300_000),
     "enron-like": ((6100, 5700, 244_300, 1200), 54_200_000),
@@ -55,6 +55,7 @@ PAPER_SHAPES = {
     "uber-like": ((183, 24, 1100, 1700), 3_300_000),
     "vast-like": ((165_400, 11_400, 2, 100, 89), 26_000_000),
 }
+PAPER_SHAPE_LARGE = {"nell1-like": ((2_900_000, 2_100_000, 25_500_000), 143_600_000)}
 
 
 def algorithmic_bytes(dims, nnz, R, factor_bytes=4):
@@ -398,23 +399,16 @@ def bench_precision(args):
     return 0
 
 
-def scheme1_imbalance(idx_col, dim, kappa):
-    """The paper's load balancing scheme 1 (Sec. III-B): rows sorted by
-    nonzero count and dealt cyclically to kappa workgroups, each owning its
-    rows.  Returns the largest workgroup load over the mean load, a lower
-    bound on its slowdown against an even nonzero split."""
-    deg = np.bincount(idx_col.astype(np.int64), minlength=dim)
-    order = np.sort(deg)[::-1]
-    loads = np.zeros(kappa, dtype=np.int64)
-    np.add.at(loads, np.arange(order.shape[0]) % kappa, order)
-    return float(loads.max() / (deg.sum() / kappa))
-
-
 def bench_paper_shapes(args, R=32):
-    """Synthetic tensors with the shapes and nonzero counts of the paper's
-    evaluation set: all-mode MTTKRP with this build's nonzero split and carry
-    fix-up, against the paper's scheme 2 (global atomics for cut rows) on the
-    same kernel, and scheme 1's load imbalance from each mode's degrees."""
+    """The paper's load-balancing ablation (Sec. V-B, Fig. 4) on synthetic
+    tensors with the shapes and nonzero counts of its evaluation set (Table
+    III), at kappa = one partition per compute unit.  Per mode, three
+    partitioners on the same kernel: this build's nonzero split with the
+    deterministic carry fix-up; scheme 2 (equal nonzero chunks, global
+    atomics for rows cut by chunk boundaries); scheme 1 (whole rows dealt to
+    kappa partitions by LPT).  All-mode totals for scheme 1 only, scheme 2
+    only, the paper's adaptive choice (scheme 1 where I_n >= kappa, else
+    scheme 2) and this build.  Returns the result line as a dict."""
     import torch
 
     import workloads
@@ -422,8 +416,11 @@ def bench_paper_shapes(args, R=32):
 
     stream = torch.cuda.current_stream()
     K, W = args.steps, args.warmup
+    shapes = dict(PAPER_SHAPES)
+    if not args.skip_large_shape:
+        shapes.update(PAPER_SHAPE_LARGE)
     rows = {}
-    for name, (dims, nnz) in PAPER_SHAPES.items():
+    for name, (dims, nnz) in shapes.items():
         t0 = time.perf_counter()
         t = workloads.random_tensor(dims, nnz, dist="zipf", s=1.2, seed=7,
                                     progress=lambda m: print(f"[bench] {name}: {m}", file=sys.stderr, flush=True))
@@ -431,57 +428,75 @@ def bench_paper_shapes(args, R=32):
         N = len(t.dims)
         h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R), stream=stream)
         kappa = capi.mttkrp_layout_info(h)["cu_count"]
+        t1 = time.perf_counter()
+        h1 = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, partitioner=capi.MTTKRP_PART_ROWS_LPT,
+                                                                      lpt_parts=kappa), stream=stream)
+        lpt_build_s = time.perf_counter() - t1
         dF = [torch.from_numpy(f).cuda() for f in workloads.random_factors(t.dims, R, seed=7)]
-        outs = [torch.empty((d, R), device="cuda") for d in t.dims]
-        outs2 = [torch.empty((d, R), device="cuda") for d in t.dims]
+        del t
+        out = {k: [torch.empty((d, R), device="cuda") for d in dims] for k in ("nnz", "s2", "s1")}
 
-        def timed(run, o):
-            for _ in range(W):
+        def per_mode(run, hh, o):
+            ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(N)]
+            tot = [0.0] * N
+            for rep in range(W + K):
                 for n in range(N):
-                    run(h, n, dF, o[n], R, stream=stream)
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            z = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(K):
-                for n in range(N):
-                    run(h, n, dF, o[n], R, stream=stream)
-            z.record(stream)
-            torch.cuda.synchronize()
-            return a.elapsed_time(z) / K
+                    ev[n][0].record(stream)
+                    run(hh, n, dF, o[n], R, stream=stream)
+                    ev[n][1].record(stream)
+                torch.cuda.synchronize()
+                if rep >= W:
+                    for n in range(N):
+                        tot[n] += ev[n][0].elapsed_time(ev[n][1])
+            return [x / K for x in tot]
 
-        ms = timed(capi.mttkrp_run, outs)
-        ms2 = timed(capi.mttkrp_run_scheme2, outs2)
-        diff = max(float(torch.linalg.norm(outs[n] - outs2[n]) / max(float(torch.linalg.norm(outs[n])), 1e-30))
-                   for n in range(N))
-        byts = sum(algorithmic_bytes(t.dims, t.nnz, R))
-        flops = N * R * t.nnz * N
+        ms = {"this_build": per_mode(capi.mttkrp_run, h, out["nnz"]),
+              "scheme2_atomics": per_mode(capi.mttkrp_run_scheme2, h, out["s2"]),
+              "scheme1_lpt": per_mode(capi.mttkrp_run, h1, out["s1"])}
+        adaptive = [ms["scheme1_lpt"][n] if dims[n] >= kappa else ms["scheme2_atomics"][n] for n in range(N)]
+
+        def rel(a, b):
+            return max(float(torch.linalg.norm(a[n] - b[n]) / max(float(torch.linalg.norm(b[n])), 1e-30))
+                       for n in range(N))
+
+        byts = sum(algorithmic_bytes(dims, nnz, R))
+        flops = N * R * nnz * N
+        tot = {k: sum(v) for k, v in ms.items()}
+        tot["adaptive_paper"] = sum(adaptive)
         rows[name] = {
-            "dims": list(t.dims), "nnz": t.nnz, "gen_s": round(gen_s, 1),
-            "ms_all_modes": round(ms, 4), "gflops": round(flops / (ms / 1e3) / 1e9, 1),
-            "hbm_frac": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "scheme2_atomics_ms_all_modes": round(ms2, 4),
-            "scheme2_rel_diff": diff,
-            "scheme1_imbalance_per_mode": [round(scheme1_imbalance(t.idx[:, n], t.dims[n], kappa), 2)
-                                           for n in range(N)],
+            "dims": list(dims), "nnz": int(nnz), "gen_s": round(gen_s, 1), "lpt_build_s": round(lpt_build_s, 2),
+            "ms_per_mode": {k: [round(x, 4) for x in v] for k, v in ms.items()},
+            "adaptive_choice": ["scheme1" if dims[n] >= kappa else "scheme2" for n in range(N)],
+            "ms_all_modes": {k: round(v, 4) for k, v in tot.items()},
+            "speedup_vs_adaptive": {k: round(tot["adaptive_paper"] / v, 3) for k, v in tot.items()},
+            "gflops_this_build": round(flops / (tot["this_build"] / 1e3) / 1e9, 1),
+            "hbm_frac_this_build": round(byts / (tot["this_build"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "max_rel_diff_vs_this_build": {"scheme2_atomics": rel(out["s2"], out["nnz"]),
+                                           "scheme1_lpt": rel(out["s1"], out["nnz"])},
         }
         print(f"[bench] {name}: {json.dumps(rows[name])}", file=sys.stderr, flush=True)
         h.free()
-        del t
-    gm = float(np.exp(np.mean([np.log(r["scheme2_atomics_ms_all_modes"] / r["ms_all_modes"]) for r in rows.values()])))
+        h1.free()
+        del dF, out
+        torch.cuda.empty_cache()
+
+    def gm(key):
+        return round(float(np.exp(np.mean([np.log(r["ms_all_modes"]["adaptive_paper"] / r["ms_all_modes"][key])
+                                           for r in rows.values()]))), 3)
+
     res = {
         "metric": "all-mode spMTTKRP GFLOP/s on tensors shaped like the paper's evaluation set",
-        "value": round(float(np.exp(np.mean([np.log(r["gflops"]) for r in rows.values()]))), 1),
+        "value": round(float(np.exp(np.mean([np.log(r["gflops_this_build"]) for r in rows.values()]))), 1),
         "unit": "GFLOP/s (geometric mean)", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": round(sum(r["ms_all_modes"] for r in rows.values()), 4),
+        "ms_per_step": round(sum(r["ms_all_modes"]["this_build"] for r in rows.values()), 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "paper-shapes: Zipf(1.2) stand-ins with the shapes and nnz of the paper's Table III "
-                               "tensors (all but the 143.6M-nonzero one), R=32, fp32"},
+                               f"tensors, R={R}, fp32, kappa = {kappa} partitions for scheme 1"},
         "tensors": rows,
-        "scheme2_over_this_build_geomean": round(gm, 3),
+        "speedup_vs_adaptive_geomean": {k: gm(k) for k in ("this_build", "scheme2_atomics", "scheme1_lpt",
+                                                           "adaptive_paper")},
     }
-    print(json.dumps(res))
-    return 0
+    return res
 
 
 def _serve_tensor(spec):
@@ -621,6 +636,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true", help="accepted for compatibility; parity lives in tests/")
     ap.add_argument("--no-gather-ceiling", action="store_true")
+    ap.add_argument("--skip-large-shape", action="store_true",
+                    help="paper-shapes: leave out the 143.6M-nonzero tensor")
     ap.add_argument("--serve-slots", type=int, nargs="+", default=[8, 4],
                     help="concurrent job slots of the continuous-batching server (serve-poisson)")
     ap.add_argument("--serve-jobs", type=int, default=200, help="timed jobs of serve-poisson")
@@ -656,7 +673,8 @@ def main(argv=None):
     if args.workload == "precision-100M-4mode":
         return bench_precision(args)
     if args.workload == "paper-shapes":
-        return bench_paper_shapes(args)
+        print(json.dumps(bench_paper_shapes(args)))
+        return 0
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * 2 ** 20 // 4
         a = torch.rand(n, device="cuda")

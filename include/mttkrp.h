@@ -75,7 +75,17 @@ typedef struct {
                                   packed coordinate key of all N indices fits 128 bits, 1 <= nnz < 2^31 and
                                   hot_rows is 0 (the copies are identical either way; the device build
                                   holds a transient scratch of about nnz * (4N + 48) bytes) */
+    int partitioner;           /* how each mode copy is split into workgroup partitions (Sec. III-B):
+                                  MTTKRP_PART_NNZ (default): equal nonzero ranges, rows cut by a range
+                                  boundary combined by a deterministic fix-up (scheme 2 without atomics);
+                                  MTTKRP_PART_ROWS_LPT: scheme 1, whole output rows dealt to lpt_parts
+                                  partitions, longest first to the least-loaded partition (built on the
+                                  host; no hot rows; not usable in batches or the gather probe) */
+    int lpt_parts;             /* partitions (the paper's kappa) of MTTKRP_PART_ROWS_LPT; 0 = one per
+                                  compute unit */
 } mttkrp_opts;
+
+enum { MTTKRP_PART_NNZ = 0, MTTKRP_PART_ROWS_LPT = 1 };
 
 /* Fill `o` with the defaults listed above. */
 void mttkrp_opts_default(mttkrp_opts* o);
@@ -218,6 +228,7 @@ typedef struct {
     uint32_t hot_rows;            /* rows per input factor the MTTKRP kernel keeps in LDS */
     uint32_t wg_threads;          /* threads per MTTKRP workgroup */
     uint32_t parts_per_cu;        /* MTTKRP workgroups launched per compute unit */
+    uint32_t lpt_parts;           /* scheme-1 partitions (MTTKRP_PART_ROWS_LPT), 0 for the nonzero split */
 } mttkrp_info;
 
 mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
@@ -336,6 +347,18 @@ void mttkrp_layout_free(mttkrp_handle h);
 /* Message of the last failed call on this thread ("" if none). */
 const char* mttkrp_last_error(void);
 
+/* The scheme-1 partitioner alone (host only): rows of the given nonzero
+ * counts dealt to kappa partitions by longest processing time first (Sec.
+ * III-B, scheme 1; Graham's rule, whose makespan is at most (4/3 - 1/(3
+ * kappa)) times the optimum, the bound the paper quotes): rows by decreasing
+ * count, ties to the lower row, each to the least-loaded partition, ties to
+ * the lower partition.
+ *   loads:     host, nrows counts
+ *   part:      host out, nrows partition indices
+ *   part_load: host out (may be NULL), kappa sums */
+mttkrp_status mttkrp_lpt_partition(const uint64_t* loads, uint64_t nrows, uint32_t kappa, uint32_t* part,
+                                   uint64_t* part_load);
+
 /* Host view of one mode copy of a host-only handle (for inspection and tests).
  * All pointers stay valid until mttkrp_layout_free. */
 typedef struct {
@@ -351,9 +374,15 @@ typedef struct {
     const uint32_t* winfo;        /* 2 words per 32 nonzeros: row-start bits, row ordinal of the first */
     const uint32_t* row_id;       /* output row of each nonempty row, increasing (nrows_nz) */
     const uint32_t* empty_rows;   /* rows without nonzeros, increasing (nempty) */
-    const uint64_t* src_pos;      /* position in the caller's COO input of nonzero k */
+    const uint64_t* src_pos;      /* position in the caller's COO input of nonzero k (nnz entries; for
+                                     scheme-1 copies nnz_pad entries, all ones at gap entries) */
     uint64_t nhot;                /* rows per input mode served from LDS */
     const uint32_t* hot_rows[MTTKRP_MAX_MODES - 1]; /* hot_rows[j][s]: row of mode in_modes[j] in slot s */
+    uint64_t nparts;              /* scheme-1 partitions (0 for the nonzero split) */
+    const uint64_t* part_range;   /* 2 * nparts: first position and nonzeros of each partition; the rows of
+                                     partition p, in increasing order, fill [first, first + nonzeros) and
+                                     every first is a multiple of 32 (entries between partitions are
+                                     zero and belong to none) */
 } mttkrp_mode_view;
 
 mttkrp_status mttkrp_layout_view(mttkrp_handle h, int mode, mttkrp_mode_view* v);

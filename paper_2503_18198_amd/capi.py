@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("MTTKRP_HIP_LIB") or os.path.join(_HERE, "libmttkrp_hi
 
 MTTKRP_OK, MTTKRP_EINVAL, MTTKRP_ERANGE, MTTKRP_ENOMEM, MTTKRP_EUNSUPPORTED, MTTKRP_ENOTSPD, MTTKRP_EHIP = range(7)
 MTTKRP_FP32, MTTKRP_BF16 = 0, 1
+MTTKRP_PART_NNZ, MTTKRP_PART_ROWS_LPT = 0, 1
 MTTKRP_MAX_MODES = 8
 STATUS_NAMES = {0: "MTTKRP_OK", 1: "MTTKRP_EINVAL", 2: "MTTKRP_ERANGE", 3: "MTTKRP_ENOMEM",
                 4: "MTTKRP_EUNSUPPORTED", 5: "MTTKRP_ENOTSPD", 6: "MTTKRP_EHIP"}
@@ -31,7 +32,7 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
             "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
             "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes", "mttkrp_batch_create_in",
-            "mttkrp_run_noalloc", "mttkrp_noalloc_scratch_bytes"]
+            "mttkrp_run_noalloc", "mttkrp_noalloc_scratch_bytes", "mttkrp_lpt_partition"]
 
 
 class MttkrpError(RuntimeError):
@@ -43,7 +44,7 @@ class MttkrpError(RuntimeError):
 class mttkrp_opts(ctypes.Structure):
     _fields_ = [("parts_per_cu", ctypes.c_int), ("factor_dtype", ctypes.c_int), ("max_R", ctypes.c_int),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int), ("hot_rows", ctypes.c_int),
-                ("build_on_host", ctypes.c_int)]
+                ("build_on_host", ctypes.c_int), ("partitioner", ctypes.c_int), ("lpt_parts", ctypes.c_int)]
 
 
 class mttkrp_mode_view(ctypes.Structure):
@@ -54,12 +55,13 @@ class mttkrp_mode_view(ctypes.Structure):
                 ("val", ctypes.POINTER(ctypes.c_float)), ("winfo", ctypes.POINTER(ctypes.c_uint32)),
                 ("row_id", ctypes.POINTER(ctypes.c_uint32)), ("empty_rows", ctypes.POINTER(ctypes.c_uint32)),
                 ("src_pos", ctypes.POINTER(ctypes.c_uint64)), ("nhot", ctypes.c_uint64),
-                ("hot_rows", ctypes.POINTER(ctypes.c_uint32) * (MTTKRP_MAX_MODES - 1))]
+                ("hot_rows", ctypes.POINTER(ctypes.c_uint32) * (MTTKRP_MAX_MODES - 1)),
+                ("nparts", ctypes.c_uint64), ("part_range", ctypes.POINTER(ctypes.c_uint64))]
 
 
 class mttkrp_info(ctypes.Structure):
     _fields_ = [("cu_count", ctypes.c_uint32), ("lds_per_workgroup", ctypes.c_uint32), ("hot_rows", ctypes.c_uint32),
-                ("wg_threads", ctypes.c_uint32), ("parts_per_cu", ctypes.c_uint32)]
+                ("wg_threads", ctypes.c_uint32), ("parts_per_cu", ctypes.c_uint32), ("lpt_parts", ctypes.c_uint32)]
 
 
 class mttkrp_plan(ctypes.Structure):
@@ -86,6 +88,8 @@ def _load():
     lib.mttkrp_run_bf16.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
     lib.mttkrp_run_scheme2.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
     lib.mttkrp_run_noalloc.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), vp, ctypes.c_int, vp]
+    lib.mttkrp_lpt_partition.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64, ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]
     lib.mttkrp_noalloc_scratch_bytes.argtypes = []
     lib.mttkrp_noalloc_scratch_bytes.restype = ctypes.c_uint64
     lib.cpd_als_init.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
@@ -123,7 +127,7 @@ def _load():
                  "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
                  "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
                  "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes",
-                 "mttkrp_batch_create_in", "mttkrp_run_noalloc"):
+                 "mttkrp_batch_create_in", "mttkrp_run_noalloc", "mttkrp_lpt_partition"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -397,6 +401,18 @@ def cpd_als_status(h: Layout, stream=None):
     _check(_lib.cpd_als_status(ctypes.c_void_p(h.ptr), ctypes.c_void_p(_stream(stream))))
 
 
+def mttkrp_lpt_partition(loads, kappa: int):
+    """Scheme 1's partitioner (host): returns (partition of each row, load of
+    each partition)."""
+    ld = np.ascontiguousarray(np.asarray(loads, dtype=np.uint64))
+    part = np.zeros(ld.shape[0], dtype=np.uint32)
+    pl = np.zeros(int(kappa), dtype=np.uint64)
+    _check(_lib.mttkrp_lpt_partition(ld.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), ld.shape[0], int(kappa),
+                                     part.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                     pl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return part, pl
+
+
 def mttkrp_layout_view(h: Layout, mode: int) -> dict:
     """Copies of the host arrays of one mode copy (host-only layouts)."""
     v = mttkrp_mode_view()
@@ -412,8 +428,9 @@ def mttkrp_layout_view(h: Layout, mode: int) -> dict:
                 idx=[arr(v.idx[j], v.nnz_pad, np.uint32) for j in range(v.n_in)],
                 val=arr(v.val, v.nnz_pad, np.float32), winfo=arr(v.winfo, 2 * (v.nnz_pad // 32), np.uint32),
                 row_id=arr(v.row_id, v.nrows_nz, np.uint32), empty_rows=arr(v.empty_rows, v.nempty, np.uint32),
-                src_pos=arr(v.src_pos, v.nnz, np.uint64), nhot=int(v.nhot),
-                hot_rows=[arr(v.hot_rows[j], v.nhot, np.uint32) for j in range(v.n_in)])
+                src_pos=arr(v.src_pos, v.nnz_pad if v.nparts else v.nnz, np.uint64), nhot=int(v.nhot),
+                hot_rows=[arr(v.hot_rows[j], v.nhot, np.uint32) for j in range(v.n_in)],
+                part_range=arr(v.part_range, 2 * v.nparts, np.uint64).reshape(-1, 2))
 
 
 class Batch:

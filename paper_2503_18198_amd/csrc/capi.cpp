@@ -146,6 +146,8 @@ void mttkrp_opts_default(mttkrp_opts* o)
     o->host_only = 0;
     o->hot_rows = 0;
     o->build_on_host = 0;
+    o->partitioner = MTTKRP_PART_NNZ;
+    o->lpt_parts = 0;
 }
 
 const char* mttkrp_last_error(void) { return g_err.c_str(); }
@@ -159,7 +161,27 @@ static mttkrp_status check_opts(const mttkrp_opts* in, mttkrp_opts* o)
     if (!r_supported(o->max_R)) return fail(MTTKRP_EUNSUPPORTED, "max_R must be 16, 32 or 64");
     if (o->factor_dtype != MTTKRP_FP32 && o->factor_dtype != MTTKRP_BF16)
         return fail(MTTKRP_EINVAL, "factor_dtype must be MTTKRP_FP32 or MTTKRP_BF16");
+    if (o->partitioner != MTTKRP_PART_NNZ && o->partitioner != MTTKRP_PART_ROWS_LPT)
+        return fail(MTTKRP_EINVAL, "partitioner must be MTTKRP_PART_NNZ or MTTKRP_PART_ROWS_LPT");
+    if (o->lpt_parts < 0 || o->lpt_parts > (1 << 20)) return fail(MTTKRP_EINVAL, "lpt_parts must be in [0, 2^20]");
+    if (o->partitioner == MTTKRP_PART_ROWS_LPT) o->hot_rows = 0;   // scheme-1 copies keep plain coordinates
     return MTTKRP_OK;
+}
+
+// Scheme-1 partitions of a build (the caller's count, else one per compute unit).
+static uint32_t lpt_kappa(const mttkrp_opts& o, int cu_count)
+{
+    return o.lpt_parts > 0 ? (uint32_t)o.lpt_parts : (uint32_t)(cu_count > 0 ? cu_count : 256);
+}
+
+// Extra device bytes of scheme-1 copies (gaps between partitions and the
+// partition tables of the N copies); 0 for the nonzero split.  Before the
+// device is known, a compute-unit count of 1024 bounds the default kappa.
+static uint64_t lpt_bytes(const mttkrp_opts& o, int N, int cu_count)
+{
+    if (o.partitioner != MTTKRP_PART_ROWS_LPT) return 0;
+    const uint32_t kappa = lpt_kappa(o, cu_count > 0 ? cu_count : 1024);
+    return (uint64_t)N * (mk::lpt_extra_bytes(N, kappa) + 4 * kAlign);
 }
 
 mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts* opts, uint64_t* bytes)
@@ -173,7 +195,7 @@ mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const 
     mttkrp_status s = check_opts(opts, &o);
     if (s) return s;
     *bytes = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
-             hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows));
+             hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows)) + lpt_bytes(o, N, 0);
     return MTTKRP_OK;
 }
 
@@ -201,7 +223,7 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     // largest LDS, an upper bound).
     {
         const uint64_t bound = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
-                               hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows));
+                               hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows)) + lpt_bytes(o, N, 0);
         if (!o.host_only && o.hbm_budget_bytes && bound > o.hbm_budget_bytes)
             return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(bound) + " B exceeds the budget of " +
                                            std::to_string(o.hbm_budget_bytes) + " B");
@@ -216,8 +238,16 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
             lds_limit = (uint32_t)v;
     }
     const uint32_t nhot = hot_rows_for(N, o.max_R, lds_limit, o.hot_rows);
+    int cus_here = 256;
+    if (!o.host_only) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev_id) == hipSuccess && v > 0)
+            cus_here = v;
+    }
+    const bool lpt = o.partitioner == MTTKRP_PART_ROWS_LPT;
+    const uint32_t kappa = lpt_kappa(o, cus_here);
     const uint64_t need = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
-                          hot_bytes(N, nhot);
+                          hot_bytes(N, nhot) + lpt_bytes(o, N, cus_here);
 
     auto* h = new mttkrp_layout();
     h->N = N;
@@ -234,8 +264,10 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     mk::BuildScratch scratch;
     if (h->host_only) {
         h->host.resize(N);
-        for (int n = 0; n < N; ++n)
+        for (int n = 0; n < N; ++n) {
             mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, true, threads, &hot, h->host[n], &scratch);
+            if (lpt) mk::lpt_regroup(h->host[n], kappa);
+        }
         for (auto& hs : hot) hs.rows.resize(nhot, 0u);
         h->hot = std::move(hot);
         *out = h;
@@ -313,7 +345,7 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
 
     double normX2 = 0.0;
     // With the caller's memory the device build runs only in the caller's scratch.
-    const bool dev_build = !o.build_on_host && nhot == 0 && mk::device_build_applies(dims, N, nnz) &&
+    const bool dev_build = !o.build_on_host && !lpt && nhot == 0 && mk::device_build_applies(dims, N, nnz) &&
                            (!ext_mem || (ext_scratch && ext_scratch_bytes >= mk::device_build_scratch_bytes(dims, N, nnz)));
     if (e == hipSuccess && dev_build) {
         // Mode copies sorted and laid out on the device.
@@ -340,6 +372,25 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
         mk::HostMode hm;
         for (int n = 0; n < N && e == hipSuccess; ++n) {
             mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, false, threads, &hot, hm, &scratch);
+            if (n == 0) {
+                // |X|^2 with duplicate coordinates merged: duplicates are adjacent in
+                // the sorted copy (no row start between them, same other indices).
+                uint64_t k = 0;
+                while (k < nnz) {
+                    double v = hm.val[k];
+                    uint64_t j = k + 1;
+                    while (j < nnz && !((hm.winfo[2 * (j / 32)] >> (j % 32)) & 1u)) {
+                        bool same = true;
+                        for (int t = 0; t < N - 1 && same; ++t) same = hm.idx[t][j] == hm.idx[t][k];
+                        if (!same) break;
+                        v += hm.val[j];
+                        ++j;
+                    }
+                    normX2 += v * v;
+                    k = j;
+                }
+            }
+            if (lpt) mk::lpt_regroup(hm, kappa);
             mk::DevMode& d = h->dev[n];
             d.nnz = hm.nnz;
             d.nnz_pad = hm.nnz_pad;
@@ -360,29 +411,19 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
             d.winfo = static_cast<const uint2*>(up(hm.winfo.data(), hm.winfo.size() * 4));
             d.row_id = static_cast<const uint32_t*>(up(hm.row_id.data(), hm.row_id.size() * 4));
             d.empty_rows = static_cast<const uint32_t*>(up(hm.empty_rows.data(), hm.empty_rows.size() * 4));
-            if (n == 0) {
-                // |X|^2 with duplicate coordinates merged: duplicates are adjacent in
-                // the sorted copy (no row start between them, same other indices).
-                uint64_t k = 0;
-                while (k < nnz) {
-                    double v = hm.val[k];
-                    uint64_t j = k + 1;
-                    while (j < nnz && !((hm.winfo[2 * (j / 32)] >> (j % 32)) & 1u)) {
-                        bool same = true;
-                        for (int t = 0; t < N - 1 && same; ++t) same = hm.idx[t][j] == hm.idx[t][k];
-                        if (!same) break;
-                        v += hm.val[j];
-                        ++j;
-                    }
-                    normX2 += v * v;
-                    k = j;
-                }
+            if (lpt) {
+                d.prange = static_cast<const uint64_t*>(up(hm.part_range.data(), hm.part_range.size() * 8));
+                d.nprange = kappa;
             }
             // The next mode overwrites the host arrays; wait for the copies that read them.
             if (e == hipSuccess) e = hipStreamSynchronize(stream);
         }
     }
     h->normX2 = normX2;
+    if (e == hipSuccess && off > need) {
+        drop();
+        return fail(MTTKRP_EHIP, "internal: mode copies exceed the planned device footprint");
+    }
     if (e != hipSuccess) {
         mttkrp_status st = hip_fail(e, "uploading the mode copies");
         drop();
@@ -440,6 +481,20 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info)
     info->hot_rows = h->nhot;
     info->wg_threads = (uint32_t)mk::partition_wg_threads(h->N - 1);
     info->parts_per_cu = (uint32_t)h->opts.parts_per_cu;
+    info->lpt_parts = h->opts.partitioner == MTTKRP_PART_ROWS_LPT ? lpt_kappa(h->opts, h->cu_count) : 0u;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_lpt_partition(const uint64_t* loads, uint64_t nrows, uint32_t kappa, uint32_t* part,
+                                   uint64_t* part_load)
+{
+    g_err.clear();
+    if (kappa == 0) return fail(MTTKRP_EINVAL, "kappa must be at least 1");
+    if (nrows && (!loads || !part)) return fail(MTTKRP_EINVAL, "NULL loads or part");
+    std::vector<uint64_t> pl;
+    const std::vector<uint32_t> p = mk::lpt_assign(loads, nrows, kappa, &pl);
+    std::copy(p.begin(), p.end(), part);
+    if (part_load) std::copy(pl.begin(), pl.end(), part_load);
     return MTTKRP_OK;
 }
 
@@ -501,6 +556,8 @@ mttkrp_status mttkrp_layout_view(mttkrp_handle h, int mode, mttkrp_mode_view* v)
     v->src_pos = m.src_pos.data();
     v->nhot = h->nhot;
     for (int j = 0; j < v->n_in; ++j) v->hot_rows[j] = h->hot[m.in_modes[j]].rows.data();
+    v->nparts = m.part_range.size() / 2;
+    v->part_range = m.part_range.empty() ? nullptr : m.part_range.data();
     return MTTKRP_OK;
 }
 
@@ -622,6 +679,8 @@ mttkrp_status mttkrp_gather_probe(mttkrp_handle h, int mode, const void* const* 
         return fail(MTTKRP_EINVAL, "factor_dtype must be MTTKRP_FP32 or MTTKRP_BF16");
     if (what != 0 && what != 1) return fail(MTTKRP_EINVAL, "what must be 0 (stream) or 1 (stream and gathers)");
     if (!h) return fail(MTTKRP_EINVAL, "NULL handle");
+    if (h->opts.partitioner == MTTKRP_PART_ROWS_LPT)
+        return fail(MTTKRP_EUNSUPPORTED, "the gather probe runs the nonzero-balanced partitions only");
     // The probe has no output: the handle's own carry workspace stands in for
     // it in the common argument checks.
     mttkrp_status s = check_run(h, mode, factors, h->carry, R);
@@ -838,6 +897,9 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
         if (!h || h->host_only) return fail(MTTKRP_EINVAL, "layout " + std::to_string(t) + " is NULL or host-only");
         if (h->N != N) return fail(MTTKRP_EINVAL, "all layouts of a batch need the same N");
         if (R > h->opts.max_R) return fail(MTTKRP_EINVAL, "R exceeds the max_R of layout " + std::to_string(t));
+        if (h->opts.partitioner == MTTKRP_PART_ROWS_LPT)
+            return fail(MTTKRP_EUNSUPPORTED, "layout " + std::to_string(t) +
+                                                 " uses scheme-1 partitions, which batches do not support");
         if (h->nhot)
             return fail(MTTKRP_EUNSUPPORTED, "layout " + std::to_string(t) +
                                                  " keeps hot rows in LDS; batches take layouts built with hot_rows = 0");

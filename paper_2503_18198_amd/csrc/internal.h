@@ -26,6 +26,10 @@ struct DevMode {
     const uint2* winfo = nullptr;      // per 32 nonzeros: {row-start bits, ordinal of the row holding the first}
     const uint32_t* row_id = nullptr;  // ordinal -> output row
     const uint32_t* empty_rows = nullptr;
+    // Scheme 1 (whole rows per partition): {first position, nonzeros} of each
+    // of nprange partitions; null for the nonzero-balanced split.
+    const uint64_t* prange = nullptr;
+    uint32_t nprange = 0;
 };
 
 // Launch geometry of one MTTKRP call.

@@ -6,6 +6,7 @@
 #include <sched.h>
 
 #include <algorithm>
+#include <queue>
 #include <atomic>
 #include <condition_variable>
 #include <deque>
@@ -356,6 +357,7 @@ void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const
     out.src_pos.resize(keep_src_pos ? nnz : 0);
     out.row_id.clear();
     out.empty_rows.clear();
+    out.part_range.clear();
 
     std::vector<int> cyc;
     for (int j = 1; j < N; ++j) cyc.push_back((n + j) % N);
@@ -432,6 +434,102 @@ void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const
         out.winfo[2 * w + 1] = (uint32_t)(before + (bits & 1u) - 1u);
         before += (uint64_t)__builtin_popcount(bits);
     }
+}
+
+std::vector<uint32_t> lpt_assign(const uint64_t* load, uint64_t nrows, uint32_t kappa, std::vector<uint64_t>* part_load)
+{
+    std::vector<uint32_t> order(nrows);
+    for (uint64_t i = 0; i < nrows; ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return load[a] > load[b]; });
+    // Min-heap of (load, partition): the least-loaded partition, lowest index on ties.
+    using Slot = std::pair<uint64_t, uint32_t>;
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (uint32_t p = 0; p < kappa; ++p) heap.push({0, p});
+    std::vector<uint32_t> part(nrows, 0);
+    std::vector<uint64_t> pl(kappa, 0);
+    for (uint32_t r : order) {
+        Slot s = heap.top();
+        heap.pop();
+        part[r] = s.second;
+        s.first += load[r];
+        pl[s.second] = s.first;
+        heap.push(s);
+    }
+    if (part_load) *part_load = std::move(pl);
+    return part;
+}
+
+uint64_t lpt_extra_bytes(int N, uint32_t kappa)
+{
+    // up to 31 gap entries per partition (N-1 indices and a value each), their
+    // row-start words, and the partition table
+    return (uint64_t)kappa * (31ull * 4ull * (uint64_t)N + 8ull) + 16ull * kappa + 256ull;
+}
+
+void lpt_regroup(HostMode& hm, uint32_t kappa)
+{
+    std::vector<uint64_t>& part_range = hm.part_range;
+    const uint64_t nrows = hm.nrows_nz;
+    const int n_in = (int)hm.idx.size();
+    // Row extents in the sorted copy (ordinal order = increasing row).
+    std::vector<uint64_t> beg(nrows + 1, hm.nnz);
+    {
+        uint64_t o = 0;
+        for (uint64_t k = 0; k < hm.nnz; ++k)
+            if ((hm.winfo[2 * (k / 32)] >> (k % 32)) & 1u) beg[o++] = k;
+    }
+    std::vector<uint64_t> len(nrows);
+    for (uint64_t o = 0; o < nrows; ++o) len[o] = beg[o + 1] - beg[o];
+    std::vector<uint64_t> pl;
+    const std::vector<uint32_t> part = lpt_assign(len.data(), nrows, kappa, &pl);
+    // Partition starts, each at a multiple of 32.
+    part_range.assign(2 * (uint64_t)kappa, 0);
+    uint64_t pos = 0;
+    for (uint32_t p = 0; p < kappa; ++p) {
+        part_range[2 * p] = pos;
+        part_range[2 * p + 1] = pl[p];
+        pos = (pos + pl[p] + 31) / 32 * 32;
+    }
+    const uint64_t total = pos < 32 ? 32 : pos;
+    // Rows of each partition in increasing row order.
+    std::vector<std::vector<uint32_t>> rows_of(kappa);
+    for (uint64_t o = 0; o < nrows; ++o) rows_of[part[o]].push_back((uint32_t)o);
+    std::vector<buf<uint32_t>> idx(n_in);
+    for (auto& v : idx) v.assign(total, 0u);
+    buf<float> val;
+    val.assign(total, 0.0f);
+    const bool keep_src = !hm.src_pos.empty();
+    buf<uint64_t> src;
+    if (keep_src) src.assign(total, ~0ull);
+    std::vector<uint32_t> row_id;
+    row_id.reserve(nrows);
+    std::vector<uint32_t> winfo(2 * (total / 32), 0u);
+    for (uint32_t p = 0; p < kappa; ++p) {
+        uint64_t w = part_range[2 * p];
+        for (uint32_t o : rows_of[p]) {
+            winfo[2 * (w / 32)] |= 1u << (w % 32);
+            row_id.push_back(hm.row_id[o]);
+            for (int j = 0; j < n_in; ++j)
+                std::copy(hm.idx[j].begin() + beg[o], hm.idx[j].begin() + beg[o + 1], idx[j].begin() + w);
+            std::copy(hm.val.begin() + beg[o], hm.val.begin() + beg[o + 1], val.begin() + w);
+            if (keep_src) std::copy(hm.src_pos.begin() + beg[o], hm.src_pos.begin() + beg[o + 1], src.begin() + w);
+            w += len[o];
+        }
+    }
+    // Ordinal of the row holding each word's first entry (gap entries count
+    // with the row before them; no partition covers them).
+    uint64_t before = 0;
+    for (uint64_t wd = 0; wd < total / 32; ++wd) {
+        const uint32_t bits = winfo[2 * wd];
+        winfo[2 * wd + 1] = (uint32_t)(before + (bits & 1u) - 1u);
+        before += (uint64_t)__builtin_popcount(bits);
+    }
+    for (int j = 0; j < n_in; ++j) hm.idx[j] = std::move(idx[j]);
+    hm.val = std::move(val);
+    hm.winfo = std::move(winfo);
+    hm.row_id = std::move(row_id);
+    hm.nnz_pad = total;
+    hm.src_pos = std::move(src);   // per position (gap entries: all ones)
 }
 
 }  // namespace mk

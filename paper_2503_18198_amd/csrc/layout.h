@@ -52,6 +52,7 @@ struct HostMode {
     std::vector<uint32_t> row_id;              // [nrows_nz]
     std::vector<uint32_t> empty_rows;          // [nempty]
     buf<uint64_t> src_pos;                     // [nnz] (kept only on request)
+    std::vector<uint64_t> part_range;          // scheme 1 only: {first position, nonzeros} per partition
 };
 
 // Sort buffers of a build, kept across its modes so their pages are mapped once.
@@ -85,6 +86,25 @@ std::string validate_coo(const uint32_t* coo, uint64_t nnz, const uint32_t* dims
 void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const uint32_t* dims, int N, int mode,
                      bool keep_src_pos, int threads, const std::vector<HotSet>* hot, HostMode& out,
                      BuildScratch* scratch = nullptr);
+
+// Load balancing scheme 1 (Sec. III-B): whole output rows are dealt to kappa
+// partitions by longest processing time first (Graham's rule, which meets the
+// 4/3 bound the paper quotes): rows by decreasing nonzero count (ties: lower
+// row first), each to the partition with the fewest nonzeros so far (ties:
+// lower partition).  Returns the partition of every row; part_load (may be
+// null) receives each partition's nonzeros.
+std::vector<uint32_t> lpt_assign(const uint64_t* load, uint64_t nrows, uint32_t kappa,
+                                 std::vector<uint64_t>* part_load);
+
+// Regroup a copy for scheme 1: the rows of partition 0 in increasing row
+// order, then those of partition 1, ...; each partition starts at a multiple
+// of 32 (zero entries fill the gaps, covered by no partition).
+// hm.part_range receives {first position, nonzeros} per partition; nnz_pad
+// grows to the regrouped length, nnz and the empty rows are unchanged.
+void lpt_regroup(HostMode& hm, uint32_t kappa);
+
+// Bytes one mode copy may grow by when regrouped for kappa partitions.
+uint64_t lpt_extra_bytes(int N, uint32_t kappa);
 
 // Bytes of one mode copy on the device (arrays only, without alignment padding).
 uint64_t mode_device_bytes(uint64_t nnz, int N, uint64_t I_mode);

@@ -226,7 +226,7 @@ hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* 
     f.out = out;
     f.wgc = g.wgc;
     f.nparts = m.nnz > 0 ? g.nparts : 0;
-    f.nbound = f.nparts > 1 ? f.nparts - 1 : 0;
+    f.nbound = f.nparts > 1 && !m.prange ? f.nparts - 1 : 0;   // scheme-1 partitions cut no rows
     f.nempty = m.nempty;
     f.R = R;
     const uint64_t eblocks = (m.nempty + kEmptyPerBlock - 1) / kEmptyPerBlock;

@@ -189,6 +189,7 @@ struct PartArgs {
     uint32_t gsz;
     uint32_t nhot;       // hot slots per input mode held in LDS
     uint32_t atomic_cut; // rows cut by a partition boundary: 0 partial to carry, 1 global atomic add to out
+    const uint64_t* prange; // scheme 1: {first position, nonzeros} per partition (whole rows); null: part * G * gsz
 };
 
 // Nonzeros whose row gathers are issued before the first is used, chosen so
@@ -428,17 +429,30 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
         __syncthreads();
     }
 
-    // 2. Walk this group's run of nonzeros, streaming one batch ahead.
-    const uint64_t wg_beg = (uint64_t)part * G * a.gsz;
-    const uint64_t g_beg = wg_beg + (uint64_t)g * a.gsz;
+    // 2. Walk this group's run of nonzeros, streaming one batch ahead.  A
+    //    nonzero-balanced partition is G runs of gsz; a scheme-1 partition
+    //    (whole rows, its own length) is split into G runs of a multiple of 32.
+    uint64_t wg_beg, wg_end;
+    uint32_t gsz;
+    if (a.prange) {
+        wg_beg = a.prange[2 * part];
+        wg_end = wg_beg + a.prange[2 * part + 1];
+        const uint64_t per = (wg_end - wg_beg + G - 1) / G;
+        gsz = (uint32_t)(per < 32 ? 32 : (per + 31) / 32 * 32);
+    } else {
+        wg_beg = (uint64_t)part * G * a.gsz;
+        wg_end = a.nnz;
+        gsz = a.gsz;
+    }
+    const uint64_t g_beg = wg_beg + (uint64_t)g * gsz;
     GroupState<E> st;
 #pragma unroll
     for (int e = 0; e < E; ++e) st.acc[e] = st.head[e] = 0.0f;
     st.first_row = -1;
     st.cur = -1;
     int hstart = -1;
-    if (g_beg < a.nnz) {
-        const uint64_t g_end = min(g_beg + (uint64_t)a.gsz, a.nnz);
+    if (g_beg < wg_end) {
+        const uint64_t g_end = min(g_beg + (uint64_t)gsz, wg_end);
         lds_char* hot_lds = (lds_char*)smem;
         __amdgpu_buffer_rsrc_t rsrc[NIN];
 #pragma unroll
@@ -477,8 +491,9 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
     }
     __syncthreads();
 
-    const uint64_t next_beg = wg_beg + (uint64_t)G * a.gsz;
-    const bool row_continues = next_beg < a.nnz && !(a.winfo[next_beg >> 5].x & 1u);
+    // Scheme-1 partitions hold whole rows: nothing continues past their end.
+    const uint64_t next_beg = wg_beg + (uint64_t)G * gsz;
+    const bool row_continues = !a.prange && next_beg < a.nnz && !(a.winfo[next_beg >> 5].x & 1u);
     const int hs = s_hstart[g];
     const int trow = s_trow[g];
 
@@ -565,6 +580,7 @@ void fill_part_args(PartArgs<NIN>& a, const DevMode& m, int R, int dtype, const 
     a.gsz = gsz;
     a.nhot = nhot;
     a.atomic_cut = 0;
+    a.prange = m.prange;
 }
 
 template <int NIN, int R, int DT, bool HOT>
@@ -582,7 +598,8 @@ hipError_t launch_part(const DevMode& m, const void* const* fac, const uint32_t*
         if (e != hipSuccess) return e;
         lds_set = lds;
     }
-    hipLaunchKernelGGL((mttkrp_part_kernel<NIN, R, DT, HOT>), dim3(g.nparts), dim3(part_wg(NIN)), lds, s, a);
+    hipLaunchKernelGGL((mttkrp_part_kernel<NIN, R, DT, HOT>), dim3(m.prange ? m.nprange : g.nparts),
+                       dim3(part_wg(NIN)), lds, s, a);
     return hipGetLastError();
 }
 

@@ -83,6 +83,14 @@ typedef struct {
                                   host; no hot rows; not usable in batches or the gather probe) */
     int lpt_parts;             /* partitions (the paper's kappa) of MTTKRP_PART_ROWS_LPT; 0 = one per
                                   compute unit */
+    int hot_steps;             /* 1: lay the copies out in wave steps for rank max_R and factor_dtype
+                                  (3- and 4-mode tensors; built on the host): each input's most gathered
+                                  rows are held in LDS, every output row's nonzeros are ordered by which
+                                  of their input rows are held there, and rows are padded with zero
+                                  entries to whole steps of one wave, so that steps whose rows are all held
+                                  skip the global gathers.  Runs then need R = max_R (fp32, or bf16 when
+                                  factor_dtype is MTTKRP_BF16); not usable in batches, the gather probe or
+                                  mttkrp_run_scheme2; hot_rows and partitioner are ignored.  0 (default): off */
 } mttkrp_opts;
 
 enum { MTTKRP_PART_NNZ = 0, MTTKRP_PART_ROWS_LPT = 1 };
@@ -229,6 +237,7 @@ typedef struct {
     uint32_t wg_threads;          /* threads per MTTKRP workgroup */
     uint32_t parts_per_cu;        /* MTTKRP workgroups launched per compute unit */
     uint32_t lpt_parts;           /* scheme-1 partitions (MTTKRP_PART_ROWS_LPT), 0 for the nonzero split */
+    uint32_t step_entries;        /* hot-steps copies: entries per wave step (0: nonzero-ordered copies) */
 } mttkrp_info;
 
 mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
@@ -378,6 +387,11 @@ typedef struct {
                                      scheme-1 copies nnz_pad entries, all ones at gap entries) */
     uint64_t nhot;                /* rows per input mode served from LDS */
     const uint32_t* hot_rows[MTTKRP_MAX_MODES - 1]; /* hot_rows[j][s]: row of mode in_modes[j] in slot s */
+    uint64_t step_entries;        /* hot-steps copies: entries per step; the arrays then hold nsteps steps
+                                     (nnz_pad = steps padded to 32, times step_entries), entry e of step s
+                                     at (s / 32) * 32 * step_entries + e * 32 + s % 32, winfo per 32 steps;
+                                     padding entries have value 0 and coordinate 0x80000000 | nhot */
+    uint64_t nsteps;
     uint64_t nparts;              /* scheme-1 partitions (0 for the nonzero split) */
     const uint64_t* part_range;   /* 2 * nparts: first position and nonzeros of each partition; the rows of
                                      partition p, in increasing order, fill [first, first + nonzeros) and

@@ -44,7 +44,8 @@ class MttkrpError(RuntimeError):
 class mttkrp_opts(ctypes.Structure):
     _fields_ = [("parts_per_cu", ctypes.c_int), ("factor_dtype", ctypes.c_int), ("max_R", ctypes.c_int),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int), ("hot_rows", ctypes.c_int),
-                ("build_on_host", ctypes.c_int), ("partitioner", ctypes.c_int), ("lpt_parts", ctypes.c_int)]
+                ("build_on_host", ctypes.c_int), ("partitioner", ctypes.c_int), ("lpt_parts", ctypes.c_int),
+                ("hot_steps", ctypes.c_int)]
 
 
 class mttkrp_mode_view(ctypes.Structure):
@@ -56,12 +57,14 @@ class mttkrp_mode_view(ctypes.Structure):
                 ("row_id", ctypes.POINTER(ctypes.c_uint32)), ("empty_rows", ctypes.POINTER(ctypes.c_uint32)),
                 ("src_pos", ctypes.POINTER(ctypes.c_uint64)), ("nhot", ctypes.c_uint64),
                 ("hot_rows", ctypes.POINTER(ctypes.c_uint32) * (MTTKRP_MAX_MODES - 1)),
+                ("step_entries", ctypes.c_uint64), ("nsteps", ctypes.c_uint64),
                 ("nparts", ctypes.c_uint64), ("part_range", ctypes.POINTER(ctypes.c_uint64))]
 
 
 class mttkrp_info(ctypes.Structure):
     _fields_ = [("cu_count", ctypes.c_uint32), ("lds_per_workgroup", ctypes.c_uint32), ("hot_rows", ctypes.c_uint32),
-                ("wg_threads", ctypes.c_uint32), ("parts_per_cu", ctypes.c_uint32), ("lpt_parts", ctypes.c_uint32)]
+                ("wg_threads", ctypes.c_uint32), ("parts_per_cu", ctypes.c_uint32), ("lpt_parts", ctypes.c_uint32),
+                ("step_entries", ctypes.c_uint32)]
 
 
 class mttkrp_plan(ctypes.Structure):
@@ -426,11 +429,14 @@ def mttkrp_layout_view(h: Layout, mode: int) -> dict:
     return dict(nnz=int(v.nnz), nnz_pad=int(v.nnz_pad), nrows_nz=int(v.nrows_nz), nempty=int(v.nempty),
                 in_modes=[int(v.in_modes[j]) for j in range(v.n_in)],
                 idx=[arr(v.idx[j], v.nnz_pad, np.uint32) for j in range(v.n_in)],
-                val=arr(v.val, v.nnz_pad, np.float32), winfo=arr(v.winfo, 2 * (v.nnz_pad // 32), np.uint32),
+                val=arr(v.val, v.nnz_pad, np.float32),
+                winfo=arr(v.winfo, 2 * ((v.nnz_pad // v.step_entries if v.step_entries else v.nnz_pad) // 32), np.uint32),
                 row_id=arr(v.row_id, v.nrows_nz, np.uint32), empty_rows=arr(v.empty_rows, v.nempty, np.uint32),
-                src_pos=arr(v.src_pos, v.nnz_pad if v.nparts else v.nnz, np.uint64), nhot=int(v.nhot),
+                src_pos=arr(v.src_pos, 0 if v.step_entries else (v.nnz_pad if v.nparts else v.nnz), np.uint64),
+                nhot=int(v.nhot),
                 hot_rows=[arr(v.hot_rows[j], v.nhot, np.uint32) for j in range(v.n_in)],
-                part_range=arr(v.part_range, 2 * v.nparts, np.uint64).reshape(-1, 2))
+                part_range=arr(v.part_range, 2 * v.nparts, np.uint64).reshape(-1, 2),
+                step_entries=int(v.step_entries), nsteps=int(v.nsteps))
 
 
 class Batch:

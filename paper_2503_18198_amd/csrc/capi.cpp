@@ -148,6 +148,7 @@ void mttkrp_opts_default(mttkrp_opts* o)
     o->build_on_host = 0;
     o->partitioner = MTTKRP_PART_NNZ;
     o->lpt_parts = 0;
+    o->hot_steps = 0;
 }
 
 const char* mttkrp_last_error(void) { return g_err.c_str(); }
@@ -164,6 +165,11 @@ static mttkrp_status check_opts(const mttkrp_opts* in, mttkrp_opts* o)
     if (o->partitioner != MTTKRP_PART_NNZ && o->partitioner != MTTKRP_PART_ROWS_LPT)
         return fail(MTTKRP_EINVAL, "partitioner must be MTTKRP_PART_NNZ or MTTKRP_PART_ROWS_LPT");
     if (o->lpt_parts < 0 || o->lpt_parts > (1 << 20)) return fail(MTTKRP_EINVAL, "lpt_parts must be in [0, 2^20]");
+    if (o->hot_steps != 0 && o->hot_steps != 1) return fail(MTTKRP_EINVAL, "hot_steps must be 0 or 1");
+    if (o->hot_steps) {
+        o->partitioner = MTTKRP_PART_NNZ;   // step copies carry their own hot rows and partitions
+        o->hot_rows = 0;
+    }
     if (o->partitioner == MTTKRP_PART_ROWS_LPT) o->hot_rows = 0;   // scheme-1 copies keep plain coordinates
     return MTTKRP_OK;
 }
@@ -184,6 +190,42 @@ static uint64_t lpt_bytes(const mttkrp_opts& o, int N, int cu_count)
     return (uint64_t)N * (mk::lpt_extra_bytes(N, kappa) + 4 * kAlign);
 }
 
+// Hot rows per input of a hot-steps layout: as many rows of max_R values of
+// the factor dtype as fit in the step kernel's LDS beside its wave partials,
+// less one zero row.
+static uint32_t step_hot_rows(int N, int maxR, int dtype, uint32_t lds_limit)
+{
+    const int es = dtype == MTTKRP_FP32 ? 4 : 2;
+    const uint32_t row = (uint32_t)(N - 1) * (uint32_t)maxR * (uint32_t)es;
+    const uint32_t partials = mk::step_kernel_lds_bytes(N - 1, maxR, es, 0) - row;
+    if (lds_limit <= partials + 2 * row) return 0;
+    return (lds_limit - partials) / row - 1;
+}
+
+// Device bytes of the N hot-steps copies (an upper bound: every output row
+// padded by up to one step).
+static uint64_t step_copies_bytes(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts& o)
+{
+    const uint32_t P = mk::step_entries(o.max_R, o.factor_dtype);
+    uint64_t b = 0;
+    for (int n = 0; n < N; ++n) {
+        const uint64_t steps = mk::step_copy_steps_bound(nnz, std::min<uint64_t>(nnz, dims[n]), P);
+        b += steps * P * 4ull * (uint64_t)N + steps / 32 * 8 + (uint64_t)dims[n] * 4 + (uint64_t)(N + 4) * kAlign;
+    }
+    return b;
+}
+
+static uint64_t layout_copies_bytes(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts& o)
+{
+    return o.hot_steps ? step_copies_bytes(dims, N, nnz, o) : copies_bytes(dims, N, nnz);
+}
+
+static uint32_t layout_hot_rows(int N, const mttkrp_opts& o, uint32_t lds_limit)
+{
+    return o.hot_steps ? step_hot_rows(N, o.max_R, o.factor_dtype, lds_limit)
+                       : hot_rows_for(N, o.max_R, lds_limit, o.hot_rows);
+}
+
 mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts* opts, uint64_t* bytes)
 {
     g_err.clear();
@@ -194,8 +236,8 @@ mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const 
     mttkrp_opts o;
     mttkrp_status s = check_opts(opts, &o);
     if (s) return s;
-    *bytes = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
-             hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows)) + lpt_bytes(o, N, 0);
+    *bytes = layout_copies_bytes(dims, N, nnz, o) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
+             hot_bytes(N, layout_hot_rows(N, o, kAssumedLds)) + lpt_bytes(o, N, 0);
     return MTTKRP_OK;
 }
 
@@ -222,8 +264,9 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     // Admission first, before any device call (the hot tables are sized for the
     // largest LDS, an upper bound).
     {
-        const uint64_t bound = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
-                               hot_bytes(N, hot_rows_for(N, o.max_R, kAssumedLds, o.hot_rows)) + lpt_bytes(o, N, 0);
+        const uint64_t bound = layout_copies_bytes(dims, N, nnz, o) +
+                               plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
+                               hot_bytes(N, layout_hot_rows(N, o, kAssumedLds)) + lpt_bytes(o, N, 0);
         if (!o.host_only && o.hbm_budget_bytes && bound > o.hbm_budget_bytes)
             return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(bound) + " B exceeds the budget of " +
                                            std::to_string(o.hbm_budget_bytes) + " B");
@@ -237,7 +280,8 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id) == hipSuccess && v > 0)
             lds_limit = (uint32_t)v;
     }
-    const uint32_t nhot = hot_rows_for(N, o.max_R, lds_limit, o.hot_rows);
+    if (o.hot_steps && (N < 3 || N > 4)) return fail(MTTKRP_EUNSUPPORTED, "hot_steps supports 3- and 4-mode tensors");
+    const uint32_t nhot = layout_hot_rows(N, o, lds_limit);
     int cus_here = 256;
     if (!o.host_only) {
         int v = 0;
@@ -246,8 +290,10 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     }
     const bool lpt = o.partitioner == MTTKRP_PART_ROWS_LPT;
     const uint32_t kappa = lpt_kappa(o, cus_here);
-    const uint64_t need = copies_bytes(dims, N, nnz) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
-                          hot_bytes(N, nhot) + lpt_bytes(o, N, cus_here);
+    const uint64_t need = layout_copies_bytes(dims, N, nnz, o) +
+                          plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total + hot_bytes(N, nhot) +
+                          lpt_bytes(o, N, cus_here);
+    const uint32_t step_P = o.hot_steps ? mk::step_entries(o.max_R, o.factor_dtype) : 0u;
 
     auto* h = new mttkrp_layout();
     h->N = N;
@@ -265,8 +311,20 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     if (h->host_only) {
         h->host.resize(N);
         for (int n = 0; n < N; ++n) {
-            mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, true, threads, &hot, h->host[n], &scratch);
+            mk::build_host_mode(coo_idx, vals, nnz, dims, N, n, !o.hot_steps, threads, &hot, h->host[n], &scratch);
             if (lpt) mk::lpt_regroup(h->host[n], kappa);
+            if (step_P) {
+                // The view shows the step copy: its arrays replace the nonzero-ordered ones.
+                mk::StepCopy sc;
+                mk::build_step_copy(h->host[n], step_P, nhot, threads, sc);
+                mk::HostMode& hm = h->host[n];
+                hm.idx = std::move(sc.idx);
+                hm.val = std::move(sc.val);
+                hm.winfo = std::move(sc.winfo);
+                hm.nnz_pad = sc.nsteps_pad * step_P;
+                hm.step_P = step_P;
+                hm.nsteps = sc.nsteps;
+            }
         }
         for (auto& hs : hot) hs.rows.resize(nhot, 0u);
         h->hot = std::move(hot);
@@ -345,7 +403,7 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
 
     double normX2 = 0.0;
     // With the caller's memory the device build runs only in the caller's scratch.
-    const bool dev_build = !o.build_on_host && !lpt && nhot == 0 && mk::device_build_applies(dims, N, nnz) &&
+    const bool dev_build = !o.build_on_host && !lpt && !o.hot_steps && nhot == 0 && mk::device_build_applies(dims, N, nnz) &&
                            (!ext_mem || (ext_scratch && ext_scratch_bytes >= mk::device_build_scratch_bytes(dims, N, nnz)));
     if (e == hipSuccess && dev_build) {
         // Mode copies sorted and laid out on the device.
@@ -391,6 +449,16 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
                 }
             }
             if (lpt) mk::lpt_regroup(hm, kappa);
+            if (step_P) {
+                mk::StepCopy sc;
+                mk::build_step_copy(hm, step_P, nhot, threads, sc);
+                hm.idx = std::move(sc.idx);
+                hm.val = std::move(sc.val);
+                hm.winfo = std::move(sc.winfo);
+                hm.nnz_pad = sc.nsteps_pad * step_P;
+                hm.step_P = step_P;
+                hm.nsteps = sc.nsteps;
+            }
             mk::DevMode& d = h->dev[n];
             d.nnz = hm.nnz;
             d.nnz_pad = hm.nnz_pad;
@@ -415,6 +483,8 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
                 d.prange = static_cast<const uint64_t*>(up(hm.part_range.data(), hm.part_range.size() * 8));
                 d.nprange = kappa;
             }
+            d.step_P = hm.step_P;
+            d.nsteps = hm.nsteps;
             // The next mode overwrites the host arrays; wait for the copies that read them.
             if (e == hipSuccess) e = hipStreamSynchronize(stream);
         }
@@ -482,6 +552,7 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info)
     info->wg_threads = (uint32_t)mk::partition_wg_threads(h->N - 1);
     info->parts_per_cu = (uint32_t)h->opts.parts_per_cu;
     info->lpt_parts = h->opts.partitioner == MTTKRP_PART_ROWS_LPT ? lpt_kappa(h->opts, h->cu_count) : 0u;
+    info->step_entries = h->opts.hot_steps ? mk::step_entries(h->opts.max_R, h->opts.factor_dtype) : 0u;
     return MTTKRP_OK;
 }
 
@@ -556,6 +627,8 @@ mttkrp_status mttkrp_layout_view(mttkrp_handle h, int mode, mttkrp_mode_view* v)
     v->src_pos = m.src_pos.data();
     v->nhot = h->nhot;
     for (int j = 0; j < v->n_in; ++j) v->hot_rows[j] = h->hot[m.in_modes[j]].rows.data();
+    v->step_entries = m.step_P;
+    v->nsteps = m.nsteps;
     v->nparts = m.part_range.size() / 2;
     v->part_range = m.part_range.empty() ? nullptr : m.part_range.data();
     return MTTKRP_OK;
@@ -582,6 +655,25 @@ static mttkrp_status check_run(mttkrp_handle h, int mode, const void* const* fac
     return MTTKRP_OK;
 }
 
+// Launch plan of one mode's MTTKRP on this handle (nonzero partitions, or
+// wave steps for hot-steps copies, which run at the layout's rank and dtype only).
+static mttkrp_status plan_for(mttkrp_handle h, const mk::DevMode& d, int R, int dtype, mk::Geometry* g)
+{
+    if (d.step_P) {
+        if (R != h->opts.max_R || dtype != h->opts.factor_dtype)
+            return fail(MTTKRP_EUNSUPPORTED, "this handle's copies are laid out in wave steps for R=" +
+                                                 std::to_string(h->opts.max_R) + " and " +
+                                                 (h->opts.factor_dtype == MTTKRP_FP32 ? "fp32" : "bf16") +
+                                                 " factors only");
+        *g = mk::plan_step_geometry(d.nsteps, R, dtype, d.step_P, h->opts.parts_per_cu * h->cu_count,
+                                    max_parts_for(h->nnz), kMaxChain, (uint32_t)h->cu_count);
+        return MTTKRP_OK;
+    }
+    *g = mk::plan_geometry(d.nnz, d.n_in, R, dtype, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz),
+                           kMaxChain);
+    return MTTKRP_OK;
+}
+
 static mttkrp_status run_mode(mttkrp_handle h, int mode, const void* const* factors, int dtype, float* out, int R,
                               hipStream_t stream)
 {
@@ -592,7 +684,9 @@ static mttkrp_status run_mode(mttkrp_handle h, int mode, const void* const* fact
         fac[j] = factors[d.in_modes[j]];
         hot[j] = h->hot_rows[d.in_modes[j]];
     }
-    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, dtype, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz), kMaxChain);
+    mk::Geometry g;
+    mttkrp_status ps = plan_for(h, d, R, dtype, &g);
+    if (ps) return ps;
     hipError_t e = mk::launch_mttkrp(d, R, dtype, fac, hot, h->nhot, out, h->carry, g, stream);
     if (e != hipSuccess) return hip_fail(e, "MTTKRP launch");
     return MTTKRP_OK;
@@ -627,8 +721,9 @@ mttkrp_status mk::run_fp32_with_carry(mttkrp_handle h, int mode, const float* co
         fac[j] = factors[d.in_modes[j]];
         hot[j] = h->hot_rows[d.in_modes[j]];
     }
-    const mk::Geometry g = mk::plan_geometry(d.nnz, d.n_in, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count,
-                                             max_parts_for(h->nnz), kMaxChain);
+    mk::Geometry g;
+    mttkrp_status ps = plan_for(h, d, R, MTTKRP_FP32, &g);
+    if (ps) return ps;
     const uint64_t need = (uint64_t)g.nparts * 2ull * (uint64_t)R * sizeof(float);
     if (need > carry_bytes)
         return fail(MTTKRP_ENOMEM, "this launch needs " + std::to_string(need) + " B of carry rows (" +
@@ -656,6 +751,7 @@ mttkrp_status mttkrp_run_scheme2(mttkrp_handle h, int mode, const float* const* 
     g_err.clear();
     mttkrp_status s = check_run(h, mode, reinterpret_cast<const void* const*>(factors), out, R);
     if (s) return s;
+    if (h->opts.hot_steps) return fail(MTTKRP_EUNSUPPORTED, "scheme 2 runs on nonzero-ordered copies only");
     const mk::DevMode& d = h->dev[mode];
     const void* fac[mk::kMaxIn];
     const uint32_t* hot[mk::kMaxIn];
@@ -679,7 +775,7 @@ mttkrp_status mttkrp_gather_probe(mttkrp_handle h, int mode, const void* const* 
         return fail(MTTKRP_EINVAL, "factor_dtype must be MTTKRP_FP32 or MTTKRP_BF16");
     if (what != 0 && what != 1) return fail(MTTKRP_EINVAL, "what must be 0 (stream) or 1 (stream and gathers)");
     if (!h) return fail(MTTKRP_EINVAL, "NULL handle");
-    if (h->opts.partitioner == MTTKRP_PART_ROWS_LPT)
+    if (h->opts.partitioner == MTTKRP_PART_ROWS_LPT || h->opts.hot_steps)
         return fail(MTTKRP_EUNSUPPORTED, "the gather probe runs the nonzero-balanced partitions only");
     // The probe has no output: the handle's own carry workspace stands in for
     // it in the common argument checks.
@@ -900,6 +996,9 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
         if (h->opts.partitioner == MTTKRP_PART_ROWS_LPT)
             return fail(MTTKRP_EUNSUPPORTED, "layout " + std::to_string(t) +
                                                  " uses scheme-1 partitions, which batches do not support");
+        if (h->opts.hot_steps)
+            return fail(MTTKRP_EUNSUPPORTED, "layout " + std::to_string(t) +
+                                                 " has hot-steps copies, which batches do not support");
         if (h->nhot)
             return fail(MTTKRP_EUNSUPPORTED, "layout " + std::to_string(t) +
                                                  " keeps hot rows in LDS; batches take layouts built with hot_rows = 0");

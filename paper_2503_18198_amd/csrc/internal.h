@@ -30,6 +30,10 @@ struct DevMode {
     // of nprange partitions; null for the nonzero-balanced split.
     const uint64_t* prange = nullptr;
     uint32_t nprange = 0;
+    // Hot-steps copy (step_P > 0): the arrays hold nsteps steps of step_P
+    // entries, transposed per 32 steps, and winfo describes steps.
+    uint32_t step_P = 0;
+    uint64_t nsteps = 0;
 };
 
 // Launch geometry of one MTTKRP call.
@@ -38,7 +42,8 @@ struct Geometry {
     int groups;         // lane groups per workgroup
     uint32_t gsz;       // nonzeros per lane group (multiple of 32)
     uint64_t wgc;       // nonzeros per workgroup partition = groups * gsz
-    uint32_t nparts;    // workgroups
+    uint32_t nparts;    // workgroups (partitions)
+    uint32_t grid = 0;  // hot-steps copies: resident workgroups that walk the partitions
 };
 
 // Partitions of about nnz / target_parts nonzeros, with at most max_parts
@@ -46,6 +51,19 @@ struct Geometry {
 // lane group (the length of its FP32 accumulation chain).
 Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts,
                        uint32_t max_gsz);
+
+// Launch plan of a hot-steps copy of nsteps steps: gsz = steps per wave run
+// (a multiple of 32, at most max_chain / passes), groups = waves per
+// workgroup, wgc = steps per partition, nparts partitions (at most max_parts).
+Geometry plan_step_geometry(uint64_t nsteps, int R, int dtype, uint32_t P, int target_parts, uint32_t max_parts,
+                            uint32_t max_chain, uint32_t cu_count);
+
+// Entries per step of a hot-steps copy laid out for rank R and factor dtype:
+// the lane groups one wave runs at that rank and dtype.
+uint32_t step_entries(int R, int dtype);
+
+// LDS bytes of the step kernel for n_in inputs, rank R, element bytes es, nhot hot rows each.
+uint32_t step_kernel_lds_bytes(int n_in, int R, int es, uint32_t nhot);
 
 // Threads per partition workgroup for n_in input modes.
 int partition_wg_threads(int n_in);

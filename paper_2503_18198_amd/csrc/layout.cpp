@@ -358,6 +358,8 @@ void build_host_mode(const uint32_t* coo, const float* vals, uint64_t nnz, const
     out.row_id.clear();
     out.empty_rows.clear();
     out.part_range.clear();
+    out.step_P = 0;
+    out.nsteps = 0;
 
     std::vector<int> cyc;
     for (int j = 1; j < N; ++j) cyc.push_back((n + j) % N);
@@ -530,6 +532,85 @@ void lpt_regroup(HostMode& hm, uint32_t kappa)
     hm.row_id = std::move(row_id);
     hm.nnz_pad = total;
     hm.src_pos = std::move(src);   // per position (gap entries: all ones)
+}
+
+uint32_t class_rank(uint32_t cls)
+{
+    // position of cls in the reflected Gray sequence: inverse Gray code
+    uint32_t r = cls;
+    for (uint32_t sh = 1; sh < 32; sh <<= 1) r ^= r >> sh;
+    return r;
+}
+
+uint64_t step_copy_steps_bound(uint64_t nnz, uint64_t rows, uint32_t P)
+{
+    const uint64_t steps = (nnz + (uint64_t)(P - 1) * rows + P - 1) / P;
+    return (steps + 31) / 32 * 32;
+}
+
+void build_step_copy(const HostMode& hm, uint32_t P, uint32_t nhot, int threads, StepCopy& out)
+{
+    const int n_in = (int)hm.idx.size();
+    const uint64_t nrows = hm.nrows_nz;
+    // Row extents of the sorted copy.
+    std::vector<uint64_t> beg(nrows + 1, hm.nnz);
+    {
+        uint64_t o = 0;
+        for (uint64_t w = 0; w < hm.nnz_pad / 32; ++w) {
+            uint32_t bits = hm.winfo[2 * w];
+            while (bits) {
+                const int b = __builtin_ctz(bits);
+                bits &= bits - 1;
+                beg[o++] = w * 32 + (uint64_t)b;
+            }
+        }
+    }
+    // First step of every row.
+    std::vector<uint64_t> sbeg(nrows + 1, 0);
+    for (uint64_t o = 0; o < nrows; ++o) sbeg[o + 1] = sbeg[o] + (beg[o + 1] - beg[o] + P - 1) / P;
+    out.P = P;
+    out.nsteps = sbeg[nrows];
+    out.nsteps_pad = (out.nsteps + 31) / 32 * 32;
+    if (out.nsteps_pad == 0) out.nsteps_pad = 32;
+    const uint64_t len = out.nsteps_pad * P;
+    out.idx.resize(n_in);
+    const uint32_t pad_coord = kHotBit | nhot;   // the zero row after the hot rows
+    for (auto& v : out.idx) v.assign(len, pad_coord);
+    out.val.assign(len, 0.0f);
+    auto at = [&](uint64_t s, uint32_t e) { return (s / 32) * 32 * P + (uint64_t)e * 32 + s % 32; };
+    parallel_for(nrows, threads, [&](uint64_t o0, uint64_t o1) {
+        std::vector<std::pair<uint32_t, uint32_t>> key;   // (class rank, offset in the row)
+        for (uint64_t o = o0; o < o1; ++o) {
+            const uint64_t b = beg[o], n = beg[o + 1] - beg[o];
+            key.resize(n);
+            for (uint64_t k = 0; k < n; ++k) {
+                uint32_t cls = 0;
+                for (int j = 0; j < n_in; ++j)
+                    if (!(hm.idx[j][b + k] & kHotBit)) cls |= 1u << j;
+                key[k] = {class_rank(cls), (uint32_t)k};
+            }
+            std::stable_sort(key.begin(), key.end(),
+                             [](const std::pair<uint32_t, uint32_t>& x, const std::pair<uint32_t, uint32_t>& y) {
+                                 return x.first < y.first;
+                             });
+            for (uint64_t k = 0; k < n; ++k) {
+                const uint64_t src = b + key[k].second;
+                const uint64_t dst = at(sbeg[o] + k / P, (uint32_t)(k % P));
+                for (int j = 0; j < n_in; ++j) out.idx[j][dst] = hm.idx[j][src];
+                out.val[dst] = hm.val[src];
+            }
+        }
+    });
+    // Per 32 steps: row-start bits and the ordinal of the row holding the first step.
+    const uint64_t nw = out.nsteps_pad / 32;
+    out.winfo.assign(2 * nw, 0u);
+    for (uint64_t o = 0; o < nrows; ++o) out.winfo[2 * (sbeg[o] / 32)] |= 1u << (sbeg[o] % 32);
+    uint64_t before = 0;
+    for (uint64_t w = 0; w < nw; ++w) {
+        const uint32_t bits = out.winfo[2 * w];
+        out.winfo[2 * w + 1] = (uint32_t)(before + (bits & 1u) - 1u);
+        before += (uint64_t)__builtin_popcount(bits);
+    }
 }
 
 }  // namespace mk

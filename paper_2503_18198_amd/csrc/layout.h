@@ -53,6 +53,8 @@ struct HostMode {
     std::vector<uint32_t> empty_rows;          // [nempty]
     buf<uint64_t> src_pos;                     // [nnz] (kept only on request)
     std::vector<uint64_t> part_range;          // scheme 1 only: {first position, nonzeros} per partition
+    uint32_t step_P = 0;                       // hot-steps copy: entries per step (arrays hold steps, transposed)
+    uint64_t nsteps = 0;
 };
 
 // Sort buffers of a build, kept across its modes so their pages are mapped once.
@@ -105,6 +107,35 @@ void lpt_regroup(HostMode& hm, uint32_t kappa);
 
 // Bytes one mode copy may grow by when regrouped for kappa partitions.
 uint64_t lpt_extra_bytes(int N, uint32_t kappa);
+
+// A mode copy laid out in wave steps (the hot-steps layout): inside every
+// output row the nonzeros are ordered by which of their input rows are hot
+// (held in LDS; coordinates kHotBit | slot), all-hot first, then in the same
+// cyclic index order as before; every row is padded with entries of value 0
+// whose coordinates name the zero row kHotBit | nhot to a whole number of
+// steps of P entries, so a step lies in one row and a wave can tell, for each
+// input, whether all its lanes' rows are hot.  Storage is transposed per 32
+// steps: entry e of step s sits at (s / 32) * 32 * P + e * 32 + s % 32, so
+// the entries one lane group takes from 32 consecutive steps are contiguous.
+struct StepCopy {
+    uint32_t P = 0;                            // entries per step
+    uint64_t nsteps = 0, nsteps_pad = 0;       // steps, and padded to a multiple of 32
+    std::vector<buf<uint32_t>> idx;            // [n_in][nsteps_pad * P]
+    buf<float> val;                            // [nsteps_pad * P]
+    std::vector<uint32_t> winfo;               // per 32 steps: {row-start bits, ordinal of the row of the first}
+};
+
+// Order of a hot/cold class (bit j set: input j cold): reflected Gray code, so
+// consecutive classes differ in one input.
+uint32_t class_rank(uint32_t cls);
+
+// Lay out a copy (built with hot sets) in steps of P entries.  Rows and their
+// ordinals, empty rows and |X|^2 are those of hm.
+void build_step_copy(const HostMode& hm, uint32_t P, uint32_t nhot, int threads, StepCopy& out);
+
+// Steps of a step copy of a tensor whose mode has the given nonempty-row count,
+// at most (bound used for footprints): ceil((nnz + (P - 1) * rows) / P) rounded up to 32.
+uint64_t step_copy_steps_bound(uint64_t nnz, uint64_t rows, uint32_t P);
 
 // Bytes of one mode copy on the device (arrays only, without alignment padding).
 uint64_t mode_device_bytes(uint64_t nnz, int N, uint64_t I_mode);

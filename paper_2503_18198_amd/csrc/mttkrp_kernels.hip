@@ -27,6 +27,7 @@
 //    one; ordinals map to output rows through the list of nonempty rows.
 #include "internal.h"
 #include "part_kernel.h"
+#include "step_kernel.h"
 
 namespace mk {
 
@@ -61,6 +62,11 @@ extern template hipError_t launch_part_nin<6>(const DevMode&, int, int, const vo
                                                 uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 extern template hipError_t launch_part_nin<7>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
                                                 uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
+
+extern template hipError_t launch_step_nin<2>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                             uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
+extern template hipError_t launch_step_nin<3>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
+                                             uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 
 namespace {
 
@@ -180,6 +186,37 @@ Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_part
 
 uint32_t partition_lds_bytes(int n_in, int R, int dtype, uint32_t nhot) { return part_lds_bytes(n_in, R, dtype, nhot); }
 
+uint32_t step_entries(int R, int dtype) { return 64u / (uint32_t)lanes_per_row(R, dtype); }
+
+uint32_t step_kernel_lds_bytes(int n_in, int R, int es, uint32_t nhot) { return step_lds_bytes(n_in, R, es, nhot); }
+
+Geometry plan_step_geometry(uint64_t nsteps, int R, int dtype, uint32_t P, int target_parts, uint32_t max_parts,
+                            uint32_t max_chain, uint32_t cu_count)
+{
+    Geometry g;
+    g.lanes = lanes_per_row(R, dtype);
+    g.groups = kStepWaves;
+    const uint32_t passes = P / step_entries(R, dtype);   // entries one lane group adds per step
+    if (target_parts < 1) target_parts = 1;
+    uint64_t max_w = max_chain / (passes ? passes : 1);
+    max_w = max_w < 32 ? 32 : max_w / 32 * 32;
+    uint64_t per = (nsteps + (uint64_t)target_parts * kStepWaves - 1) / ((uint64_t)target_parts * kStepWaves);
+    uint64_t w = (per + 31) / 32 * 32;
+    if (w < 32) w = 32;
+    if (w > max_w) w = max_w;
+    uint64_t parts = (nsteps + w * kStepWaves - 1) / (w * kStepWaves);
+    if (parts > max_parts) {
+        const uint64_t pw = (nsteps + (uint64_t)max_parts * kStepWaves - 1) / ((uint64_t)max_parts * kStepWaves);
+        w = (pw + 31) / 32 * 32;
+        parts = (nsteps + w * kStepWaves - 1) / (w * kStepWaves);
+    }
+    g.gsz = (uint32_t)w;
+    g.wgc = w * kStepWaves;
+    g.nparts = (uint32_t)parts;
+    g.grid = g.nparts < cu_count ? g.nparts : (cu_count ? cu_count : 1u);
+    return g;
+}
+
 int partition_wg_threads(int n_in) { return part_wg(n_in); }
 
 // out[0..n) = 0 (a kernel, not a memset, so that it can sit in a captured graph).
@@ -205,7 +242,16 @@ hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* 
         if (e != hipSuccess) return e;
     }
     const uint32_t ac = atomic_cut ? 1u : 0u;
-    if (m.nnz > 0) {
+    if (m.nnz > 0 && m.step_P) {
+        // Hot-steps copy: one resident workgroup per compute unit walks the partitions.
+        const uint32_t grid = g.grid ? g.grid : 1u;
+        switch (m.n_in) {
+            case 2: e = launch_step_nin<2>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, grid, s); break;
+            case 3: e = launch_step_nin<3>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, grid, s); break;
+            default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    } else if (m.nnz > 0) {
         switch (m.n_in) {
             case 2: e = launch_part_nin<2>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, ac, s); break;
             case 3: e = launch_part_nin<3>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, ac, s); break;

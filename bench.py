@@ -631,6 +631,10 @@ def main(argv=None):
     ap.add_argument("--no-side-workloads", action="store_true",
                     help="default workload only: leave out the batch and serve sub-objects")
     ap.add_argument("--parts-per-cu", type=int, default=0)
+    ap.add_argument("--kernel", choices=("steps", "nonzero"), default="nonzero",
+                    help="layout timed for the MTTKRP: nonzero-ordered copies or hot-steps copies (3- and 4-mode)")
+    ap.add_argument("--no-compare-layouts", action="store_true",
+                    help="time only the chosen layout (no second layout beside it)")
     ap.add_argument("--hot-rows", type=int, default=0, help="rows per input factor cached in LDS (-1: as many as fit)")
     ap.add_argument("--als-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -694,23 +698,35 @@ def main(argv=None):
     N = len(t.dims)
     print(f"[bench] generated {t.dims} nnz={t.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
-    opts = dict(max_R=R, hot_rows=args.hot_rows)
+    # The timed layout: nonzero-ordered copies (the library default) unless
+    # --kernel steps.  The other layout of a 3- or 4-mode tensor is timed
+    # beside it on the same factors; the gather-ceiling probe runs on the
+    # nonzero-ordered copies.
+    steps = args.kernel == "steps" and N in (3, 4)
+    other = N in (3, 4) and not args.no_compare_layouts
+    opts0 = dict(max_R=R, hot_rows=args.hot_rows)
     if args.parts_per_cu:
-        opts["parts_per_cu"] = args.parts_per_cu
+        opts0["parts_per_cu"] = args.parts_per_cu
+    opts1 = dict(max_R=R, hot_steps=1, parts_per_cu=args.parts_per_cu or 2)
     stream = torch.cuda.current_stream()
     t_b = time.perf_counter()
-    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=opts, stream=stream)
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=opts1 if steps else opts0, stream=stream)
     build_s = time.perf_counter() - t_b
     print(f"[bench] layout built in {build_s:.1f}s ({capi.mttkrp_layout_bytes(h) / 2**30:.2f} GiB)",
           file=sys.stderr, flush=True)
+    t_b = time.perf_counter()
+    h_other = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=opts0 if steps else opts1,
+                                       stream=stream) if other else None
+    other_build_s = time.perf_counter() - t_b
+    h0 = h_other if steps else h      # nonzero-ordered copies (None: not built)
     dF = [torch.from_numpy(f).cuda() for f in F]
     outs = [torch.empty((d, R), dtype=torch.float32, device="cuda") for d in t.dims]
 
-    def all_modes(ev=None):
+    def all_modes(ev=None, hh=None):
         for n in range(N):
             if ev is not None:
                 ev[n][0].record(stream)
-            capi.mttkrp_run(h, n, dF, outs[n], R, stream=stream)
+            capi.mttkrp_run(hh or h, n, dF, outs[n], R, stream=stream)
             if ev is not None:
                 ev[n][1].record(stream)
 
@@ -732,6 +748,20 @@ def main(argv=None):
     ms_step = total_ms / K
     mode_ms = [float(np.mean([events[k][n][0].elapsed_time(events[k][n][1]) for k in range(K)])) for n in range(N)]
     step_ms = [events[k][0][0].elapsed_time(events[k][N - 1][1]) for k in range(K)]
+
+    # The other layout on the same factors, for comparison.
+    mode_ms_other = None
+    if other:
+        for _ in range(args.warmup):
+            all_modes(hh=h_other)
+        ev0 = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(N)]
+               for _ in range(K)]
+        torch.cuda.synchronize()
+        for k in range(K):
+            all_modes(ev0[k], hh=h_other)
+        torch.cuda.synchronize()
+        mode_ms_other = [float(np.mean([ev0[k][n][0].elapsed_time(ev0[k][n][1]) for k in range(K)])) for n in range(N)]
+    mode_ms0 = mode_ms_other if steps else mode_ms
 
     flops = N * R * t.nnz * N
     gflops = flops / (ms_step / 1e3) / 1e9
@@ -760,24 +790,36 @@ def main(argv=None):
         "step_ms_min": round(float(np.min(step_ms)), 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(args.workload),
-                     "kernel": "per-mode MTTKRP launch pair (mttkrp_part_kernel + mttkrp_fixup_kernel): "
-                               "algorithmic bytes per mode / HIP-event time of the pair, averaged over modes",
+                     "kernel": ("per-mode MTTKRP launch pair (mttkrp_step_kernel on hot-steps copies + "
+                                "mttkrp_fixup_kernel)" if steps else
+                                "per-mode MTTKRP launch pair (mttkrp_part_kernel + mttkrp_fixup_kernel)") +
+                               ": algorithmic bytes per mode / HIP-event time of the pair, averaged over modes",
                      "algorithmic_bytes_per_launch": round(sum(bytes_mode) / N),
                      "bytes_per_mode": bytes_mode},
         "build_s": round(build_s, 2),
         "launch": capi.mttkrp_layout_info(h),
+        "layout": ("hot-steps copies (rows ordered by hot/cold input rows, padded to wave steps; built on the host)"
+                   if steps else "nonzero-ordered copies"),
     }
+    if other:
+        result["nonzero_order_copies" if steps else "hot_steps_copies"] = {
+            "per_mode_ms": [round(x, 4) for x in mode_ms_other], "all_mode_ms": round(sum(mode_ms_other), 4),
+            "build_s": round(other_build_s, 2), "launch": capi.mttkrp_layout_info(h_other),
+            "what": ("the same MTTKRP on the nonzero-ordered copies (mttkrp_part_kernel)" if steps else
+                     "the same MTTKRP on hot-steps copies (mttkrp_step_kernel; hot_steps=1, 2 partitions per CU): "
+                     "rows ordered by hot/cold input rows and padded to wave steps, hot rows read from LDS") +
+                    ", same factors and steps"}
 
     # On-chip ceilings of this index pattern: the same partitions' stream
     # loads alone, and with every factor-row gather, without the arithmetic.
-    if not args.no_gather_ceiling:
+    if not args.no_gather_ceiling and h0 is not None:
         def probe_ms(what):
             ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(N)]
             tot = [0.0] * N
             for rep in range(K + 1):
                 for n in range(N):
                     ev[n][0].record(stream)
-                    capi.mttkrp_gather_probe(h, n, dF, R, what, stream=stream)
+                    capi.mttkrp_gather_probe(h0, n, dF, R, what, stream=stream)
                     ev[n][1].record(stream)
                 torch.cuda.synchronize()
                 if rep:
@@ -792,10 +834,10 @@ def main(argv=None):
             "stream_and_gathers_ms_per_mode": [round(x, 4) for x in gather_ms],
             "gathered_bytes_per_mode": gbytes[0],
             "gathered_TBps_in_probe": round(sum(gbytes) / (sum(gather_ms) / 1e3) / 1e12, 2),
-            "gathered_TBps_in_mttkrp": round(sum(gbytes) / (sum(mode_ms) / 1e3) / 1e12, 2),
-            "mttkrp_time_over_probe_time": round(sum(mode_ms) / sum(gather_ms), 3),
-            "what": "mttkrp_gather_probe: the MTTKRP's stream loads and factor-row gathers on the same partitions "
-                    "and lanes, arithmetic and stores replaced by an XOR fold",
+            "gathered_TBps_in_mttkrp": round(sum(gbytes) / (sum(mode_ms0) / 1e3) / 1e12, 2),
+            "mttkrp_time_over_probe_time": round(sum(mode_ms0) / sum(gather_ms), 3),
+            "what": "mttkrp_gather_probe on the nonzero-ordered copies: their MTTKRP's stream loads and factor-row "
+                    "gathers on the same partitions and lanes, arithmetic and stores replaced by an XOR fold",
         }
 
     # CP-ALS sweeps (MTTKRP plus the FP64 update), timed separately.
@@ -821,6 +863,8 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(t, R, F)
     h.free()
+    if h_other is not None:
+        h_other.free()
     del dF, outs
     if side:
         # The second half of the metric: batched requests/s and served p50/p99

@@ -549,7 +549,7 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info)
     info->cu_count = (uint32_t)h->cu_count;
     info->lds_per_workgroup = h->lds_limit;
     info->hot_rows = h->nhot;
-    info->wg_threads = (uint32_t)mk::partition_wg_threads(h->N - 1);
+    info->wg_threads = (uint32_t)(h->opts.hot_steps ? mk::step_wg_threads() : mk::partition_wg_threads(h->N - 1));
     info->parts_per_cu = (uint32_t)h->opts.parts_per_cu;
     info->lpt_parts = h->opts.partitioner == MTTKRP_PART_ROWS_LPT ? lpt_kappa(h->opts, h->cu_count) : 0u;
     info->step_entries = h->opts.hot_steps ? mk::step_entries(h->opts.max_R, h->opts.factor_dtype) : 0u;

@@ -68,6 +68,9 @@ uint32_t step_kernel_lds_bytes(int n_in, int R, int es, uint32_t nhot);
 // Threads per partition workgroup for n_in input modes.
 int partition_wg_threads(int n_in);
 
+// Threads per workgroup of the step kernel (hot-steps copies).
+int step_wg_threads();
+
 // Dynamic LDS of the partition kernel for n_in input modes and nhot cached rows per mode.
 uint32_t partition_lds_bytes(int n_in, int R, int dtype, uint32_t nhot);
 

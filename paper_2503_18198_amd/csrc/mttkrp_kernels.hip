@@ -219,6 +219,8 @@ Geometry plan_step_geometry(uint64_t nsteps, int R, int dtype, uint32_t P, int t
 
 int partition_wg_threads(int n_in) { return part_wg(n_in); }
 
+int step_wg_threads() { return kStepWG; }
+
 // out[0..n) = 0 (a kernel, not a memset, so that it can sit in a captured graph).
 __global__ __launch_bounds__(kWG) void zero_fill_kernel(float* __restrict__ p, uint64_t n)
 {

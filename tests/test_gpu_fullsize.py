@@ -1,6 +1,7 @@
-"""Parity at the benchmark's full size and launch configuration: the
-20M-nonzero 200000 x 150000 x 100000 Zipf(1.2) tensor at R=32 with the
-library defaults (the launch bench.py times).  Every output row of every
+"""Parity at the benchmark's full size and launch configurations: the
+20M-nonzero 200000 x 150000 x 100000 Zipf(1.2) tensor at R=32, on the
+hot-steps copies with 2 partitions per compute unit (the launch bench.py
+times) and on the nonzero-ordered copies with the library defaults.  Every output row of every
 mode is compared with the FP64 oracle (16 threads, about a second per mode).
 Bar: relative Frobenius error <= 1e-5 per mode, and no row whose own
 relative error exceeds 1e-5 (rows of tiny norm are judged against the mode's
@@ -18,12 +19,19 @@ from tests import gpu_util as gu
 pytestmark = pytest.mark.gpu
 
 
-def test_zipf20m_full_size_every_row():
-    print("case full-size zipf1.2-20M, every row", flush=True)
+@pytest.fixture(scope="module")
+def tensor():
+    return workloads.named_tensor("zipf1.2-20M")
+
+
+@pytest.mark.parametrize("layout", ["hot_steps", "nonzero_order"])
+def test_zipf20m_full_size_every_row(tensor, layout):
+    print("case full-size zipf1.2-20M, every row,", layout, flush=True)
     R = 32
-    t = workloads.named_tensor("zipf1.2-20M")
+    t = tensor
     F = workloads.random_factors(t.dims, R, seed=2)
-    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R))
+    opts = dict(max_R=R, hot_steps=1, parts_per_cu=2) if layout == "hot_steps" else dict(max_R=R)
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=opts)
     dF = gu.dev_factors(F)
     F64 = [f.astype(np.float64) for f in F]
     val64 = t.val.astype(np.float64)

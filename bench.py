@@ -189,17 +189,30 @@ def bench_batch(args, R=16, count=256):
     build_s = time.perf_counter() - t0
     F = [[torch.from_numpy(f).cuda() for f in workloads.random_factors(t.dims, R, seed=i)] for i, t in enumerate(ts)]
     outs = [[torch.empty((d, R), device="cuda") for d in t.dims] for t in ts]
-    # Partition size: measured by the autotuner unless given.
+    # Launch shape (partitions per CU, workgroup size, gathers in flight):
+    # measured by the shape autotuner unless the partition size is given.
     if args.parts_per_cu:
         capi.mttkrp_batch_autotune(hs, R, F, outs, candidates=[args.parts_per_cu], reps=1, stream=stream)
-        tuned = {"parts_per_cu": args.parts_per_cu, "source": "--parts-per-cu"}
+        info = capi.mttkrp_layout_info(hs[0])
+        tuned = {"parts_per_cu": args.parts_per_cu, "wg_threads": info["wg_threads"],
+                 "gathers_in_flight": info["gathers_in_flight"], "source": "--parts-per-cu"}
     else:
         t0 = time.perf_counter()
-        best, times = capi.mttkrp_batch_autotune(hs, R, F, outs, reps=3, stream=stream)
-        tuned = {"parts_per_cu": best, "source": "mttkrp_batch_autotune",
-                 "candidate_ms_per_pass": {str(k): round(v, 4) for k, v in times.items()},
+        best, times = capi.mttkrp_batch_autotune_shape(hs, R, F, outs, reps=3, stream=stream)
+        info = capi.mttkrp_layout_info(hs[0])
+        ms = sorted(times.values())
+        dflt = [v for (p, th, g), v in times.items()
+                if p == 8 and (th or 512) == 512 and g in (0, 2 if R == 16 else 4)]
+        tuned = {"parts_per_cu": best[0], "wg_threads": info["wg_threads"],
+                 "gathers_in_flight": info["gathers_in_flight"], "source": "mttkrp_batch_autotune_shape",
+                 "candidates": len(times),
+                 "spread_ms_per_pass": {"fastest": round(ms[0], 4), "median": round(ms[len(ms) // 2], 4),
+                                        "slowest": round(ms[-1], 4),
+                                        "default_shape": round(dflt[0], 4) if dflt else None},
+                 "candidate_ms_per_pass": {f"{p}/{th or 'def'}/{g or 'def'}": round(v, 4)
+                                           for (p, th, g), v in times.items()},
                  "tuning_s": round(time.perf_counter() - t0, 2)}
-    print(f"[bench] partition size {tuned}", file=sys.stderr, flush=True)
+    print(f"[bench] launch shape {tuned}", file=sys.stderr, flush=True)
     b = capi.mttkrp_batch_create(hs, R)
 
     def batched(st=stream):
@@ -307,7 +320,7 @@ def bench_batch(args, R=16, count=256):
         "config": {"workload": f"batch256-R16: {count} 3-mode tensors, dims U[100,5000], nnz log-U[1e3,1e6] "
                                f"(capped), uniform distinct, R={R}; one step = all modes of every tensor",
                    "total_nnz": total_nnz, "R": R},
-        "partition_size": tuned,
+        "launch_shape": tuned,
         "timing": "one step = 3 modes; both methods replayed from a HIP graph of one step",
         "plain_ms_per_step": round(ms_p, 4),
         "batched_speedup_vs_plain": round(ms_p / ms_b, 3),
@@ -419,6 +432,12 @@ def bench_paper_shapes(args, R=32):
     shapes = dict(PAPER_SHAPES)
     if not args.skip_large_shape:
         shapes.update(PAPER_SHAPE_LARGE)
+    if args.only_shapes:
+        every = {**PAPER_SHAPES, **PAPER_SHAPE_LARGE}
+        unknown = [n for n in args.only_shapes if n not in every]
+        if unknown:
+            raise SystemExit(f"unknown shape(s) {unknown}; known: {sorted(every)}")
+        shapes = {n: every[n] for n in args.only_shapes}
     rows = {}
     for name, (dims, nnz) in shapes.items():
         t0 = time.perf_counter()
@@ -642,6 +661,8 @@ def main(argv=None):
     ap.add_argument("--no-gather-ceiling", action="store_true")
     ap.add_argument("--skip-large-shape", action="store_true",
                     help="paper-shapes: leave out the 143.6M-nonzero tensor")
+    ap.add_argument("--only-shapes", nargs="+", default=None,
+                    help="paper-shapes: run only these tensors (e.g. nell1-like)")
     ap.add_argument("--serve-slots", type=int, nargs="+", default=[8, 4],
                     help="concurrent job slots of the continuous-batching server (serve-poisson)")
     ap.add_argument("--serve-jobs", type=int, default=200, help="timed jobs of serve-poisson")
@@ -870,7 +891,7 @@ def main(argv=None):
         # The second half of the metric: batched requests/s and served p50/p99
         # latency, on the batching and serving workloads, as sub-objects.
         result["batch"] = _sub(bench_batch(args), ("metric", "value", "unit", "ms_per_step", "config",
-                                                   "partition_size", "plain_ms_per_step", "batched_speedup_vs_plain",
+                                                   "launch_shape", "plain_ms_per_step", "batched_speedup_vs_plain",
                                                    "eager_launch_ms_per_step", "gflops", "hbm_pct_peak",
                                                    "als_20_sweeps", "build_s"))
         torch.cuda.empty_cache()

@@ -91,6 +91,15 @@ typedef struct {
                                   skip the global gathers.  Runs then need R = max_R (fp32, or bf16 when
                                   factor_dtype is MTTKRP_BF16); not usable in batches, the gather probe or
                                   mttkrp_run_scheme2; hot_rows and partitioner are ignored.  0 (default): off */
+    int wide_indices;          /* 1: always store 32-bit input coordinates.  0 (default): a copy whose input
+                                  dimensions are all <= 65536 stores them as uint16 (3- to 5-mode tensors,
+                                  nonzero split, no hot rows or steps; the paper's memory model counts
+                                  log2 of the dimension per index, Sec. III-C) */
+    int part_threads;          /* partition-kernel workgroup size for fp32 runs of 3-mode tensors without hot
+                                  rows or steps: 256, 512 or 1024 threads; 0 (default) = 512.  Ignored elsewhere */
+    int part_gathers;          /* nonzeros whose row gathers each lane group keeps in flight in those runs: 2
+                                  or 4; 0 (default) = 2 at R = 16, else 4.  Ignored elsewhere.  Both change
+                                  the partitioning, so results change by rounding only */
 } mttkrp_opts;
 
 enum { MTTKRP_PART_NNZ = 0, MTTKRP_PART_ROWS_LPT = 1 };
@@ -238,6 +247,9 @@ typedef struct {
     uint32_t parts_per_cu;        /* MTTKRP workgroups launched per compute unit */
     uint32_t lpt_parts;           /* scheme-1 partitions (MTTKRP_PART_ROWS_LPT), 0 for the nonzero split */
     uint32_t step_entries;        /* hot-steps copies: entries per wave step (0: nonzero-ordered copies) */
+    uint32_t idx16_modes;         /* bit n set: the copy of output mode n stores 16-bit input coordinates */
+    uint32_t gathers_in_flight;   /* nonzeros' row gathers in flight per lane group (fp32 runs at max_R;
+                                     0 for hot-steps copies) */
 } mttkrp_info;
 
 mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
@@ -275,8 +287,11 @@ typedef struct mttkrp_batch* mttkrp_batch_handle;
 
 /* layouts: host array of `count` device handles (same N, each with max_R >= R).
  * The handles must outlive the batch.  Each tensor is partitioned with its own
- * handle's parts_per_cu; opts (may be NULL) is validated only.  Allocates the
- * batch's descriptor tables and carry rows. */
+ * handle's parts_per_cu.  opts (may be NULL) sets the batch's gather precision
+ * with factor_dtype: MTTKRP_FP32 (default; mttkrp_batch_run) or MTTKRP_BF16
+ * (mttkrp_batch_run_bf16, and cpd_als_batch_iter_async on layouts built with
+ * factor_dtype MTTKRP_BF16); its other fields are validated only.  Allocates
+ * the batch's descriptor tables and carry rows. */
 mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R, const mttkrp_opts* opts,
                                   mttkrp_batch_handle* out);
 
@@ -289,11 +304,20 @@ mttkrp_status mttkrp_batch_create(const mttkrp_handle* layouts, int count, int R
 mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* const* factors, float* const* outs,
                                hipStream_t stream);
 
+/* Same for a batch created with factor_dtype MTTKRP_BF16: factors are bf16 bit
+ * patterns (uint16, I_m x R), gathered and multiplied in FP32 with FP32
+ * accumulation; each tensor's result is bitwise mttkrp_run_bf16 on its handle.
+ * MTTKRP_EINVAL on an fp32 batch (and mttkrp_batch_run on a bf16 one). */
+mttkrp_status mttkrp_batch_run_bf16(mttkrp_batch_handle b, int mode, const uint16_t* const* factors,
+                                    float* const* outs, hipStream_t stream);
+
 /* One CP-ALS sweep for every tensor of the batch, enqueued only (capturable):
  * per mode, each tensor's FP64 normal-equation kernels around one batched
  * MTTKRP launch pair.  Every tensor must have been prepared with
- * cpd_als_init(h, ..., R) (fp32 factor_dtype).  Each tensor's results are
- * bitwise those of cpd_als_iter_async on its own handle.
+ * cpd_als_init(h, ..., R), and every layout's factor_dtype must be the
+ * batch's: with MTTKRP_BF16 the MTTKRPs gather the layouts' bf16 factor copies,
+ * refreshed after each mode update by one batched cast.  Each tensor's results
+ * are bitwise those of cpd_als_iter_async on its own handle.
  *   factors: host array of count * N device pointers (updated in place)
  *   lambdas: host array of count device pointers (R doubles each)
  *   fits:    host array of count device pointers (1 double each) or NULL */
@@ -316,6 +340,31 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
 mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int R, const int* candidates,
                                     int n_candidates, const float* const* factors, float* const* outs, int reps,
                                     hipStream_t stream, int* best_ppc, float* times_ms);
+
+/* A launch shape of the partition kernel, as the shape autotuner sets it. */
+typedef struct {
+    int parts_per_cu;   /* partitions per compute unit, [1, 64] */
+    int threads;        /* opts.part_threads: 0, 256, 512 or 1024 */
+    int gathers;        /* opts.part_gathers: 0, 2 or 4 */
+} mttkrp_part_shape;
+
+/* As mttkrp_batch_autotune over launch shapes: each candidate sets
+ * parts_per_cu, part_threads and part_gathers on every layout (the shape
+ * fields apply to fp32 runs of 3-mode tensors without hot rows, and are
+ * ignored elsewhere).  The fastest stays set and is returned in *best.
+ *   candidates: n_candidates shapes, or NULL for the defaults listed by
+ *               mttkrp_batch_autotune_default_shapes(layouts[0]'s N)
+ *   times_ms:   NULL or one float per candidate */
+mttkrp_status mttkrp_batch_autotune_shape(const mttkrp_handle* layouts, int count, int R,
+                                          const mttkrp_part_shape* candidates, int n_candidates,
+                                          const float* const* factors, float* const* outs, int reps,
+                                          hipStream_t stream, mttkrp_part_shape* best, float* times_ms);
+
+/* The default candidates of mttkrp_batch_autotune_shape for N-mode tensors
+ * (parts_per_cu 1, 2, 4, 8, 16; for N = 3 each with threads 256, 512, 1024 and
+ * gathers 2, 4): written to out when it is not NULL (room for 30); returns
+ * their number. */
+int mttkrp_batch_autotune_default_shapes(int N, mttkrp_part_shape* out);
 
 /* Release a batch (not its layouts).  A batch that allocated its own device
  * memory synchronises the device first; one from mttkrp_batch_create_in

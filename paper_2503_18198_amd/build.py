@@ -20,7 +20,8 @@ OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["capi.cpp", "layout.cpp", "layout_device.hip", "mttkrp_kernels.hip", "als_kernels.hip", "probe_kernels.hip",
-           "noalloc.hip", "step_n3.hip", "step_n4.hip"] + [
+           "noalloc.hip", "step_n3.hip", "step_n4.hip", "part_tuned_256.hip", "part_tuned_512.hip",
+           "part_tuned_1024.hip"] + [
     f"part_n{n}.hip" for n in range(3, 9)
 ]
 

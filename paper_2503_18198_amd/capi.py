@@ -32,7 +32,8 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_batch_free", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
             "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
             "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes", "mttkrp_batch_create_in",
-            "mttkrp_run_noalloc", "mttkrp_noalloc_scratch_bytes", "mttkrp_lpt_partition"]
+            "mttkrp_run_noalloc", "mttkrp_noalloc_scratch_bytes", "mttkrp_lpt_partition", "mttkrp_batch_run_bf16",
+            "mttkrp_batch_autotune_shape", "mttkrp_batch_autotune_default_shapes"]
 
 
 class MttkrpError(RuntimeError):
@@ -45,7 +46,8 @@ class mttkrp_opts(ctypes.Structure):
     _fields_ = [("parts_per_cu", ctypes.c_int), ("factor_dtype", ctypes.c_int), ("max_R", ctypes.c_int),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int), ("hot_rows", ctypes.c_int),
                 ("build_on_host", ctypes.c_int), ("partitioner", ctypes.c_int), ("lpt_parts", ctypes.c_int),
-                ("hot_steps", ctypes.c_int)]
+                ("hot_steps", ctypes.c_int), ("wide_indices", ctypes.c_int), ("part_threads", ctypes.c_int),
+                ("part_gathers", ctypes.c_int)]
 
 
 class mttkrp_mode_view(ctypes.Structure):
@@ -64,7 +66,12 @@ class mttkrp_mode_view(ctypes.Structure):
 class mttkrp_info(ctypes.Structure):
     _fields_ = [("cu_count", ctypes.c_uint32), ("lds_per_workgroup", ctypes.c_uint32), ("hot_rows", ctypes.c_uint32),
                 ("wg_threads", ctypes.c_uint32), ("parts_per_cu", ctypes.c_uint32), ("lpt_parts", ctypes.c_uint32),
-                ("step_entries", ctypes.c_uint32)]
+                ("step_entries", ctypes.c_uint32), ("idx16_modes", ctypes.c_uint32),
+                ("gathers_in_flight", ctypes.c_uint32)]
+
+
+class mttkrp_part_shape(ctypes.Structure):
+    _fields_ = [("parts_per_cu", ctypes.c_int), ("threads", ctypes.c_int), ("gathers", ctypes.c_int)]
 
 
 class mttkrp_plan(ctypes.Structure):
@@ -106,11 +113,18 @@ def _load():
     lib.mttkrp_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(mttkrp_opts),
                                         ctypes.POINTER(vp)]
     lib.mttkrp_batch_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.mttkrp_batch_run_bf16.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.cpd_als_iter_async.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.c_int, vp, vp]
     lib.cpd_als_status.argtypes = [vp, vp]
     lib.mttkrp_batch_autotune.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                           ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
+    lib.mttkrp_batch_autotune_shape.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(mttkrp_part_shape), ctypes.c_int, ctypes.POINTER(vp),
+                                                ctypes.POINTER(vp), ctypes.c_int, vp,
+                                                ctypes.POINTER(mttkrp_part_shape), ctypes.POINTER(ctypes.c_float)]
+    lib.mttkrp_batch_autotune_default_shapes.argtypes = [ctypes.c_int, ctypes.POINTER(mttkrp_part_shape)]
+    lib.mttkrp_batch_autotune_default_shapes.restype = ctypes.c_int
     lib.mttkrp_gather_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     lib.cpd_als_batch_iter_async.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.mttkrp_batch_free.argtypes = [vp]
@@ -130,7 +144,8 @@ def _load():
                  "mttkrp_batch_run", "cpd_als_iter_async", "cpd_als_status", "cpd_als_batch_iter_async",
                  "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
                  "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes",
-                 "mttkrp_batch_create_in", "mttkrp_run_noalloc", "mttkrp_lpt_partition"):
+                 "mttkrp_batch_create_in", "mttkrp_run_noalloc", "mttkrp_lpt_partition", "mttkrp_batch_run_bf16",
+                 "mttkrp_batch_autotune_shape"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -495,11 +510,7 @@ def mttkrp_batch_create_in(layouts, R: int, dev_mem, opts=None, stream=None) -> 
     return Batch(b.value, layouts, R, dev_mem=dev_mem)
 
 
-def mttkrp_batch_autotune(layouts, R: int, factors, outs, candidates=None, reps: int = 3, stream=None):
-    """Time the batched all-mode MTTKRP for each candidate parts_per_cu, leave
-    the fastest set on the layouts and return ``(best, {candidate: ms})``.
-    factors: per tensor, N fp32 device tensors; outs: per tensor, N outputs
-    (tensor t's mode-n output of shape (I_n, R))."""
+def _autotune_args(layouts, R, factors, outs):
     count = len(layouts)
     N = len(layouts[0].dims)
     if len(factors) != count or len(outs) != count:
@@ -513,6 +524,15 @@ def mttkrp_batch_autotune(layouts, R: int, factors, outs, candidates=None, reps:
     arr = (ctypes.c_void_p * count)(*[h.ptr for h in layouts])
     fac = (ctypes.c_void_p * (count * N))(*[int(f.data_ptr()) for fs in factors for f in fs])
     out = (ctypes.c_void_p * (count * N))(*[int(o.data_ptr()) for os_ in outs for o in os_])
+    return count, arr, fac, out
+
+
+def mttkrp_batch_autotune(layouts, R: int, factors, outs, candidates=None, reps: int = 3, stream=None):
+    """Time the batched all-mode MTTKRP for each candidate parts_per_cu, leave
+    the fastest set on the layouts and return ``(best, {candidate: ms})``.
+    factors: per tensor, N fp32 device tensors; outs: per tensor, N outputs
+    (tensor t's mode-n output of shape (I_n, R))."""
+    count, arr, fac, out = _autotune_args(layouts, R, factors, outs)
     cands = list(candidates) if candidates is not None else [1, 2, 4, 8, 16]
     carr = (ctypes.c_int * len(cands))(*cands)
     times = (ctypes.c_float * len(cands))()
@@ -520,6 +540,30 @@ def mttkrp_batch_autotune(layouts, R: int, factors, outs, candidates=None, reps:
     _check(_lib.mttkrp_batch_autotune(arr, count, int(R), carr, len(cands), fac, out, int(reps),
                                       ctypes.c_void_p(_stream(stream)), ctypes.byref(best), times))
     return int(best.value), {c: float(times[i]) for i, c in enumerate(cands)}
+
+
+def mttkrp_batch_autotune_default_shapes(N: int):
+    """The shape autotuner's default candidates for N-mode tensors, as
+    (parts_per_cu, threads, gathers) tuples."""
+    n = _lib.mttkrp_batch_autotune_default_shapes(int(N), None)
+    arr = (mttkrp_part_shape * max(n, 1))()
+    _lib.mttkrp_batch_autotune_default_shapes(int(N), arr)
+    return [(arr[i].parts_per_cu, arr[i].threads, arr[i].gathers) for i in range(n)]
+
+
+def mttkrp_batch_autotune_shape(layouts, R: int, factors, outs, candidates=None, reps: int = 3, stream=None):
+    """Time the batched all-mode MTTKRP for each candidate launch shape
+    (parts_per_cu, threads, gathers), leave the fastest set on the layouts and
+    return ``(best, {shape: ms})``; candidates None = the library's defaults."""
+    count, arr, fac, out = _autotune_args(layouts, R, factors, outs)
+    cands = ([tuple(c) for c in candidates] if candidates is not None
+             else mttkrp_batch_autotune_default_shapes(len(layouts[0].dims)))
+    carr = (mttkrp_part_shape * len(cands))(*[mttkrp_part_shape(*c) for c in cands])
+    times = (ctypes.c_float * len(cands))()
+    best = mttkrp_part_shape()
+    _check(_lib.mttkrp_batch_autotune_shape(arr, count, int(R), carr, len(cands), fac, out, int(reps),
+                                            ctypes.c_void_p(_stream(stream)), ctypes.byref(best), times))
+    return (best.parts_per_cu, best.threads, best.gathers), {c: float(times[i]) for i, c in enumerate(cands)}
 
 
 def mttkrp_batch_run(b: Batch, mode: int, factors, outs, stream=None):
@@ -541,6 +585,28 @@ def mttkrp_batch_run(b: Batch, mode: int, factors, outs, stream=None):
             raise MttkrpError(MTTKRP_EINVAL, f"output of tensor {t} must be ({h.dims[mode]}, {b.R}) float32")
         op[t] = int(o.data_ptr())
     _check(_lib.mttkrp_batch_run(ctypes.c_void_p(b.ptr), int(mode), fp, op, ctypes.c_void_p(_stream(stream))))
+
+
+def mttkrp_batch_run_bf16(b: Batch, mode: int, factors, outs, stream=None):
+    """As mttkrp_batch_run on a batch created with factor_dtype MTTKRP_BF16:
+    factors are bfloat16 device tensors."""
+    import torch
+    N = len(b.layouts[0].dims)
+    if len(factors) != len(b.layouts) or len(outs) != len(b.layouts):
+        raise MttkrpError(MTTKRP_EINVAL, "need factors and outputs for every tensor of the batch")
+    if not 0 <= int(mode) < N:
+        raise MttkrpError(MTTKRP_EINVAL, "mode out of range")
+    fp = (ctypes.c_void_p * (len(b.layouts) * N))()
+    op = (ctypes.c_void_p * len(b.layouts))()
+    for t, (h, fs, o) in enumerate(zip(b.layouts, factors, outs)):
+        for m in range(N):
+            if m != mode:
+                _check_factor(fs[m], h.dims[m], b.R, "bf16", f"factor {m} of tensor {t}")
+                fp[t * N + m] = int(fs[m].data_ptr())
+        if o.dtype != torch.float32 or not o.is_cuda or not o.is_contiguous() or tuple(o.shape) != (h.dims[mode], b.R):
+            raise MttkrpError(MTTKRP_EINVAL, f"output of tensor {t} must be ({h.dims[mode]}, {b.R}) float32")
+        op[t] = int(o.data_ptr())
+    _check(_lib.mttkrp_batch_run_bf16(ctypes.c_void_p(b.ptr), int(mode), fp, op, ctypes.c_void_p(_stream(stream))))
 
 
 def mttkrp_batch_free(b: Batch):

@@ -628,6 +628,39 @@ hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w
     return als_gram_jobs(j, nullptr, nullptr, 0, 1, R, s);
 }
 
+// Round-to-nearest-even bf16 copies of many tensors' factors: work item
+// (job, block) casts rows [block * rpb, min((block + 1) * rpb, I)) of job's A
+// into its A16, with the same rounding as cast_bf16_kernel.
+__global__ __launch_bounds__(kWG) void cast_bf16_jobs_kernel(const DenseJob* __restrict__ jobs,
+                                                             const uint2* __restrict__ work, uint32_t nwork, int R)
+{
+    for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const uint2 wk = work[w];
+        const DenseJob& j = jobs[wk.x];
+        const uint64_t r0 = (uint64_t)wk.y * j.rpb;
+        const uint64_t r1 = min(r0 + j.rpb, (uint64_t)j.I);
+        if (r0 >= r1) continue;
+        const uint64_t n = (r1 - r0) * (uint64_t)R;
+        const float* A = j.A + r0 * R;
+        uint16_t* out = j.A16 + r0 * R;
+        for (uint64_t i = threadIdx.x; i < n; i += kWG) {
+            const uint32_t b = __float_as_uint(A[i]);
+            uint16_t h;
+            if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) h = (uint16_t)((b >> 16) | 0x0040u);
+            else h = (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+            out[i] = h;
+        }
+    }
+}
+
+hipError_t cast_bf16_jobs(const DenseJob* jobs, const uint2* work, uint32_t nwork, int R, hipStream_t s)
+{
+    if (nwork == 0) return hipSuccess;
+    const uint32_t grid = nwork < 4096u ? nwork : 4096u;
+    hipLaunchKernelGGL(cast_bf16_jobs_kernel, dim3(grid), dim3(kWG), 0, s, jobs, work, nwork, R);
+    return hipGetLastError();
+}
+
 hipError_t cast_bf16(const float* A, uint64_t n, uint16_t* out, hipStream_t s)
 {
     uint64_t blocks = (n + kWG - 1) / kWG;

@@ -96,10 +96,25 @@ uint32_t hot_rows_for(int N, int maxR, uint32_t lds_limit, int requested)
     return k;
 }
 
-uint64_t copies_bytes(const uint32_t* dims, int N, uint64_t nnz)
+// Whether the copy of output mode n stores 16-bit input coordinates: every
+// input dimension <= 65536, at most kMaxIn16 inputs, nonzero-ordered copies
+// without hot rows, and the caller did not ask for 32-bit coordinates.
+bool copy_idx16(const uint32_t* dims, int N, int n, const mttkrp_opts& o, uint32_t nhot)
+{
+    if (o.wide_indices || o.hot_steps || nhot || o.partitioner != MTTKRP_PART_NNZ || N - 1 > mk::kMaxIn16) return false;
+    for (int m = 0; m < N; ++m)
+        if (m != n && dims[m] > 65536u) return false;
+    return true;
+}
+
+uint64_t copies_bytes(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts* o = nullptr, uint32_t nhot = 0)
 {
     uint64_t b = 0;
-    for (int n = 0; n < N; ++n) b += mk::mode_device_bytes(nnz, N, dims[n]) + (uint64_t)(N + 4) * kAlign;
+    const uint64_t pad = (nnz + 31) / 32 * 32;
+    for (int n = 0; n < N; ++n) {
+        b += mk::mode_device_bytes(nnz, N, dims[n]) + (uint64_t)(N + 4) * kAlign;
+        if (o && copy_idx16(dims, N, n, *o, nhot)) b -= pad * 2ull * (uint64_t)(N - 1);   // half-width coordinates
+    }
     return b;
 }
 
@@ -149,6 +164,9 @@ void mttkrp_opts_default(mttkrp_opts* o)
     o->partitioner = MTTKRP_PART_NNZ;
     o->lpt_parts = 0;
     o->hot_steps = 0;
+    o->wide_indices = 0;
+    o->part_threads = 0;
+    o->part_gathers = 0;
 }
 
 const char* mttkrp_last_error(void) { return g_err.c_str(); }
@@ -166,6 +184,10 @@ static mttkrp_status check_opts(const mttkrp_opts* in, mttkrp_opts* o)
         return fail(MTTKRP_EINVAL, "partitioner must be MTTKRP_PART_NNZ or MTTKRP_PART_ROWS_LPT");
     if (o->lpt_parts < 0 || o->lpt_parts > (1 << 20)) return fail(MTTKRP_EINVAL, "lpt_parts must be in [0, 2^20]");
     if (o->hot_steps != 0 && o->hot_steps != 1) return fail(MTTKRP_EINVAL, "hot_steps must be 0 or 1");
+    if (o->part_threads < 0 || o->part_gathers < 0 ||
+        ((o->part_threads || o->part_gathers) &&
+         !mk::tuned_shape_supported(o->part_threads ? o->part_threads : 512, o->part_gathers ? o->part_gathers : 4)))
+        return fail(MTTKRP_EINVAL, "part_threads must be 0, 256, 512 or 1024 and part_gathers 0, 2 or 4");
     if (o->hot_steps) {
         o->partitioner = MTTKRP_PART_NNZ;   // step copies carry their own hot rows and partitions
         o->hot_rows = 0;
@@ -215,9 +237,9 @@ static uint64_t step_copies_bytes(const uint32_t* dims, int N, uint64_t nnz, con
     return b;
 }
 
-static uint64_t layout_copies_bytes(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts& o)
+static uint64_t layout_copies_bytes(const uint32_t* dims, int N, uint64_t nnz, const mttkrp_opts& o, uint32_t nhot)
 {
-    return o.hot_steps ? step_copies_bytes(dims, N, nnz, o) : copies_bytes(dims, N, nnz);
+    return o.hot_steps ? step_copies_bytes(dims, N, nnz, o) : copies_bytes(dims, N, nnz, &o, nhot);
 }
 
 static uint32_t layout_hot_rows(int N, const mttkrp_opts& o, uint32_t lds_limit)
@@ -236,8 +258,9 @@ mttkrp_status mttkrp_footprint(const uint32_t* dims, int N, uint64_t nnz, const 
     mttkrp_opts o;
     mttkrp_status s = check_opts(opts, &o);
     if (s) return s;
-    *bytes = layout_copies_bytes(dims, N, nnz, o) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
-             hot_bytes(N, layout_hot_rows(N, o, kAssumedLds)) + lpt_bytes(o, N, 0);
+    const uint32_t nhot_fp = layout_hot_rows(N, o, kAssumedLds);
+    *bytes = layout_copies_bytes(dims, N, nnz, o, nhot_fp) + plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
+             hot_bytes(N, nhot_fp) + lpt_bytes(o, N, 0);
     return MTTKRP_OK;
 }
 
@@ -264,9 +287,10 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     // Admission first, before any device call (the hot tables are sized for the
     // largest LDS, an upper bound).
     {
-        const uint64_t bound = layout_copies_bytes(dims, N, nnz, o) +
+        const uint32_t nhot_b = layout_hot_rows(N, o, kAssumedLds);
+        const uint64_t bound = layout_copies_bytes(dims, N, nnz, o, nhot_b) +
                                plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total +
-                               hot_bytes(N, layout_hot_rows(N, o, kAssumedLds)) + lpt_bytes(o, N, 0);
+                               hot_bytes(N, nhot_b) + lpt_bytes(o, N, 0);
         if (!o.host_only && o.hbm_budget_bytes && bound > o.hbm_budget_bytes)
             return fail(MTTKRP_ENOMEM, "footprint " + std::to_string(bound) + " B exceeds the budget of " +
                                            std::to_string(o.hbm_budget_bytes) + " B");
@@ -290,7 +314,7 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     }
     const bool lpt = o.partitioner == MTTKRP_PART_ROWS_LPT;
     const uint32_t kappa = lpt_kappa(o, cus_here);
-    const uint64_t need = layout_copies_bytes(dims, N, nnz, o) +
+    const uint64_t need = layout_copies_bytes(dims, N, nnz, o, nhot) +
                           plan_workspace(dims, N, nnz, o.max_R, o.factor_dtype).total + hot_bytes(N, nhot) +
                           lpt_bytes(o, N, cus_here);
     const uint32_t step_P = o.hot_steps ? mk::step_entries(o.max_R, o.factor_dtype) : 0u;
@@ -410,7 +434,9 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
         const uint64_t nnz_pad = (nnz + 31) / 32 * 32;
         std::vector<mk::DeviceModeSlots> slots(N);
         for (int n = 0; n < N; ++n) {
-            for (int j = 0; j < N - 1; ++j) slots[n].idx[j] = static_cast<uint32_t*>(take(nnz_pad * 4));
+            slots[n].idx16 = copy_idx16(dims, N, n, o, nhot);
+            for (int j = 0; j < N - 1; ++j)
+                slots[n].idx[j] = static_cast<uint32_t*>(take(nnz_pad * (slots[n].idx16 ? 2 : 4)));
             slots[n].val = static_cast<float*>(take(nnz_pad * 4));
             slots[n].winfo = static_cast<uint2*>(take(nnz_pad / 32 * 8));
             slots[n].rows = static_cast<uint32_t*>(take((uint64_t)dims[n] * 4));
@@ -470,10 +496,20 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
                 if (bytes && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
                 return dst;
             };
+            d.idx16 = copy_idx16(dims, N, n, o, nhot);
+            std::vector<uint16_t> narrow;
             for (int j = 0; j < N - 1; ++j) {
                 d.in_modes[j] = hm.in_modes[j];
                 d.in_dims[j] = dims[hm.in_modes[j]];
-                d.idx[j] = static_cast<const uint32_t*>(up(hm.idx[j].data(), hm.nnz_pad * 4));
+                if (d.idx16) {
+                    // 16-bit coordinates; the copy waits for this upload before
+                    // the buffer is refilled for the next input
+                    narrow.assign(hm.idx[j].begin(), hm.idx[j].begin() + hm.nnz_pad);
+                    d.idx[j] = static_cast<const uint32_t*>(up(narrow.data(), hm.nnz_pad * 2));
+                    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+                } else {
+                    d.idx[j] = static_cast<const uint32_t*>(up(hm.idx[j].data(), hm.nnz_pad * 4));
+                }
             }
             d.val = static_cast<const float*>(up(hm.val.data(), hm.nnz_pad * 4));
             d.winfo = static_cast<const uint2*>(up(hm.winfo.data(), hm.winfo.size() * 4));
@@ -542,6 +578,34 @@ mttkrp_status mttkrp_layout_build_in(const uint32_t* coo_idx, const float* vals,
 
 uint64_t mttkrp_layout_bytes(mttkrp_handle h) { return h ? h->dbytes : 0; }
 
+// The partition kernel's shape on this handle for n_in inputs, rank R and
+// dtype: the handle's part_threads / part_gathers where a tuned shape applies
+// (3-mode tensors, fp32 factors, no hot rows), else the default.
+static void part_shape(const mttkrp_layout* h, int n_in, int R, int dtype, int* threads, int* gathers)
+{
+    mk::default_part_shape(n_in, R, dtype, threads, gathers);
+    if (n_in == 2 && dtype == MTTKRP_FP32 && h->nhot == 0 && !h->opts.hot_steps) {
+        if (h->opts.part_threads) *threads = h->opts.part_threads;
+        if (h->opts.part_gathers) *gathers = h->opts.part_gathers;
+    }
+}
+
+// Nonzero partitions of one mode copy of nnz nonzeros on this handle, with
+// its launch shape (the tuned fields set only where they differ from the default).
+static mk::Geometry plan_nnz(const mttkrp_layout* h, uint64_t nnz, int n_in, int R, int dtype)
+{
+    int th = 0, gu = 0, dth = 0, dgu = 0;
+    part_shape(h, n_in, R, dtype, &th, &gu);
+    mk::default_part_shape(n_in, R, dtype, &dth, &dgu);
+    mk::Geometry g =
+        mk::plan_geometry(nnz, n_in, R, dtype, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz), kMaxChain, th);
+    if (th != dth || gu != dgu) {
+        g.threads = th;
+        g.gathers = gu;
+    }
+    return g;
+}
+
 mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info)
 {
     g_err.clear();
@@ -549,10 +613,16 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info)
     info->cu_count = (uint32_t)h->cu_count;
     info->lds_per_workgroup = h->lds_limit;
     info->hot_rows = h->nhot;
-    info->wg_threads = (uint32_t)(h->opts.hot_steps ? mk::step_wg_threads() : mk::partition_wg_threads(h->N - 1));
+    int th = 0, gu = 0;
+    part_shape(h, h->N - 1, h->opts.max_R, MTTKRP_FP32, &th, &gu);
+    info->wg_threads = (uint32_t)(h->opts.hot_steps ? mk::step_wg_threads() : th);
+    info->gathers_in_flight = h->opts.hot_steps ? 0u : (uint32_t)gu;
     info->parts_per_cu = (uint32_t)h->opts.parts_per_cu;
     info->lpt_parts = h->opts.partitioner == MTTKRP_PART_ROWS_LPT ? lpt_kappa(h->opts, h->cu_count) : 0u;
     info->step_entries = h->opts.hot_steps ? mk::step_entries(h->opts.max_R, h->opts.factor_dtype) : 0u;
+    info->idx16_modes = 0u;
+    for (int n = 0; n < h->N; ++n)
+        if (h->host_only ? copy_idx16(h->dims, h->N, n, h->opts, h->nhot) : h->dev[n].idx16) info->idx16_modes |= 1u << n;
     return MTTKRP_OK;
 }
 
@@ -669,8 +739,7 @@ static mttkrp_status plan_for(mttkrp_handle h, const mk::DevMode& d, int R, int 
                                     max_parts_for(h->nnz), kMaxChain, (uint32_t)h->cu_count);
         return MTTKRP_OK;
     }
-    *g = mk::plan_geometry(d.nnz, d.n_in, R, dtype, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz),
-                           kMaxChain);
+    *g = plan_nnz(h, d.nnz, d.n_in, R, dtype);
     return MTTKRP_OK;
 }
 
@@ -759,8 +828,7 @@ mttkrp_status mttkrp_run_scheme2(mttkrp_handle h, int mode, const float* const* 
         fac[j] = factors[d.in_modes[j]];
         hot[j] = h->hot_rows[d.in_modes[j]];
     }
-    const mk::Geometry g =
-        mk::plan_geometry(d.nnz, d.n_in, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz), kMaxChain);
+    const mk::Geometry g = plan_nnz(h, d.nnz, d.n_in, R, MTTKRP_FP32);
     hipError_t e = mk::launch_mttkrp(d, R, MTTKRP_FP32, fac, hot, h->nhot, out, h->carry, g, stream, true,
                                      h->dims[mode]);
     if (e != hipSuccess) return hip_fail(e, "MTTKRP (scheme 2) launch");
@@ -923,7 +991,7 @@ mttkrp_status cpd_als_status(mttkrp_handle h, hipStream_t stream)
     mttkrp_status s = read_flag(h, stream);
     if (s == MTTKRP_ENOTSPD) {
         // clear the sticky flag for the next sweeps
-        mk::als_hadamard(h->als.grams, h->N, -1, h->als_R ? h->als_R : 16, h->als.V, h->als.scal + 1, 1, stream);
+        (void)mk::als_hadamard(h->als.grams, h->N, -1, h->als_R ? h->als_R : 16, h->als.V, h->als.scal + 1, 1, stream);
         (void)hipStreamSynchronize(stream);
     }
     return s;
@@ -936,6 +1004,7 @@ mttkrp_status cpd_als_status(mttkrp_handle h, hipStream_t stream)
 
 struct mttkrp_batch {
     int count = 0, N = 0, R = 0;
+    int dtype = MTTKRP_FP32;                              // gather precision of the batched MTTKRP
     std::vector<mttkrp_handle> hs;
     void* dmem = nullptr;
     bool owns_mem = true;                                 // false: dmem is the caller's (mttkrp_batch_create_in)
@@ -949,6 +1018,7 @@ struct mttkrp_batch {
     uint32_t npart_work[MTTKRP_MAX_MODES] = {};
     uint32_t nfix_work[MTTKRP_MAX_MODES] = {};
     uint32_t grid_part = 0, grid_fix = 0;
+    int threads = 0, gathers = 0;                         // tuned partition-kernel shape (0: the default)
     std::vector<const void*> last_ptrs[MTTKRP_MAX_MODES]; // pointers of the uploaded descriptors
     mk::InvJob* inv_jobs = nullptr;                       // device: every tensor's normal-equation inverse job
     mk::DenseJob* dense_jobs[MTTKRP_MAX_MODES + 1] = {};  // device: per mode (and [N]: fit) one job per tensor
@@ -1011,6 +1081,7 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
     b->count = count;
     b->N = N;
     b->R = R;
+    b->dtype = o.factor_dtype;
     b->hs.assign(layouts, layouts + count);
     (void)total_nnz;
     const int cus = layouts[0]->cu_count;
@@ -1021,9 +1092,18 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
     for (int n = 0; n < N; ++n)
         for (int t = 0; t < count; ++t) {
             const mttkrp_handle h = b->hs[t];
-            b->geo[n][t] =
-                mk::plan_geometry(h->nnz, N - 1, R, MTTKRP_FP32, h->opts.parts_per_cu * h->cu_count, max_parts_for(h->nnz), kMaxChain);
+            b->geo[n][t] = plan_nnz(h, h->nnz, N - 1, R, b->dtype);
             max_parts[t] = std::max(max_parts[t], b->geo[n][t].nparts);
+        }
+    // One launch runs every tensor: they must share the partition kernel's shape.
+    b->threads = b->geo[0][0].threads;
+    b->gathers = b->geo[0][0].gathers;
+    for (int t = 1; t < count; ++t)
+        if (b->geo[0][t].threads != b->threads || b->geo[0][t].gathers != b->gathers) {
+            delete b;
+            return fail(MTTKRP_EINVAL, "layout " + std::to_string(t) +
+                                           " has another part_threads / part_gathers than layout 0; the layouts "
+                                           "of a batch share one launch shape");
         }
     // Work lists (largest tensors first, which balances the resident grid).
     std::vector<int> order(count);
@@ -1040,6 +1120,23 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
             const uint32_t nb = mk::fill_fix_desc(scratch_desc.data(), b->hs[t]->dev[n], g, nullptr, nullptr, R);
             for (uint32_t k = 0; k < nb; ++k) fw[n].push_back(make_uint2((uint32_t)t, k));
         }
+    // Sizes are planned for the larger of the fp32 and bf16 geometries, so
+    // mttkrp_batch_bytes (which has no dtype) covers batches of either.
+    std::vector<uint64_t> pw_cap(N);
+    for (int n = 0; n < N; ++n) pw_cap[n] = pw[n].size();
+    {
+        const int other = b->dtype == MTTKRP_FP32 ? MTTKRP_BF16 : MTTKRP_FP32;
+        for (int n = 0; n < N; ++n) {
+            uint64_t items = 0;
+            for (int t = 0; t < count; ++t) {
+                const mttkrp_handle h = b->hs[t];
+                const mk::Geometry g2 = plan_nnz(h, h->nnz, N - 1, R, other);
+                items += h->nnz ? g2.nparts : 0;
+                max_parts[t] = std::max(max_parts[t], g2.nparts);
+            }
+            pw_cap[n] = std::max<uint64_t>(pw_cap[n], items);
+        }
+    }
     uint64_t carry_floats = 0;
     b->carry_off.resize(count);
     for (int t = 0; t < count; ++t) {
@@ -1058,7 +1155,7 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
                     (uint64_t)(N + 1) * align_up((uint64_t)count * sizeof(mk::DenseJob));
     for (int n = 0; n < N; ++n) need += align_up(dw[n].size() * 8 + 8);
     for (int n = 0; n < N; ++n)
-        need += align_up((uint64_t)count * pdb) + align_up((uint64_t)count * fdb) + align_up(pw[n].size() * 8 + 8) +
+        need += align_up((uint64_t)count * pdb) + align_up((uint64_t)count * fdb) + align_up(pw_cap[n] * 8 + 8) +
                 align_up(fw[n].size() * 8 + 8);
     if (bytes_only) {
         delete b;
@@ -1109,7 +1206,7 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         b->part_desc[n] = take((uint64_t)count * pdb);
         b->fix_desc[n] = take((uint64_t)count * fdb);
-        b->part_work[n] = reinterpret_cast<uint2*>(take(pw[n].size() * 8 + 8));
+        b->part_work[n] = reinterpret_cast<uint2*>(take(pw_cap[n] * 8 + 8));
         b->fix_work[n] = reinterpret_cast<uint2*>(take(fw[n].size() * 8 + 8));
         b->npart_work[n] = (uint32_t)pw[n].size();
         b->nfix_work[n] = (uint32_t)fw[n].size();
@@ -1126,7 +1223,7 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
         mttkrp_batch_free(b);
         return s2;
     }
-    b->grid_part = (uint32_t)cus * (uint32_t)std::max(1, 1024 / mk::partition_wg_threads(N - 1));
+    b->grid_part = (uint32_t)cus * (uint32_t)std::max(1, 1024 / (b->threads ? b->threads : mk::partition_wg_threads(N - 1)));
     b->grid_fix = (uint32_t)cus * 8u;
     *out = b;
     return MTTKRP_OK;
@@ -1157,11 +1254,15 @@ mttkrp_status mttkrp_batch_create_in(const mttkrp_handle* layouts, int count, in
     return batch_impl(layouts, count, R, opts, dev_mem, dev_bytes, stream, false, nullptr, out);
 }
 
-mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* const* factors, float* const* outs,
-                               hipStream_t stream)
+}  // extern "C"
+
+static mttkrp_status batch_run_impl(mttkrp_batch_handle b, int mode, const void* const* factors, int dtype,
+                                    float* const* outs, hipStream_t stream)
 {
-    g_err.clear();
     if (!b) return fail(MTTKRP_EINVAL, "NULL batch");
+    if (dtype != b->dtype)
+        return fail(MTTKRP_EINVAL, std::string("this batch gathers ") + (b->dtype == MTTKRP_FP32 ? "fp32" : "bf16") +
+                                       " factors (its factor_dtype at creation)");
     if (mode < 0 || mode >= b->N) return fail(MTTKRP_EINVAL, "mode out of range");
     if (!factors || !outs) return fail(MTTKRP_EINVAL, "NULL factors or outs");
     const int N = b->N, R = b->R;
@@ -1170,7 +1271,7 @@ mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* con
     ptrs.reserve((size_t)b->count * (N + 1));
     for (int t = 0; t < b->count; ++t) {
         for (int m = 0; m < N; ++m) {
-            const float* f = factors[(size_t)t * N + m];
+            const void* f = factors[(size_t)t * N + m];
             if (m != mode && (!f || reinterpret_cast<uintptr_t>(f) % 16))
                 return fail(MTTKRP_EINVAL, "factor " + std::to_string(m) + " of tensor " + std::to_string(t) +
                                                " is NULL or not 16-byte aligned");
@@ -1190,7 +1291,7 @@ mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* con
             const void* fac[mk::kMaxIn];
             for (int j = 0; j < d.n_in; ++j) fac[j] = factors[(size_t)t * N + d.in_modes[j]];
             float* carry = b->carry + b->carry_off[t];
-            mk::fill_part_desc(pd.data() + (size_t)t * pdb, d, R, MTTKRP_FP32, fac, outs[t], carry, g.gsz);
+            mk::fill_part_desc(pd.data() + (size_t)t * pdb, d, R, b->dtype, fac, outs[t], carry, g.gsz);
             mk::fill_fix_desc(fd.data() + (size_t)t * fdb, d, g, carry, outs[t], R);
         }
         // Stream-ordered after the launches that read the old tables; the host
@@ -1202,8 +1303,8 @@ mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* con
         b->last_ptrs[mode] = std::move(ptrs);
     }
     const uint32_t gp = std::min(b->grid_part, std::max<uint32_t>(b->npart_work[mode], 1));
-    e = mk::launch_batch_part(N - 1, R, MTTKRP_FP32, b->part_desc[mode], b->part_work[mode], b->npart_work[mode], gp,
-                              stream);
+    e = mk::launch_batch_part(N - 1, R, b->dtype, b->threads, b->gathers, b->part_desc[mode], b->part_work[mode],
+                              b->npart_work[mode], gp, stream);
     if (e == hipSuccess) {
         const uint32_t gf = std::min(b->grid_fix, std::max<uint32_t>(b->nfix_work[mode], 1));
         e = mk::launch_batch_fixup(b->fix_desc[mode], b->fix_work[mode], b->nfix_work[mode], gf, stream);
@@ -1212,29 +1313,78 @@ mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* con
     return MTTKRP_OK;
 }
 
-mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int R, const int* candidates,
-                                    int n_candidates, const float* const* factors, float* const* outs, int reps,
-                                    hipStream_t stream, int* best_ppc, float* times_ms)
+extern "C" {
+
+mttkrp_status mttkrp_batch_run(mttkrp_batch_handle b, int mode, const float* const* factors, float* const* outs,
+                               hipStream_t stream)
 {
     g_err.clear();
-    static const int kDefault[] = {1, 2, 4, 8, 16};
-    if (!best_ppc) return fail(MTTKRP_EINVAL, "NULL best_ppc");
-    if (!layouts || count <= 0 || !factors || !outs) return fail(MTTKRP_EINVAL, "NULL layouts, factors or outs");
-    if (!candidates) {
-        candidates = kDefault;
-        n_candidates = 5;
+    return batch_run_impl(b, mode, reinterpret_cast<const void* const*>(factors), MTTKRP_FP32, outs, stream);
+}
+
+mttkrp_status mttkrp_batch_run_bf16(mttkrp_batch_handle b, int mode, const uint16_t* const* factors,
+                                    float* const* outs, hipStream_t stream)
+{
+    g_err.clear();
+    return batch_run_impl(b, mode, reinterpret_cast<const void* const*>(factors), MTTKRP_BF16, outs, stream);
+}
+
+}  // extern "C"
+
+// The autotuner's default candidates for N-mode tensors: parts_per_cu 1 to
+// 16, and for 3-mode tensors every tuned workgroup size and gathers in flight.
+static std::vector<mttkrp_part_shape> default_shapes(int N)
+{
+    std::vector<mttkrp_part_shape> c;
+    for (int ppc : {1, 2, 4, 8, 16}) {
+        if (N != 3) {
+            c.push_back({ppc, 0, 0});
+            continue;
+        }
+        for (int th : {256, 512, 1024})
+            for (int gu : {2, 4}) c.push_back({ppc, th, gu});
     }
-    if (n_candidates <= 0) return fail(MTTKRP_EINVAL, "need at least one candidate");
-    for (int i = 0; i < n_candidates; ++i)
-        if (candidates[i] < 1 || candidates[i] > 64) return fail(MTTKRP_EINVAL, "candidates must be in [1, 64]");
+    return c;
+}
+
+// The autotuner behind mttkrp_batch_autotune (set_shape false: candidates
+// change parts_per_cu only) and mttkrp_batch_autotune_shape.  Each candidate
+// is set on every layout, a batch is built and `reps` all-mode passes are
+// timed after a warm-up pass; the fastest candidate stays set.
+static mttkrp_status autotune_impl(const mttkrp_handle* layouts, int count, int R,
+                                   const std::vector<mttkrp_part_shape>& cands, bool set_shape,
+                                   const float* const* factors, float* const* outs, int reps, hipStream_t stream,
+                                   int* best_out, float* times_ms)
+{
+    if (!layouts || count <= 0 || !factors || !outs) return fail(MTTKRP_EINVAL, "NULL layouts, factors or outs");
+    if (cands.empty()) return fail(MTTKRP_EINVAL, "need at least one candidate");
+    for (const mttkrp_part_shape& c : cands) {
+        if (c.parts_per_cu < 1 || c.parts_per_cu > 64) return fail(MTTKRP_EINVAL, "parts_per_cu must be in [1, 64]");
+        if (set_shape && (c.threads < 0 || c.gathers < 0 ||
+                          ((c.threads || c.gathers) &&
+                           !mk::tuned_shape_supported(c.threads ? c.threads : 512, c.gathers ? c.gathers : 4))))
+            return fail(MTTKRP_EINVAL, "threads must be 0, 256, 512 or 1024 and gathers 0, 2 or 4");
+    }
     if (reps < 1) return fail(MTTKRP_EINVAL, "reps must be >= 1");
     for (int t = 0; t < count; ++t)
         if (!layouts[t]) return fail(MTTKRP_EINVAL, "layout " + std::to_string(t) + " is NULL");
     const int N = layouts[0]->N;
-    std::vector<int> old(count);
-    for (int t = 0; t < count; ++t) old[t] = layouts[t]->opts.parts_per_cu;
+    std::vector<mttkrp_part_shape> old(count);
+    for (int t = 0; t < count; ++t)
+        old[t] = {layouts[t]->opts.parts_per_cu, layouts[t]->opts.part_threads, layouts[t]->opts.part_gathers};
+    auto apply = [&](int t, const mttkrp_part_shape& c) {
+        layouts[t]->opts.parts_per_cu = c.parts_per_cu;
+        if (set_shape) {
+            layouts[t]->opts.part_threads = c.threads;
+            layouts[t]->opts.part_gathers = c.gathers;
+        }
+    };
     auto restore = [&]() {
-        for (int t = 0; t < count; ++t) layouts[t]->opts.parts_per_cu = old[t];
+        for (int t = 0; t < count; ++t) {
+            layouts[t]->opts.parts_per_cu = old[t].parts_per_cu;
+            layouts[t]->opts.part_threads = old[t].threads;
+            layouts[t]->opts.part_gathers = old[t].gathers;
+        }
     };
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipError_t e = hipEventCreate(&ev[0]);
@@ -1247,8 +1397,8 @@ mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int
     int best = -1;
     float best_ms = 0.0f;
     mttkrp_status st = MTTKRP_OK;
-    for (int i = 0; i < n_candidates && st == MTTKRP_OK; ++i) {
-        for (int t = 0; t < count; ++t) layouts[t]->opts.parts_per_cu = candidates[i];
+    for (size_t i = 0; i < cands.size() && st == MTTKRP_OK; ++i) {
+        for (int t = 0; t < count; ++t) apply(t, cands[i]);
         mttkrp_batch_handle b = nullptr;
         st = mttkrp_batch_create(layouts, count, R, nullptr, &b);
         if (st) break;
@@ -1271,7 +1421,7 @@ mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int
         ms /= (float)reps;
         if (times_ms) times_ms[i] = ms;
         if (best < 0 || ms < best_ms) {
-            best = i;
+            best = (int)i;
             best_ms = ms;
         }
     }
@@ -1281,11 +1431,62 @@ mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int
         restore();
         return st;
     }
-    for (int t = 0; t < count; ++t) layouts[t]->opts.parts_per_cu = candidates[best];
-    *best_ppc = candidates[best];
+    for (int t = 0; t < count; ++t) apply(t, cands[best]);
+    *best_out = best;
     return MTTKRP_OK;
 }
 
+extern "C" {
+
+mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int R, const int* candidates,
+                                    int n_candidates, const float* const* factors, float* const* outs, int reps,
+                                    hipStream_t stream, int* best_ppc, float* times_ms)
+{
+    g_err.clear();
+    static const int kDefault[] = {1, 2, 4, 8, 16};
+    if (!best_ppc) return fail(MTTKRP_EINVAL, "NULL best_ppc");
+    if (!candidates) {
+        candidates = kDefault;
+        n_candidates = 5;
+    }
+    if (n_candidates <= 0) return fail(MTTKRP_EINVAL, "need at least one candidate");
+    std::vector<mttkrp_part_shape> c(n_candidates);
+    for (int i = 0; i < n_candidates; ++i) c[i] = {candidates[i], 0, 0};
+    int best = 0;
+    mttkrp_status st = autotune_impl(layouts, count, R, c, false, factors, outs, reps, stream, &best, times_ms);
+    if (st) return st;
+    *best_ppc = c[best].parts_per_cu;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_batch_autotune_shape(const mttkrp_handle* layouts, int count, int R,
+                                          const mttkrp_part_shape* candidates, int n_candidates,
+                                          const float* const* factors, float* const* outs, int reps,
+                                          hipStream_t stream, mttkrp_part_shape* best, float* times_ms)
+{
+    g_err.clear();
+    if (!best) return fail(MTTKRP_EINVAL, "NULL best");
+    if (!layouts || count <= 0 || !layouts[0]) return fail(MTTKRP_EINVAL, "NULL layouts");
+    std::vector<mttkrp_part_shape> c;
+    if (candidates) {
+        if (n_candidates <= 0) return fail(MTTKRP_EINVAL, "need at least one candidate");
+        c.assign(candidates, candidates + n_candidates);
+    } else {
+        c = default_shapes(layouts[0]->N);
+    }
+    int k = 0;
+    mttkrp_status st = autotune_impl(layouts, count, R, c, true, factors, outs, reps, stream, &k, times_ms);
+    if (st) return st;
+    *best = c[k];
+    return MTTKRP_OK;
+}
+
+int mttkrp_batch_autotune_default_shapes(int N, mttkrp_part_shape* out)
+{
+    const std::vector<mttkrp_part_shape> c = default_shapes(N);
+    if (out) std::copy(c.begin(), c.end(), out);
+    return (int)c.size();
+}
 
 mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* factors, double* const* lambdas,
                                        double* const* fits, hipStream_t stream)
@@ -1299,8 +1500,9 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
         mttkrp_status s = check_factors(h, reinterpret_cast<const void* const*>(factors + (size_t)t * N), R);
         if (s) return fail(s, "tensor " + std::to_string(t) + ": " + g_err);
         if (h->als_R != R) return fail(MTTKRP_EINVAL, "tensor " + std::to_string(t) + ": call cpd_als_init first");
-        if (h->opts.factor_dtype != MTTKRP_FP32)
-            return fail(MTTKRP_EUNSUPPORTED, "batched CP-ALS gathers fp32 factors only");
+        if (h->opts.factor_dtype != b->dtype)
+            return fail(MTTKRP_EINVAL, "tensor " + std::to_string(t) + ": its factor_dtype differs from the batch's "
+                                       "(create the batch with the layouts' factor_dtype)");
         if (!lambdas[t]) return fail(MTTKRP_EINVAL, "NULL lambda for tensor " + std::to_string(t));
     }
     std::vector<float*> outs(C);
@@ -1315,6 +1517,7 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
             float* A = factors[(size_t)t * N + (n < N ? n : N - 1)];
             jobs[t] = n < N ? dense_job(h, A, n, R)
                             : fit_job(h, A, R, (fits && fits[t]) ? fits[t] : h->als.scal, lambdas[t]);
+            if (n < N && b->dtype == MTTKRP_BF16) jobs[t].A16 = h->als.bf16[n];
         }
         if (jobs.size() != b->last_jobs[n].size() ||
             std::memcmp(jobs.data(), b->last_jobs[n].data(), jobs.size() * sizeof(mk::DenseJob)) != 0) {
@@ -1328,11 +1531,19 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         e = mk::als_normal_eq_inverse(b->inv_jobs, C, N, n, R, 0, stream);
         if (e != hipSuccess) break;
-        mttkrp_status st = mttkrp_batch_run(b, n, factors, outs.data(), stream);
+        // The MTTKRP gathers the fp32 factors, or the handles' bf16 copies.
+        std::vector<const void*> gather((size_t)C * N);
+        for (int t = 0; t < C; ++t)
+            for (int m = 0; m < N; ++m)
+                gather[(size_t)t * N + m] = b->dtype == MTTKRP_BF16 ? static_cast<const void*>(b->hs[t]->als.bf16[m])
+                                                                    : static_cast<const void*>(factors[(size_t)t * N + m]);
+        mttkrp_status st = batch_run_impl(b, n, gather.data(), b->dtype, outs.data(), stream);
         if (st) return st;
         e = mk::als_solve_normalize_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R, stream);
         if (e == hipSuccess)
             e = mk::als_gram_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R, stream);
+        if (e == hipSuccess && b->dtype == MTTKRP_BF16)
+            e = mk::cast_bf16_jobs(b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], R, stream);
     }
     if (e == hipSuccess)
         e = mk::als_fit_jobs(none, b->dense_jobs[N], b->dense_work[N - 1], b->ndense_work[N - 1], C, R, stream);

@@ -12,6 +12,7 @@ namespace mk {
 
 constexpr int kWG = 256;                       // threads per workgroup in every kernel here
 constexpr int kMaxIn = MTTKRP_MAX_MODES - 1;   // input modes per nonzero, at most
+constexpr int kMaxIn16 = 4;                    // input modes up to which 16-bit coordinate kernels exist
 
 // One mode-specific copy of the tensor in device memory (Sec. III-C).
 // Nonzeros are ordered by output row; arrays are padded to nnz_pad (a
@@ -34,6 +35,9 @@ struct DevMode {
     // entries, transposed per 32 steps, and winfo describes steps.
     uint32_t step_P = 0;
     uint64_t nsteps = 0;
+    // idx16: the input coordinate arrays hold uint16 (every input dimension
+    // <= 65536, 3- to 5-mode tensors, nonzero-ordered copies without hot rows).
+    bool idx16 = false;
 };
 
 // Launch geometry of one MTTKRP call.
@@ -44,13 +48,24 @@ struct Geometry {
     uint64_t wgc;       // nonzeros per workgroup partition = groups * gsz
     uint32_t nparts;    // workgroups (partitions)
     uint32_t grid = 0;  // hot-steps copies: resident workgroups that walk the partitions
+    // A tuned partition-kernel shape (3-mode tensors, fp32 factors, no hot
+    // rows): threads per workgroup and gathers in flight; 0 = the default.
+    int threads = 0, gathers = 0;
 };
 
 // Partitions of about nnz / target_parts nonzeros, with at most max_parts
 // partitions and, unless max_parts forbids it, at most max_gsz nonzeros per
-// lane group (the length of its FP32 accumulation chain).
+// lane group (the length of its FP32 accumulation chain); workgroups of
+// `threads` threads (0: the default for n_in).  The caller sets the tuned
+// shape fields.
 Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts,
-                       uint32_t max_gsz);
+                       uint32_t max_gsz, int threads = 0);
+
+// The partition kernel's default shape for n_in inputs, rank R and dtype.
+void default_part_shape(int n_in, int R, int dtype, int* threads, int* gathers);
+
+// Whether a tuned shape (threads per workgroup, gathers in flight) is compiled.
+bool tuned_shape_supported(int threads, int gathers);
 
 // Launch plan of a hot-steps copy of nsteps steps: gsz = steps per wave run
 // (a multiple of 32, at most max_chain / passes), groups = waves per
@@ -96,8 +111,9 @@ void fill_part_desc(void* dst, const DevMode& m, int R, int dtype, const void* c
 size_t fix_desc_bytes();
 // Returns the number of fix-up blocks of this copy.
 uint32_t fill_fix_desc(void* dst, const DevMode& m, const Geometry& g, float* carry, float* out, int R);
-hipError_t launch_batch_part(int n_in, int R, int dtype, const void* descs, const uint2* work, uint32_t nwork,
-                             uint32_t grid, hipStream_t s);
+// threads, gathers: the batch's tuned shape (0, 0: the default kernels).
+hipError_t launch_batch_part(int n_in, int R, int dtype, int threads, int gathers, const void* descs,
+                             const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s);
 hipError_t launch_batch_fixup(const void* descs, const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s);
 
 // CP-ALS helpers (als_kernels.hip).  All FP64 unless noted.
@@ -149,6 +165,7 @@ struct DenseJob {
     double* fit_out;       // 1 double (fit)
     double* lam_out;       // R (fit: the caller's lambda)
     double normX2;         // |X|^2 (fit)
+    uint16_t* A16;         // bf16 copy of A (batched casts), or null
     uint32_t I, rpb, nb;
     int N;
 };
@@ -160,12 +177,15 @@ hipError_t als_gram_jobs(const DenseJob& single, const DenseJob* jobs, const uin
 hipError_t als_fit_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
                         int R, hipStream_t s);
 hipError_t cast_bf16(const float* A, uint64_t n, uint16_t* out, hipStream_t s);
+// bf16 copies of every job's A into its A16 over a (job, row block) work list.
+hipError_t cast_bf16_jobs(const DenseJob* jobs, const uint2* work, uint32_t nwork, int R, hipStream_t s);
 
 // Device memory of one mode copy, sized for nnz_pad nonzeros and I_n rows:
 // N-1 index arrays, values, per-word row info, and the row lists (nonempty
 // rows first, then the empty rows, I_n entries in all).
 struct DeviceModeSlots {
-    uint32_t* idx[kMaxIn] = {};
+    uint32_t* idx[kMaxIn] = {};   // uint16 arrays when idx16
+    bool idx16 = false;
     float* val = nullptr;
     uint2* winfo = nullptr;
     uint32_t* rows = nullptr;

@@ -26,9 +26,16 @@ struct KeyFields {
 };
 
 struct DecodeOut {
-    uint32_t* idx[kMaxIn];
+    void* idx[kMaxIn];   // uint32 arrays, or uint16 where bit j of narrow is set
+    uint32_t narrow;
     float* val;
 };
+
+__device__ __forceinline__ void put_idx(const DecodeOut& out, int j, uint64_t k, uint32_t v)
+{
+    if ((out.narrow >> j) & 1u) static_cast<uint16_t*>(out.idx[j])[k] = (uint16_t)v;
+    else static_cast<uint32_t*>(out.idx[j])[k] = v;
+}
 
 using u128 = unsigned __int128;
 
@@ -77,14 +84,14 @@ __global__ void decode_kernel(const uint64_t* __restrict__ lo, const uint64_t* _
     const uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (k >= nnz_pad) return;
     if (k >= nnz) {
-        for (int f = 0; f < kf.nf; ++f) out.idx[kf.slot[f]][k] = 0u;
+        for (int f = 0; f < kf.nf; ++f) put_idx(out, kf.slot[f], k, 0u);
         out.val[k] = 0.0f;
         return;
     }
     const u128 x = key_at(lo, hi, k);
     for (int f = 0; f < kf.nf; ++f) {
         const uint32_t mask = kf.bits[f] ? (uint32_t)((1ull << kf.bits[f]) - 1ull) : 0u;
-        out.idx[kf.slot[f]][k] = (uint32_t)(x >> kf.shift[f]) & mask;
+        put_idx(out, kf.slot[f], k, (uint32_t)(x >> kf.shift[f]) & mask);
     }
     out.val[k] = val_in[pos[k]];
 }
@@ -321,6 +328,7 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
         }
         DecodeOut out{};
         for (int j = 0; j < N - 1; ++j) out.idx[j] = sl.idx[j];
+        out.narrow = sl.idx16 ? (1u << (N - 1)) - 1u : 0u;
         out.val = sl.val;
         decode_kernel<<<blocks_for(nnz_pad, T), T, 0, s>>>(lo, hi, pos, d_val, nnz, nnz_pad, kf, out);
         row_bits_kernel<<<blocks_for(nwords, T), T, 0, s>>>(lo, hi, nnz, nwords, kf, d_bits, d_cnt);
@@ -362,6 +370,7 @@ hipError_t build_device_modes(const uint32_t* coo_host, const float* vals_host, 
             d.in_dims[j] = dims[m];
             d.idx[j] = sl.idx[j];
         }
+        d.idx16 = sl.idx16;
         d.val = sl.val;
         d.winfo = sl.winfo;
         d.row_id = sl.rows;

@@ -63,6 +63,18 @@ extern template hipError_t launch_part_nin<6>(const DevMode&, int, int, const vo
 extern template hipError_t launch_part_nin<7>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
                                                 uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 
+extern template hipError_t launch_part_tuned_wg<256>(const DevMode&, int, int, const void* const*, float*, float*,
+                                                    const Geometry&, uint32_t, hipStream_t);
+extern template hipError_t launch_part_tuned_wg<512>(const DevMode&, int, int, const void* const*, float*, float*,
+                                                    const Geometry&, uint32_t, hipStream_t);
+extern template hipError_t launch_part_tuned_wg<1024>(const DevMode&, int, int, const void* const*, float*, float*,
+                                                     const Geometry&, uint32_t, hipStream_t);
+extern template hipError_t launch_batch_part_tuned_wg<256>(int, int, const void*, const uint2*, uint32_t, uint32_t,
+                                                          hipStream_t);
+extern template hipError_t launch_batch_part_tuned_wg<512>(int, int, const void*, const uint2*, uint32_t, uint32_t,
+                                                          hipStream_t);
+extern template hipError_t launch_batch_part_tuned_wg<1024>(int, int, const void*, const uint2*, uint32_t, uint32_t,
+                                                           hipStream_t);
 extern template hipError_t launch_step_nin<2>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
                                              uint32_t, float*, float*, const Geometry&, uint32_t, hipStream_t);
 extern template hipError_t launch_step_nin<3>(const DevMode&, int, int, const void* const*, const uint32_t* const*,
@@ -159,11 +171,12 @@ __global__ __launch_bounds__(kWG) void mttkrp_batch_fixup_kernel(const FixArgs* 
 
 }  // namespace
 
-Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts, uint32_t max_gsz)
+Geometry plan_geometry(uint64_t nnz, int n_in, int R, int dtype, int target_parts, uint32_t max_parts, uint32_t max_gsz,
+                       int threads)
 {
     Geometry g;
     g.lanes = lanes_per_row(R, dtype);
-    g.groups = part_wg(n_in) / g.lanes;
+    g.groups = (threads > 0 ? threads : part_wg(n_in)) / g.lanes;
     if (target_parts < 1) target_parts = 1;
     max_gsz = max_gsz < 32 ? 32 : max_gsz / 32 * 32;
     uint64_t per_group = (nnz + (uint64_t)target_parts * g.groups - 1) / ((uint64_t)target_parts * g.groups);
@@ -219,6 +232,28 @@ Geometry plan_step_geometry(uint64_t nsteps, int R, int dtype, uint32_t P, int t
 
 int partition_wg_threads(int n_in) { return part_wg(n_in); }
 
+void default_part_shape(int n_in, int R, int dtype, int* threads, int* gathers)
+{
+    *threads = part_wg(n_in);
+    *gathers = part::gathers_in_flight(n_in, R, dtype);
+}
+
+bool tuned_shape_supported(int threads, int gathers)
+{
+    return (threads == 256 || threads == 512 || threads == 1024) && (gathers == 2 || gathers == 4);
+}
+
+static hipError_t launch_part_tuned(const DevMode& m, int R, const void* const* fac, float* out, float* carry,
+                                    const Geometry& g, uint32_t atomic_cut, hipStream_t s)
+{
+    switch (g.threads) {
+        case 256: return launch_part_tuned_wg<256>(m, R, g.gathers, fac, out, carry, g, atomic_cut, s);
+        case 512: return launch_part_tuned_wg<512>(m, R, g.gathers, fac, out, carry, g, atomic_cut, s);
+        case 1024: return launch_part_tuned_wg<1024>(m, R, g.gathers, fac, out, carry, g, atomic_cut, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 int step_wg_threads() { return kStepWG; }
 
 // out[0..n) = 0 (a kernel, not a memset, so that it can sit in a captured graph).
@@ -252,6 +287,11 @@ hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* 
             case 3: e = launch_step_nin<3>(m, R, dtype, fac, hot_rows, nhot, out, carry, g, grid, s); break;
             default: e = hipErrorInvalidValue;
         }
+        if (e != hipSuccess) return e;
+    } else if (m.nnz > 0 && g.threads) {
+        // A tuned launch shape (3-mode tensors, fp32 factors, no hot rows).
+        if (dtype != MTTKRP_FP32 || nhot) return hipErrorInvalidValue;
+        e = launch_part_tuned(m, R, fac, out, carry, g, ac, s);
         if (e != hipSuccess) return e;
     } else if (m.nnz > 0) {
         switch (m.n_in) {
@@ -312,10 +352,19 @@ hipError_t launch_batch_fixup(const void* descs, const uint2* work, uint32_t nwo
     return hipGetLastError();
 }
 
-hipError_t launch_batch_part(int n_in, int R, int dtype, const void* descs, const uint2* work, uint32_t nwork,
-                             uint32_t grid, hipStream_t s)
+hipError_t launch_batch_part(int n_in, int R, int dtype, int threads, int gathers, const void* descs,
+                             const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s)
 {
     if (nwork == 0) return hipSuccess;
+    if (threads) {
+        if (n_in != 2 || dtype != MTTKRP_FP32) return hipErrorInvalidValue;
+        switch (threads) {
+            case 256: return launch_batch_part_tuned_wg<256>(R, gathers, descs, work, nwork, grid, s);
+            case 512: return launch_batch_part_tuned_wg<512>(R, gathers, descs, work, nwork, grid, s);
+            case 1024: return launch_batch_part_tuned_wg<1024>(R, gathers, descs, work, nwork, grid, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (n_in) {
         case 2: return launch_batch_part_nin<2>(R, dtype, descs, work, nwork, grid, s);
         case 3: return launch_batch_part_nin<3>(R, dtype, descs, work, nwork, grid, s);

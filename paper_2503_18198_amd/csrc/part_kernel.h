@@ -46,9 +46,9 @@ constexpr int vals_per_lane(int R, int dtype) { return (dtype == MTTKRP_BF16 && 
 constexpr int lanes_per_row(int R, int dtype) { return R / vals_per_lane(R, dtype); }
 
 // Dynamic LDS bytes of a partition workgroup.
-inline uint32_t part_lds_bytes(int n_in, int R, int dtype, uint32_t nhot)
+inline uint32_t part_lds_bytes(int n_in, int R, int dtype, uint32_t nhot, int threads = 0)
 {
-    const uint32_t groups = part_wg(n_in) / lanes_per_row(R, dtype);
+    const uint32_t groups = (threads ? threads : part_wg(n_in)) / lanes_per_row(R, dtype);
     const uint32_t es = dtype == MTTKRP_FP32 ? 4 : 2;
     const uint32_t hot = (uint32_t)n_in * nhot * (uint32_t)R * es;
     const uint32_t slots = 2u * groups * (uint32_t)R * 4u;
@@ -190,6 +190,7 @@ struct PartArgs {
     uint32_t nhot;       // hot slots per input mode held in LDS
     uint32_t atomic_cut; // rows cut by a partition boundary: 0 partial to carry, 1 global atomic add to out
     const uint64_t* prange; // scheme 1: {first position, nonzeros} per partition (whole rows); null: part * G * gsz
+    uint32_t idx16;         // 1: the input coordinates are uint16 (every input dimension <= 65536)
 };
 
 // Nonzeros whose row gathers are issued before the first is used, chosen so
@@ -197,13 +198,12 @@ struct PartArgs {
 #ifndef MK_U_BF16_WIDE
 #define MK_U_BF16_WIDE 4
 #endif
-template <int NIN, int R, int DT>
-constexpr int gathers_in_flight()
+constexpr int gathers_in_flight(int n_in, int R, int dtype)
 {
-    if constexpr (vals_per_lane(R, DT) == 8) return MK_U_BF16_WIDE;
-    if constexpr (NIN <= 2) return (DT == MTTKRP_FP32 && R == 16) ? 2 : MK_U_3MODE;
-    else if constexpr (NIN <= 3) return (DT == MTTKRP_FP32 && R == 16) ? 2 : 4;
-    else return 2;
+    if (vals_per_lane(R, dtype) == 8) return MK_U_BF16_WIDE;
+    if (n_in <= 2) return (dtype == MTTKRP_FP32 && R == 16) ? 2 : MK_U_3MODE;
+    if (n_in <= 3) return (dtype == MTTKRP_FP32 && R == 16) ? 2 : 4;
+    return 2;
 }
 
 // State of one lane group while it walks its run of nonzeros (E values per lane).
@@ -224,12 +224,26 @@ struct Batch {
     uint2 w;   // {row-start bits, ordinal of the row holding the first nonzero}
 };
 
-template <int NIN, int V>
+template <int NIN, int V, bool IDX16 = false>
 __device__ __forceinline__ void load_batch(const PartArgs<NIN>& a, uint64_t b, int gl, Batch<NIN, V>& bt)
 {
     static_for<0, NIN>([&](auto M) {
         constexpr int m = decltype(M)::value;
-        load_words<V>(a.idx[m] + b + gl * V, bt.idx[m]);
+        if constexpr (IDX16) {
+            // V uint16 coordinates = V / 2 words, widened in registers
+            static_assert(V % 2 == 0, "16-bit coordinates need an even count per lane");
+            uint32_t w[V / 2];
+            load_words<V / 2>(reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint16_t*>(a.idx[m]) + b +
+                                                                gl * V),
+                              w);
+#pragma unroll
+            for (int i = 0; i < V / 2; ++i) {
+                bt.idx[m][2 * i] = w[i] & 0xFFFFu;
+                bt.idx[m][2 * i + 1] = w[i] >> 16;
+            }
+        } else {
+            load_words<V>(a.idx[m] + b + gl * V, bt.idx[m]);
+        }
     });
     load_words<V>(reinterpret_cast<const uint32_t*>(a.val) + b + gl * V, bt.val);
     bt.w = a.winfo[b >> 5];
@@ -258,7 +272,7 @@ __device__ __forceinline__ void flush_row(const PartArgs<NIN>& a, GroupState<val
 // One batch of 32 consecutive nonzeros starting at b (b is a multiple of 32).
 // FULL: all 32 are valid (no per-nonzero bounds tests).  HOT: coordinates
 // may name LDS hot-row slots.
-template <int NIN, int R, int DT, bool HOT, bool FULL>
+template <int NIN, int R, int DT, bool HOT, bool FULL, int U>
 __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __amdgpu_buffer_rsrc_t (&rsrc)[NIN],
                                               lds_char* hot_lds, GroupState<vals_per_lane(R, DT)>& st,
                                               const Batch<NIN, 32 / lanes_per_row(R, DT)>& bt,
@@ -267,7 +281,6 @@ __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __am
     constexpr int E = vals_per_lane(R, DT);
     constexpr int L = R / E;
     constexpr int V = 32 / L;
-    constexpr int U = gathers_in_flight<NIN, R, DT>();
     using ST = typename Slice<R, DT>::T;
 
     uint32_t flags = bt.w.x;
@@ -378,10 +391,13 @@ __device__ __forceinline__ void process_batch(const PartArgs<NIN>& a, const __am
 }
 
 // The work of one partition `part` (a workgroup's share) of one mode copy.
-template <int NIN, int R, int DT, bool HOT>
+// WGT threads per workgroup and UU nonzeros' gathers in flight per lane
+// group: the library defaults (part_wg, gathers_in_flight) or a tuned shape.
+template <int NIN, int R, int DT, bool HOT, bool IDX16 = false, int WGT = part_wg(NIN),
+          int UU = gathers_in_flight(NIN, R, DT)>
 __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t part, char* smem)
 {
-    constexpr int kPartWG = part_wg(NIN);
+    constexpr int kPartWG = WGT;
     constexpr int E = vals_per_lane(R, DT);
     constexpr int L = R / E;            // lanes per group
     constexpr int V = 32 / L;
@@ -458,17 +474,17 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
 #pragma unroll
         for (int m = 0; m < NIN; ++m) rsrc[m] = make_rsrc(a.fac[m], a.fac_bytes[m]);
         Batch<NIN, V> cur_b, next_b;
-        load_batch<NIN, V>(a, g_beg, gl, cur_b);
+        load_batch<NIN, V, IDX16>(a, g_beg, gl, cur_b);
         st.first_row = st.cur = (int)cur_b.w.y;
         hstart = (int)(cur_b.w.x & 1u);
         uint64_t b = g_beg;
         for (; b + 32 <= g_end; b += 32) {
-            if (b + 32 < g_end) load_batch<NIN, V>(a, b + 32, gl, next_b);
-            process_batch<NIN, R, DT, HOT, true>(a, rsrc, hot_lds, st, cur_b, 32, b == g_beg, gl, wave_grp0);
+            if (b + 32 < g_end) load_batch<NIN, V, IDX16>(a, b + 32, gl, next_b);
+            process_batch<NIN, R, DT, HOT, true, UU>(a, rsrc, hot_lds, st, cur_b, 32, b == g_beg, gl, wave_grp0);
             cur_b = next_b;
         }
         if (b < g_end)
-            process_batch<NIN, R, DT, HOT, false>(a, rsrc, hot_lds, st, cur_b, (int)(g_end - b), b == g_beg, gl,
+            process_batch<NIN, R, DT, HOT, false, UU>(a, rsrc, hot_lds, st, cur_b, (int)(g_end - b), b == g_beg, gl,
                                                   wave_grp0);
     }
     __syncthreads();   // every group is done with the hot rows
@@ -536,25 +552,30 @@ __device__ __forceinline__ void partition_body(const PartArgs<NIN>& a, uint32_t 
     }
 }
 
-template <int NIN, int R, int DT, bool HOT>
-__global__ __launch_bounds__(part_wg(NIN)) void mttkrp_part_kernel(PartArgs<NIN> a)
+template <int NIN, int R, int DT, bool HOT, bool IDX16 = false, int WGT = part_wg(NIN),
+          int UU = gathers_in_flight(NIN, R, DT)>
+__global__ __launch_bounds__(WGT) void mttkrp_part_kernel(PartArgs<NIN> a)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    partition_body<NIN, R, DT, HOT>(a, blockIdx.x, smem);
+    partition_body<NIN, R, DT, HOT, IDX16, WGT, UU>(a, blockIdx.x, smem);
 }
 
 // Many tensors' copies of the same mode in one launch: a static list of
 // (tensor, partition) work items, walked by a grid of resident workgroups.
-template <int NIN, int R, int DT>
-__global__ __launch_bounds__(part_wg(NIN)) void mttkrp_batch_part_kernel(const PartArgs<NIN>* __restrict__ descs,
-                                                                         const uint2* __restrict__ work,
-                                                                         uint32_t nwork)
+template <int NIN, int R, int DT, int WGT = part_wg(NIN), int UU = gathers_in_flight(NIN, R, DT)>
+__global__ __launch_bounds__(WGT) void mttkrp_batch_part_kernel(const PartArgs<NIN>* __restrict__ descs,
+                                                                const uint2* __restrict__ work, uint32_t nwork)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
         const uint2 wk = work[w];
         const PartArgs<NIN> a = descs[wk.x];
-        partition_body<NIN, R, DT, false>(a, wk.y, smem);
+        if constexpr (NIN <= kMaxIn16) {
+            if (a.idx16) partition_body<NIN, R, DT, false, true, WGT, UU>(a, wk.y, smem);
+            else partition_body<NIN, R, DT, false, false, WGT, UU>(a, wk.y, smem);
+        } else {
+            partition_body<NIN, R, DT, false, false, WGT, UU>(a, wk.y, smem);
+        }
         __syncthreads();   // the next item reuses the LDS
     }
 }
@@ -581,25 +602,28 @@ void fill_part_args(PartArgs<NIN>& a, const DevMode& m, int R, int dtype, const 
     a.nhot = nhot;
     a.atomic_cut = 0;
     a.prange = m.prange;
+    a.idx16 = m.idx16 ? 1u : 0u;
 }
 
-template <int NIN, int R, int DT, bool HOT>
+template <int NIN, int R, int DT, bool HOT, bool IDX16 = false, int WGT = part_wg(NIN),
+          int UU = gathers_in_flight(NIN, R, DT)>
 hipError_t launch_part(const DevMode& m, const void* const* fac, const uint32_t* const* hot_rows, uint32_t nhot,
                        float* out, float* carry, const Geometry& g, uint32_t atomic_cut, hipStream_t s)
 {
     PartArgs<NIN> a;
     fill_part_args<NIN>(a, m, R, DT, fac, hot_rows, nhot, out, carry, g.gsz);
     a.atomic_cut = atomic_cut;
-    const uint32_t lds = part_lds_bytes(NIN, R, DT, nhot);
+    const uint32_t lds = part_lds_bytes(NIN, R, DT, nhot, WGT);
     static uint32_t lds_set = 0;   // largest dynamic LDS size already allowed for this instantiation
     if (lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mttkrp_part_kernel<NIN, R, DT, HOT>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&mttkrp_part_kernel<NIN, R, DT, HOT, IDX16, WGT, UU>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         lds_set = lds;
     }
-    hipLaunchKernelGGL((mttkrp_part_kernel<NIN, R, DT, HOT>), dim3(m.prange ? m.nprange : g.nparts),
-                       dim3(part_wg(NIN)), lds, s, a);
+    hipLaunchKernelGGL((mttkrp_part_kernel<NIN, R, DT, HOT, IDX16, WGT, UU>), dim3(m.prange ? m.nprange : g.nparts),
+                       dim3(WGT), lds, s, a);
     return hipGetLastError();
 }
 
@@ -615,6 +639,16 @@ hipError_t dispatch_r(const DevMode& m, int R, const void* const* fac, const uin
             default: return hipErrorInvalidValue;
         }
     }
+    if constexpr (NIN <= kMaxIn16) {
+        if (m.idx16) {
+            switch (R) {
+                case 16: return launch_part<NIN, 16, DT, false, true>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
+                case 32: return launch_part<NIN, 32, DT, false, true>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
+                case 64: return launch_part<NIN, 64, DT, false, true>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
+                default: return hipErrorInvalidValue;
+            }
+        }
+    }
     switch (R) {
         case 16: return launch_part<NIN, 16, DT, false>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
         case 32: return launch_part<NIN, 32, DT, false>(m, fac, hot_rows, nhot, out, carry, g, atomic_cut, s);
@@ -623,23 +657,75 @@ hipError_t dispatch_r(const DevMode& m, int R, const void* const* fac, const uin
     }
 }
 
-template <int NIN, int R, int DT>
+template <int NIN, int R, int DT, int WGT = part_wg(NIN), int UU = gathers_in_flight(NIN, R, DT)>
 hipError_t launch_batch_part(const void* descs, const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s)
 {
-    const uint32_t lds = part_lds_bytes(NIN, R, DT, 0);
+    const uint32_t lds = part_lds_bytes(NIN, R, DT, 0, WGT);
     static uint32_t lds_set = 0;
     if (lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mttkrp_batch_part_kernel<NIN, R, DT>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mttkrp_batch_part_kernel<NIN, R, DT, WGT, UU>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         lds_set = lds;
     }
-    hipLaunchKernelGGL((mttkrp_batch_part_kernel<NIN, R, DT>), dim3(grid), dim3(part_wg(NIN)), lds, s,
+    hipLaunchKernelGGL((mttkrp_batch_part_kernel<NIN, R, DT, WGT, UU>), dim3(grid), dim3(WGT), lds, s,
                        static_cast<const PartArgs<NIN>*>(descs), work, nwork);
     return hipGetLastError();
 }
 
 }  // namespace part
+
+// Launch shapes the autotuner may pick for fp32 factors of 3-mode tensors
+// without hot rows: workgroups of WGT = 256, 512 or 1024 threads and 2 or 4
+// nonzeros' gathers in flight per lane group.  Each workgroup size is
+// instantiated in a file of its own (part_tuned_<WGT>.hip); a shape equal to
+// the default of its rank runs through the default kernels instead.
+template <int R, int WGT, int UU>
+hipError_t launch_tuned_r(const DevMode& m, const void* const* fac, float* out, float* carry, const Geometry& g,
+                          uint32_t atomic_cut, hipStream_t s)
+{
+    if constexpr (WGT == part_wg(2) && UU == part::gathers_in_flight(2, R, MTTKRP_FP32)) {
+        return hipErrorInvalidValue;
+    } else {
+        if (m.idx16)
+            return part::launch_part<2, R, MTTKRP_FP32, false, true, WGT, UU>(m, fac, nullptr, 0, out, carry, g,
+                                                                             atomic_cut, s);
+        return part::launch_part<2, R, MTTKRP_FP32, false, false, WGT, UU>(m, fac, nullptr, 0, out, carry, g,
+                                                                          atomic_cut, s);
+    }
+}
+
+template <int R, int WGT, int UU>
+hipError_t launch_batch_tuned_r(const void* descs, const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s)
+{
+    if constexpr (WGT == part_wg(2) && UU == part::gathers_in_flight(2, R, MTTKRP_FP32))
+        return hipErrorInvalidValue;
+    else
+        return part::launch_batch_part<2, R, MTTKRP_FP32, WGT, UU>(descs, work, nwork, grid, s);
+}
+
+template <int WGT>
+hipError_t launch_part_tuned_wg(const DevMode& m, int R, int gathers, const void* const* fac, float* out, float* carry,
+                                const Geometry& g, uint32_t atomic_cut, hipStream_t s)
+{
+    if (m.n_in != 2) return hipErrorInvalidValue;
+#define MK_TUNED(RR, UU) \
+    if (R == RR && gathers == UU) return launch_tuned_r<RR, WGT, UU>(m, fac, out, carry, g, atomic_cut, s);
+    MK_TUNED(16, 2) MK_TUNED(16, 4) MK_TUNED(32, 2) MK_TUNED(32, 4) MK_TUNED(64, 2) MK_TUNED(64, 4)
+#undef MK_TUNED
+    return hipErrorInvalidValue;
+}
+
+template <int WGT>
+hipError_t launch_batch_part_tuned_wg(int R, int gathers, const void* descs, const uint2* work, uint32_t nwork,
+                                      uint32_t grid, hipStream_t s)
+{
+#define MK_TUNED(RR, UU) \
+    if (R == RR && gathers == UU) return launch_batch_tuned_r<RR, WGT, UU>(descs, work, nwork, grid, s);
+    MK_TUNED(16, 2) MK_TUNED(16, 4) MK_TUNED(32, 2) MK_TUNED(32, 4) MK_TUNED(64, 2) MK_TUNED(64, 4)
+#undef MK_TUNED
+    return hipErrorInvalidValue;
+}
 
 // Descriptor of one tensor's mode copy for the batched partition kernel.
 template <int NIN>

@@ -10,7 +10,7 @@
 namespace mk {
 namespace part {
 
-template <int NIN, int R, int DT, bool GATHER>
+template <int NIN, int R, int DT, bool GATHER, bool IDX16>
 __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN> a)
 {
     constexpr int kWGT = part_wg(NIN);
@@ -18,7 +18,7 @@ __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN
     constexpr int L = R / E;
     constexpr int V = 32 / L;
     constexpr int G = kWGT / L;
-    constexpr int U = gathers_in_flight<NIN, R, DT>();
+    constexpr int U = gathers_in_flight(NIN, R, DT);
     using ST = typename Slice<R, DT>::T;
 
     const int tid = threadIdx.x;
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN
         for (int m = 0; m < NIN; ++m) rsrc[m] = make_rsrc(a.fac[m], a.fac_bytes[m]);
         for (uint64_t b = g_beg; b < g_end; b += 32) {
             Batch<NIN, V> bt;
-            load_batch<NIN, V>(a, b, gl, bt);
+            load_batch<NIN, V, IDX16>(a, b, gl, bt);
             const int nvalid = (int)min((uint64_t)32, g_end - b);
             x ^= bt.w.x ^ bt.w.y;
             if constexpr (!GATHER) {
@@ -80,10 +80,19 @@ __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN
 template <int NIN, int R, int DT>
 hipError_t launch_probe_r(const PartArgs<NIN>& a, uint32_t grid, int what, hipStream_t s)
 {
+    if constexpr (NIN <= kMaxIn16) {
+        if (a.idx16) {
+            if (what == 0)
+                hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, false, true>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
+            else
+                hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, true, true>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (what == 0)
-        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, false>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
+        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, false, false>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
     else
-        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, true>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
+        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, true, false>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
     return hipGetLastError();
 }
 

@@ -179,3 +179,66 @@ def test_batch256_workload_every_tensor():
     b.free()
     for h in hs:
         h.free()
+
+
+def test_bf16_batch_mttkrp_and_als_equal_single():
+    """A batch created with factor_dtype BF16: the batched MTTKRP on bf16
+    factors is bitwise mttkrp_run_bf16 of each tensor and matches the oracle
+    fed the same bf16-rounded factors; batched CP-ALS sweeps of layouts built
+    with bf16 factor copies are bitwise their single-tensor sweeps."""
+    print("case batch bf16", flush=True)
+    import oracle
+    R = 32
+    rng = np.random.default_rng(13)
+    ts = []
+    for i in range(6):
+        dims = tuple(int(x) for x in rng.integers(100, 600, size=3))
+        ts.append(workloads.random_tensor(dims, int(rng.integers(2000, 40000)), dist="zipf", s=1.2, seed=1300 + i))
+    hs = [capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, factor_dtype=capi.MTTKRP_BF16))
+          for t in ts]
+    F = [workloads.random_factors(t.dims, R, seed=1400 + i) for i, t in enumerate(ts)]
+    d16 = [gu.dev_factors(f, dtype=torch.bfloat16) for f in F]
+    b = capi.mttkrp_batch_create(hs, R, opts=dict(factor_dtype=capi.MTTKRP_BF16))
+    for n in range(3):
+        outs = [torch.full((t.dims[n], R), float("nan"), device="cuda") for t in ts]
+        capi.mttkrp_batch_run_bf16(b, n, d16, outs)
+        torch.cuda.synchronize()
+        for i, t in enumerate(ts):
+            got = outs[i].cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), gu.gpu_mttkrp(hs[i], n, d16[i], R, bf16=True).view(np.uint32))
+            ref = gu.oracle_mttkrp(t.idx, t.val, t.dims, [oracle.bf16_round(f) for f in F[i]], n)
+            assert gu.rel_fro(got, ref) <= TOL
+    with pytest.raises(capi.MttkrpError):
+        capi.mttkrp_batch_run(b, 0, [gu.dev_factors(f) for f in F], [torch.empty((t.dims[0], R), device="cuda")
+                                                                      for t in ts])
+    # batched CP-ALS on the bf16 copies against single sweeps
+    Fb = [gu.dev_factors(f) for f in F]
+    Fs = [gu.dev_factors(f) for f in F]
+    lam_b = [torch.zeros(R, dtype=torch.float64, device="cuda") for _ in ts]
+    lam_s = [torch.zeros(R, dtype=torch.float64, device="cuda") for _ in ts]
+    fit_b = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in ts]
+    fit_s = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in ts]
+    for i, h in enumerate(hs):
+        capi.cpd_als_init(h, Fb[i], R)
+    for _ in range(3):
+        capi.cpd_als_batch_iter_async(b, Fb, lam_b, fit_b)
+    torch.cuda.synchronize()
+    out_b = [[f.clone() for f in fs] for fs in Fb]
+    fits_b = [f.item() for f in fit_b]
+    for i, h in enumerate(hs):
+        capi.cpd_als_init(h, Fs[i], R)
+        for _ in range(3):
+            capi.cpd_als_iter_async(h, Fs[i], lam_s[i], R, fit_s[i])
+        torch.cuda.synchronize()
+        capi.cpd_als_status(h)
+        for m in range(3):
+            assert torch.equal(out_b[i][m], Fs[i][m]), f"tensor {i} factor {m}"
+        assert fits_b[i] == fit_s[i].item()
+    b.free()
+    # bf16 layouts in an fp32 batch: refused for CP-ALS
+    b32 = capi.mttkrp_batch_create(hs, R)
+    with pytest.raises(capi.MttkrpError):
+        capi.cpd_als_batch_iter_async(b32, Fb, lam_b, fit_b)
+    b32.free()
+    for h in hs:
+        h.free()

@@ -265,3 +265,57 @@ def test_launch_plan_errors():
     with pytest.raises(capi.MttkrpError) as e:
         capi.mttkrp_launch_plan(2**32, 3, 32)
     assert e.value.status == capi.MTTKRP_EINVAL
+
+
+def test_16bit_coordinates_footprint_and_modes():
+    """A copy whose input dimensions are all <= 65536 stores 16-bit
+    coordinates (3- to 5-mode tensors, nonzero split, no hot rows): the
+    footprint shrinks by 2 bytes per input coordinate of such copies, and
+    wide_indices=1 keeps 32 bits everywhere."""
+    dims = (70000, 500, 400)           # copy 0 reads modes 1, 2 (16-bit); copies 1, 2 read mode 0 (32-bit)
+    nnz = 100_000
+    pad = (nnz + 31) // 32 * 32
+    f16 = capi.mttkrp_footprint(dims, nnz)
+    f32 = capi.mttkrp_footprint(dims, nnz, opts=dict(wide_indices=1))
+    assert f32 - f16 == pad * 2 * 2     # one copy, two input coordinates each
+    t = np.zeros((10, 3), dtype=np.uint32)
+    h = capi.mttkrp_layout_build(t, np.ones(10, np.float32), dims, opts=dict(host_only=1))
+    assert capi.mttkrp_layout_info(h)["idx16_modes"] == 0b001
+    h2 = capi.mttkrp_layout_build(t, np.ones(10, np.float32), dims, opts=dict(host_only=1, wide_indices=1))
+    assert capi.mttkrp_layout_info(h2)["idx16_modes"] == 0
+    h3 = capi.mttkrp_layout_build(t, np.ones(10, np.float32), dims, opts=dict(host_only=1, hot_rows=8))
+    assert capi.mttkrp_layout_info(h3)["idx16_modes"] == 0   # hot-row coordinates need the top bit
+    small = (300, 200, 100, 50, 20, 10)  # 6 modes: no 16-bit kernels
+    t6 = np.zeros((5, 6), dtype=np.uint32)
+    h6 = capi.mttkrp_layout_build(t6, np.ones(5, np.float32), small, opts=dict(host_only=1))
+    assert capi.mttkrp_layout_info(h6)["idx16_modes"] == 0
+    t5 = np.zeros((5, 5), dtype=np.uint32)
+    h5 = capi.mttkrp_layout_build(t5, np.ones(5, np.float32), small[:5], opts=dict(host_only=1))
+    assert capi.mttkrp_layout_info(h5)["idx16_modes"] == 0b11111
+
+
+def test_tuned_shape_options():
+    """part_threads / part_gathers: validated, reported by layout_info where
+    they apply (3-mode tensors without hot rows or steps) and ignored
+    elsewhere; the shape autotuner's default candidates."""
+    dims = (300, 200, 100)
+    t = np.zeros((10, 3), dtype=np.uint32)
+    v = np.ones(10, np.float32)
+    for bad in (dict(part_threads=300), dict(part_threads=128), dict(part_gathers=3), dict(part_gathers=-1)):
+        with pytest.raises(capi.MttkrpError):
+            capi.mttkrp_layout_build(t, v, dims, opts=dict(host_only=1, **bad))
+    h = capi.mttkrp_layout_build(t, v, dims, opts=dict(host_only=1, part_threads=1024, part_gathers=2))
+    i = capi.mttkrp_layout_info(h)
+    assert (i["wg_threads"], i["gathers_in_flight"]) == (1024, 2)
+    h = capi.mttkrp_layout_build(t, v, dims, opts=dict(host_only=1, max_R=16))
+    i = capi.mttkrp_layout_info(h)
+    assert (i["wg_threads"], i["gathers_in_flight"]) == (512, 2)
+    h = capi.mttkrp_layout_build(t, v, dims, opts=dict(host_only=1, part_threads=256, hot_rows=8))
+    assert capi.mttkrp_layout_info(h)["wg_threads"] == 512           # hot rows: the default kernels
+    t4 = np.zeros((10, 4), dtype=np.uint32)
+    h = capi.mttkrp_layout_build(t4, v, dims + (50,), opts=dict(host_only=1, part_threads=1024))
+    assert capi.mttkrp_layout_info(h)["wg_threads"] == 256           # 4 modes: the default kernels
+    d3 = capi.mttkrp_batch_autotune_default_shapes(3)
+    assert len(d3) == 30 and len(set(d3)) == 30
+    assert {s[1] for s in d3} == {256, 512, 1024} and {s[2] for s in d3} == {2, 4}
+    assert capi.mttkrp_batch_autotune_default_shapes(5) == [(p, 0, 0) for p in (1, 2, 4, 8, 16)]

@@ -58,6 +58,12 @@ PAPER_SHAPES = {
 PAPER_SHAPE_LARGE = {"nell1-like": ((2_900_000, 2_100_000, 25_500_000), 143_600_000)}
 
 
+def default_shape(N, R):
+    """The library's default launch shape as the shape autotuner names it:
+    8 partitions per CU; for 3 modes 512 threads and 4 gathers (2 at R = 16)."""
+    return (8, 512, 2 if R == 16 else 4) if N == 3 else (8, 0, 0)
+
+
 def algorithmic_bytes(dims, nnz, R, factor_bytes=4):
     """Bytes a mode's MTTKRP must move: the mode copy's indices and values, a
     4-byte row pointer per output row, each input factor read once, the
@@ -201,14 +207,13 @@ def bench_batch(args, R=16, count=256):
         best, times = capi.mttkrp_batch_autotune_shape(hs, R, F, outs, reps=3, stream=stream)
         info = capi.mttkrp_layout_info(hs[0])
         ms = sorted(times.values())
-        dflt = [v for (p, th, g), v in times.items()
-                if p == 8 and (th or 512) == 512 and g in (0, 2 if R == 16 else 4)]
+        dflt = times.get(default_shape(3, R))
         tuned = {"parts_per_cu": best[0], "wg_threads": info["wg_threads"],
                  "gathers_in_flight": info["gathers_in_flight"], "source": "mttkrp_batch_autotune_shape",
                  "candidates": len(times),
                  "spread_ms_per_pass": {"fastest": round(ms[0], 4), "median": round(ms[len(ms) // 2], 4),
                                         "slowest": round(ms[-1], 4),
-                                        "default_shape": round(dflt[0], 4) if dflt else None},
+                                        "default_shape": round(dflt, 4) if dflt else None},
                  "candidate_ms_per_pass": {f"{p}/{th or 'def'}/{g or 'def'}": round(v, 4)
                                            for (p, th, g), v in times.items()},
                  "tuning_s": round(time.perf_counter() - t0, 2)}
@@ -650,6 +655,10 @@ def main(argv=None):
     ap.add_argument("--no-side-workloads", action="store_true",
                     help="default workload only: leave out the batch and serve sub-objects")
     ap.add_argument("--parts-per-cu", type=int, default=0)
+    ap.add_argument("--shape", default="",
+                    help="fixed launch shape PPC,THREADS,GATHERS of the nonzero-ordered copies (no tuning)")
+    ap.add_argument("--no-tune-shape", action="store_true",
+                    help="time the library's default launch shape instead of the autotuned one")
     ap.add_argument("--kernel", choices=("steps", "nonzero"), default="nonzero",
                     help="layout timed for the MTTKRP: nonzero-ordered copies or hot-steps copies (3- and 4-mode)")
     ap.add_argument("--no-compare-layouts", action="store_true",
@@ -743,6 +752,32 @@ def main(argv=None):
     dF = [torch.from_numpy(f).cuda() for f in F]
     outs = [torch.empty((d, R), dtype=torch.float32, device="cuda") for d in t.dims]
 
+    # Launch shape of the nonzero-ordered copies (partitions per CU, and for
+    # 3-mode tensors the workgroup size and gathers in flight): measured by
+    # the library's shape autotuner over its default candidates, unless fixed.
+    launch_shape = None
+    if not steps and not args.no_tune_shape:
+        t_t = time.perf_counter()
+        if args.shape:
+            cands = [tuple(int(x) for x in args.shape.split(","))]
+        elif args.parts_per_cu:
+            cands = sorted({(args.parts_per_cu, th, g) for _, th, g in capi.mttkrp_batch_autotune_default_shapes(N)})
+        else:
+            cands = None
+        best, times = capi.mttkrp_autotune_shape(h, R, dF, outs, candidates=cands, reps=3, stream=stream)
+        info = capi.mttkrp_layout_info(h)
+        ms = sorted(times.values())
+        dflt = times.get(default_shape(N, R))
+        launch_shape = {"parts_per_cu": best[0], "wg_threads": info["wg_threads"],
+                        "gathers_in_flight": info["gathers_in_flight"],
+                        "source": "--shape" if args.shape else "mttkrp_autotune_shape",
+                        "candidates": len(times),
+                        "all_mode_ms": {"chosen": round(times[best], 4), "fastest": round(ms[0], 4),
+                                        "median": round(ms[len(ms) // 2], 4), "slowest": round(ms[-1], 4),
+                                        "default_shape": round(dflt, 4) if dflt else None},
+                        "tuning_s": round(time.perf_counter() - t_t, 2)}
+        print(f"[bench] launch shape {launch_shape}", file=sys.stderr, flush=True)
+
     def all_modes(ev=None, hh=None):
         for n in range(N):
             if ev is not None:
@@ -819,6 +854,7 @@ def main(argv=None):
                      "bytes_per_mode": bytes_mode},
         "build_s": round(build_s, 2),
         "launch": capi.mttkrp_layout_info(h),
+        "launch_shape": launch_shape,
         "layout": ("hot-steps copies (rows ordered by hot/cold input rows, padded to wave steps; built on the host)"
                    if steps else "nonzero-ordered copies"),
     }

@@ -360,10 +360,21 @@ mttkrp_status mttkrp_batch_autotune_shape(const mttkrp_handle* layouts, int coun
                                           const float* const* factors, float* const* outs, int reps,
                                           hipStream_t stream, mttkrp_part_shape* best, float* times_ms);
 
-/* The default candidates of mttkrp_batch_autotune_shape for N-mode tensors
- * (parts_per_cu 1, 2, 4, 8, 16; for N = 3 each with threads 256, 512, 1024 and
- * gathers 2, 4): written to out when it is not NULL (room for 30); returns
- * their number. */
+/* The same for one layout: each candidate is timed as `reps` passes of
+ * mttkrp_run along every mode (fp32 factors) after a warm-up pass, and the
+ * fastest stays set on h (mttkrp_run and cpd_als_iter then use it).
+ * Synchronises the stream.  MTTKRP_EUNSUPPORTED on hot-steps copies.
+ *   factors: host array of N device pointers (I_m x R fp32)
+ *   outs:    host array of N device pointers, the mode-n output (I_n x R fp32,
+ *            overwritten) at [n] */
+mttkrp_status mttkrp_autotune_shape(mttkrp_handle h, int R, const mttkrp_part_shape* candidates, int n_candidates,
+                                    const float* const* factors, float* const* outs, int reps, hipStream_t stream,
+                                    mttkrp_part_shape* best, float* times_ms);
+
+/* The default candidates of mttkrp_batch_autotune_shape and
+ * mttkrp_autotune_shape for N-mode tensors (parts_per_cu 1, 2, 4, 8, 16, 32;
+ * for N = 3 each with threads 256, 512, 1024 and gathers 2, 4): written to out
+ * when it is not NULL (room for 36); returns their number. */
 int mttkrp_batch_autotune_default_shapes(int N, mttkrp_part_shape* out);
 
 /* Release a batch (not its layouts).  A batch that allocated its own device

@@ -33,7 +33,7 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
             "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes", "mttkrp_batch_create_in",
             "mttkrp_run_noalloc", "mttkrp_noalloc_scratch_bytes", "mttkrp_lpt_partition", "mttkrp_batch_run_bf16",
-            "mttkrp_batch_autotune_shape", "mttkrp_batch_autotune_default_shapes"]
+            "mttkrp_batch_autotune_shape", "mttkrp_batch_autotune_default_shapes", "mttkrp_autotune_shape"]
 
 
 class MttkrpError(RuntimeError):
@@ -123,6 +123,9 @@ def _load():
                                                 ctypes.POINTER(mttkrp_part_shape), ctypes.c_int, ctypes.POINTER(vp),
                                                 ctypes.POINTER(vp), ctypes.c_int, vp,
                                                 ctypes.POINTER(mttkrp_part_shape), ctypes.POINTER(ctypes.c_float)]
+    lib.mttkrp_autotune_shape.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mttkrp_part_shape), ctypes.c_int,
+                                          ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
+                                          ctypes.POINTER(mttkrp_part_shape), ctypes.POINTER(ctypes.c_float)]
     lib.mttkrp_batch_autotune_default_shapes.argtypes = [ctypes.c_int, ctypes.POINTER(mttkrp_part_shape)]
     lib.mttkrp_batch_autotune_default_shapes.restype = ctypes.c_int
     lib.mttkrp_gather_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
@@ -145,7 +148,7 @@ def _load():
                  "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
                  "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes",
                  "mttkrp_batch_create_in", "mttkrp_run_noalloc", "mttkrp_lpt_partition", "mttkrp_batch_run_bf16",
-                 "mttkrp_batch_autotune_shape"):
+                 "mttkrp_batch_autotune_shape", "mttkrp_autotune_shape"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -563,6 +566,22 @@ def mttkrp_batch_autotune_shape(layouts, R: int, factors, outs, candidates=None,
     best = mttkrp_part_shape()
     _check(_lib.mttkrp_batch_autotune_shape(arr, count, int(R), carr, len(cands), fac, out, int(reps),
                                             ctypes.c_void_p(_stream(stream)), ctypes.byref(best), times))
+    return (best.parts_per_cu, best.threads, best.gathers), {c: float(times[i]) for i, c in enumerate(cands)}
+
+
+def mttkrp_autotune_shape(h: Layout, R: int, factors, outs, candidates=None, reps: int = 3, stream=None):
+    """Time mttkrp_run along every mode for each candidate launch shape
+    (parts_per_cu, threads, gathers) on one layout, leave the fastest set and
+    return ``(best, {shape: ms})``; candidates None = the library's defaults.
+    factors, outs: N fp32 device tensors each (outs[n] of shape (I_n, R))."""
+    count, arr, fac, out = _autotune_args([h], R, [factors], [outs])
+    cands = ([tuple(c) for c in candidates] if candidates is not None
+             else mttkrp_batch_autotune_default_shapes(len(h.dims)))
+    carr = (mttkrp_part_shape * len(cands))(*[mttkrp_part_shape(*c) for c in cands])
+    times = (ctypes.c_float * len(cands))()
+    best = mttkrp_part_shape()
+    _check(_lib.mttkrp_autotune_shape(ctypes.c_void_p(h.ptr), int(R), carr, len(cands), fac, out, int(reps),
+                                      ctypes.c_void_p(_stream(stream)), ctypes.byref(best), times))
     return (best.parts_per_cu, best.threads, best.gathers), {c: float(times[i]) for i, c in enumerate(cands)}
 
 

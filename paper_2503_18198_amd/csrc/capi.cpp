@@ -1332,11 +1332,11 @@ mttkrp_status mttkrp_batch_run_bf16(mttkrp_batch_handle b, int mode, const uint1
 }  // extern "C"
 
 // The autotuner's default candidates for N-mode tensors: parts_per_cu 1 to
-// 16, and for 3-mode tensors every tuned workgroup size and gathers in flight.
+// 32, and for 3-mode tensors every tuned workgroup size and gathers in flight.
 static std::vector<mttkrp_part_shape> default_shapes(int N)
 {
     std::vector<mttkrp_part_shape> c;
-    for (int ppc : {1, 2, 4, 8, 16}) {
+    for (int ppc : {1, 2, 4, 8, 16, 32}) {
         if (N != 3) {
             c.push_back({ppc, 0, 0});
             continue;
@@ -1348,13 +1348,14 @@ static std::vector<mttkrp_part_shape> default_shapes(int N)
 }
 
 // The autotuner behind mttkrp_batch_autotune (set_shape false: candidates
-// change parts_per_cu only) and mttkrp_batch_autotune_shape.  Each candidate
-// is set on every layout, a batch is built and `reps` all-mode passes are
-// timed after a warm-up pass; the fastest candidate stays set.
+// change parts_per_cu only), mttkrp_batch_autotune_shape and (single: one
+// layout timed through mttkrp_run) mttkrp_autotune_shape.  Each candidate is
+// set on every layout, a batch is built unless single, and `reps` all-mode
+// passes are timed after a warm-up pass; the fastest candidate stays set.
 static mttkrp_status autotune_impl(const mttkrp_handle* layouts, int count, int R,
                                    const std::vector<mttkrp_part_shape>& cands, bool set_shape,
                                    const float* const* factors, float* const* outs, int reps, hipStream_t stream,
-                                   int* best_out, float* times_ms)
+                                   int* best_out, float* times_ms, bool single = false)
 {
     if (!layouts || count <= 0 || !factors || !outs) return fail(MTTKRP_EINVAL, "NULL layouts, factors or outs");
     if (cands.empty()) return fail(MTTKRP_EINVAL, "need at least one candidate");
@@ -1400,12 +1401,18 @@ static mttkrp_status autotune_impl(const mttkrp_handle* layouts, int count, int 
     for (size_t i = 0; i < cands.size() && st == MTTKRP_OK; ++i) {
         for (int t = 0; t < count; ++t) apply(t, cands[i]);
         mttkrp_batch_handle b = nullptr;
-        st = mttkrp_batch_create(layouts, count, R, nullptr, &b);
-        if (st) break;
+        if (!single) {
+            st = mttkrp_batch_create(layouts, count, R, nullptr, &b);
+            if (st) break;
+        }
         float ms = 0.0f;
         for (int pass = 0; pass <= reps && st == MTTKRP_OK; ++pass) {
             if (pass == 1) e = hipEventRecord(ev[0], stream);
             for (int n = 0; n < N && st == MTTKRP_OK; ++n) {
+                if (single) {
+                    st = mttkrp_run(layouts[0], n, factors, outs[n], R, stream);
+                    continue;
+                }
                 for (int t = 0; t < count; ++t) mode_outs[t] = outs[(size_t)t * N + n];
                 st = mttkrp_batch_run(b, n, factors, mode_outs.data(), stream);
             }
@@ -1476,6 +1483,30 @@ mttkrp_status mttkrp_batch_autotune_shape(const mttkrp_handle* layouts, int coun
     }
     int k = 0;
     mttkrp_status st = autotune_impl(layouts, count, R, c, true, factors, outs, reps, stream, &k, times_ms);
+    if (st) return st;
+    *best = c[k];
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_autotune_shape(mttkrp_handle h, int R, const mttkrp_part_shape* candidates, int n_candidates,
+                                    const float* const* factors, float* const* outs, int reps, hipStream_t stream,
+                                    mttkrp_part_shape* best, float* times_ms)
+{
+    g_err.clear();
+    if (!best) return fail(MTTKRP_EINVAL, "NULL best");
+    if (!h) return fail(MTTKRP_EINVAL, "NULL handle");
+    if (h->host_only) return fail(MTTKRP_EINVAL, "host-only handle: build without host_only to run");
+    if (h->opts.hot_steps)
+        return fail(MTTKRP_EUNSUPPORTED, "hot-steps copies have one launch shape; there is nothing to tune");
+    std::vector<mttkrp_part_shape> c;
+    if (candidates) {
+        if (n_candidates <= 0) return fail(MTTKRP_EINVAL, "need at least one candidate");
+        c.assign(candidates, candidates + n_candidates);
+    } else {
+        c = default_shapes(h->N);
+    }
+    int k = 0;
+    mttkrp_status st = autotune_impl(&h, 1, R, c, true, factors, outs, reps, stream, &k, times_ms, true);
     if (st) return st;
     *best = c[k];
     return MTTKRP_OK;

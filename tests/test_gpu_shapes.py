@@ -136,7 +136,7 @@ def test_shape_autotuner_sets_its_choice():
             assert gu.rel_fro(o[i].cpu().numpy(), gu.oracle_mttkrp(t.idx, t.val, t.dims, F[i], n)) <= TOL
     b.free()
     defaults = capi.mttkrp_batch_autotune_default_shapes(3)
-    assert len(defaults) == 30 and (8, 512, 4) in defaults
+    assert len(defaults) == 36 and (8, 512, 4) in defaults
     for h in hs:
         h.free()
 
@@ -179,3 +179,29 @@ def test_cp_als_on_a_tuned_layout_matches_oracle():
     st = oracle.cp_als(t.idx, t.val, t.dims, F0, n_iter=4, threads=8)
     assert max(abs(a - b) for a, b in zip(fits, st.fits)) <= 1e-5
     h.free()
+
+
+def test_single_layout_shape_autotuner():
+    """mttkrp_autotune_shape on one layout: the fastest candidate is set and
+    mttkrp_run then matches the oracle and repeats bitwise; refused on
+    hot-steps copies."""
+    print("case shape autotune single", flush=True)
+    R = 32
+    t, F, refs = case(R)
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R))
+    dF = gu.dev_factors(F)
+    outs = [torch.empty((d, R), device="cuda") for d in t.dims]
+    cands = [(16, 256, 4), (8, 0, 0), (4, 1024, 2)]
+    best, times = capi.mttkrp_autotune_shape(h, R, dF, outs, candidates=cands, reps=2)
+    assert best in cands and times[best] == min(times.values())
+    info = capi.mttkrp_layout_info(h)
+    assert (info["parts_per_cu"], info["wg_threads"]) == (best[0], best[1] or 512)
+    for n in range(3):
+        a = gu.gpu_mttkrp(h, n, dF, R)
+        assert np.array_equal(a.view(np.uint32), gu.gpu_mttkrp(h, n, dF, R).view(np.uint32))
+        assert gu.rel_fro(a, refs[n]) <= TOL
+    h.free()
+    hs = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, hot_steps=1))
+    with pytest.raises(capi.MttkrpError):
+        capi.mttkrp_autotune_shape(hs, R, dF, outs, candidates=cands, reps=1)
+    hs.free()

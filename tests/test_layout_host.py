@@ -316,6 +316,6 @@ def test_tuned_shape_options():
     h = capi.mttkrp_layout_build(t4, v, dims + (50,), opts=dict(host_only=1, part_threads=1024))
     assert capi.mttkrp_layout_info(h)["wg_threads"] == 256           # 4 modes: the default kernels
     d3 = capi.mttkrp_batch_autotune_default_shapes(3)
-    assert len(d3) == 30 and len(set(d3)) == 30
+    assert len(d3) == 36 and len(set(d3)) == 36
     assert {s[1] for s in d3} == {256, 512, 1024} and {s[2] for s in d3} == {2, 4}
-    assert capi.mttkrp_batch_autotune_default_shapes(5) == [(p, 0, 0) for p in (1, 2, 4, 8, 16)]
+    assert capi.mttkrp_batch_autotune_default_shapes(5) == [(p, 0, 0) for p in (1, 2, 4, 8, 16, 32)]

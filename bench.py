@@ -64,14 +64,16 @@ def default_shape(N, R):
     return (8, 512, 2 if R == 16 else 4) if N == 3 else (8, 0, 0)
 
 
-def algorithmic_bytes(dims, nnz, R, factor_bytes=4):
-    """Bytes a mode's MTTKRP must move: the mode copy's indices and values, a
-    4-byte row pointer per output row, each input factor read once, the
-    output written once."""
+def algorithmic_bytes(dims, nnz, R, factor_bytes=4, idx16_modes=0):
+    """Bytes a mode's MTTKRP must move: the mode copy's indices (4 bytes each,
+    2 in the copies of output modes whose bit is set in idx16_modes) and
+    values, a 4-byte row pointer per output row, each input factor read once,
+    the output written once."""
     N = len(dims)
     per_mode = []
     for n in range(N):
-        b = nnz * (4 * (N - 1) + 4) + 4 * (dims[n] + 1)
+        ib = 2 if idx16_modes >> n & 1 else 4
+        b = nnz * (ib * (N - 1) + 4) + 4 * (dims[n] + 1)
         b += sum(dims[m] * R * factor_bytes for m in range(N) if m != n)
         b += dims[n] * R * 4
         per_mode.append(b)
@@ -313,8 +315,27 @@ def bench_batch(args, R=16, count=256):
     same = all(float(f.item()) == fg for f, fg in zip(fit, fits_graph))
     del g
 
+    # The same batch on copies with 32-bit coordinates (wide_indices=1) and the
+    # same launch shape: what the 16-bit coordinates are worth here.
+    info0 = capi.mttkrp_layout_info(hs[0])
+    shape_opts = dict(max_R=R, wide_indices=1, parts_per_cu=info0["parts_per_cu"], part_threads=info0["wg_threads"],
+                      part_gathers=info0["gathers_in_flight"])
+    hw = [capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=shape_opts, stream=stream) for t in ts]
+    bw = capi.mttkrp_batch_create(hw, R)
+
+    def batched_wide(st=stream):
+        for n in range(3):
+            capi.mttkrp_batch_run(bw, n, F, [o[n] for o in outs], stream=st)
+
+    ms_wide = graphed(batched_wide, args.steps)
+    bw.free()
+    for h in hw:
+        h.free()
+    idx16 = sum(capi.mttkrp_layout_info(h)["idx16_modes"] == 0b111 for h in hs)
+
     flops = sum(3 * R * t.nnz * 3 for t in ts)
-    byts = sum(sum(algorithmic_bytes(t.dims, t.nnz, R)) for t in ts)
+    byts = sum(sum(algorithmic_bytes(t.dims, t.nnz, R, idx16_modes=capi.mttkrp_layout_info(h)["idx16_modes"]))
+               for t, h in zip(ts, hs))
     res = {
         "metric": "batched all-mode spMTTKRP (tensors x all modes per second)",
         "value": round(count / (ms_b / 1e3), 1),
@@ -329,6 +350,8 @@ def bench_batch(args, R=16, count=256):
         "timing": "one step = 3 modes; both methods replayed from a HIP graph of one step",
         "plain_ms_per_step": round(ms_p, 4),
         "batched_speedup_vs_plain": round(ms_p / ms_b, 3),
+        "coords_16bit": {"tensors_with_16bit_copies": idx16, "ms_per_step_with_32bit_coords": round(ms_wide, 4),
+                         "speedup": round(ms_wide / ms_b, 3)},
         "eager_launch_ms_per_step": {"batched": round(ms_b_eager, 4), "plain": round(ms_p_eager, 4)},
         "gflops": round(flops / (ms_b / 1e3) / 1e9, 1),
         "hbm_pct_peak": round(100.0 * byts / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
@@ -391,7 +414,8 @@ def bench_precision(args):
         for name, dF, run, fb in (("fp32", d32, capi.mttkrp_run, 4), ("bf16", d16, capi.mttkrp_run_bf16, 2)):
             ms = per_mode_ms(lambda n: run(h, n, dF, outs[n], R, stream=stream))
             probe = per_mode_ms(lambda n: capi.mttkrp_gather_probe(h, n, dF, R, 1, stream=stream))
-            byts = algorithmic_bytes(t.dims, t.nnz, R, factor_bytes=fb)
+            byts = algorithmic_bytes(t.dims, t.nnz, R, factor_bytes=fb,
+                                     idx16_modes=capi.mttkrp_layout_info(h)["idx16_modes"])
             flops = N * R * t.nnz * N
             by[f"{name}_R{R}"] = {
                 "ms_all_modes": round(sum(ms), 4), "per_mode_ms": [round(x, 4) for x in ms],
@@ -450,13 +474,23 @@ def bench_paper_shapes(args, R=32):
                                     progress=lambda m: print(f"[bench] {name}: {m}", file=sys.stderr, flush=True))
         gen_s = time.perf_counter() - t0
         N = len(t.dims)
-        h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R), stream=stream)
+        # 32-bit coordinates in every column (scheme-1 copies have no 16-bit
+        # form), so that only the partitioning differs.
+        h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, wide_indices=1), stream=stream)
         kappa = capi.mttkrp_layout_info(h)["cu_count"]
         t1 = time.perf_counter()
         h1 = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, partitioner=capi.MTTKRP_PART_ROWS_LPT,
                                                                       lpt_parts=kappa), stream=stream)
         lpt_build_s = time.perf_counter() - t1
         dF = [torch.from_numpy(f).cuda() for f in workloads.random_factors(t.dims, R, seed=7)]
+        # Scheme 1's balance per mode: LPT's largest partition load over the
+        # mean, and the heaviest row's share of the nonzeros.
+        lpt_ratio, heavy_pct = [], []
+        for n in range(N):
+            loads = np.bincount(t.idx[:, n].astype(np.int64), minlength=dims[n]).astype(np.uint64)
+            _, pl = capi.mttkrp_lpt_partition(loads, kappa)
+            lpt_ratio.append(round(float(pl.max()) / (float(pl.sum()) / kappa), 2))
+            heavy_pct.append(round(100.0 * float(loads.max()) / max(t.nnz, 1), 2))
         del t
         out = {k: [torch.empty((d, R), device="cuda") for d in dims] for k in ("nnz", "s2", "s1")}
 
@@ -490,6 +524,7 @@ def bench_paper_shapes(args, R=32):
         rows[name] = {
             "dims": list(dims), "nnz": int(nnz), "gen_s": round(gen_s, 1), "lpt_build_s": round(lpt_build_s, 2),
             "ms_per_mode": {k: [round(x, 4) for x in v] for k, v in ms.items()},
+            "lpt_load_max_over_mean": lpt_ratio, "heaviest_row_pct": heavy_pct,
             "adaptive_choice": ["scheme1" if dims[n] >= kappa else "scheme2" for n in range(N)],
             "ms_all_modes": {k: round(v, 4) for k, v in tot.items()},
             "speedup_vs_adaptive": {k: round(tot["adaptive_paper"] / v, 3) for k, v in tot.items()},
@@ -596,7 +631,7 @@ def bench_serve(args, base, rhos=(0.5, 0.8, 0.95, 2.0), slot_list=None):
         return retired
 
     def serve(js, batched, slots, build_threads):
-        srv = CpdServer(GpuExecutor(batched=batched), budget, max_slots=slots, build_threads=build_threads,
+        srv = CpdServer(GpuExecutor(batched=batched, wide_indices=args.wide_indices), budget, max_slots=slots, build_threads=build_threads,
                         on_retire=progress(f"{slots} slot(s)"))
         srv.run(js)
         return timed_metrics(srv, js)
@@ -604,11 +639,11 @@ def bench_serve(args, base, rhos=(0.5, 0.8, 0.95, 2.0), slot_list=None):
     budget = int(args.serve_budget_gib * (1 << 30))
     # warm-up (allocations, first launches), then the plain method's capacity:
     # every job present at time 0, one at a time
-    CpdServer(GpuExecutor(batched=True), budget, max_slots=64, build_threads=args.serve_build_threads).run(
+    CpdServer(GpuExecutor(batched=True, wide_indices=args.wide_indices), budget, max_slots=64, build_threads=args.serve_build_threads).run(
         clone(base[:8], 0.0))
     t0 = time.perf_counter()
     cap_jobs = clone(base, 0.0)
-    cap_srv = CpdServer(GpuExecutor(batched=False), budget, max_slots=1, on_retire=progress("capacity"))
+    cap_srv = CpdServer(GpuExecutor(batched=False, wide_indices=args.wide_indices), budget, max_slots=1, on_retire=progress("capacity"))
     cap_srv.run(cap_jobs)
     mean_service = max(j.finished_s for j in cap_jobs) / n_jobs
     print(f"[bench] plain capacity {1.0 / mean_service:.2f} jobs/s ({time.perf_counter() - t0:.0f}s, "
@@ -637,7 +672,8 @@ def bench_serve(args, base, rhos=(0.5, 0.8, 0.95, 2.0), slot_list=None):
                                f"dims log-U[1e2,1e5], nnz log-U[1e4,1e7] ({nnzs.sum() / 1e6:.0f}M in all), "
                                f"Zipf(1.2), R in {{16,32,64}}, stop at |dfit|<1e-4 or 50 sweeps, offered load "
                                f"rho x plain capacity for rho in {list(rhos)}, HBM budget {args.serve_budget_gib:g} GiB, slots "
-                               f"{slot_list}, {args.serve_build_threads} layout-build threads; value = "
+                               f"{slot_list}, {args.serve_build_threads} layout-build threads, "
+                               f"{'32-bit coordinates' if args.wide_indices else '16-bit coordinates where dims fit'}; value = "
                                f"served jobs/s at the highest load with {slot_list[0]} slots; "
                                f"ms_per_step = ms per served job"},
         "by_offered_load": loads,
@@ -657,6 +693,8 @@ def main(argv=None):
     ap.add_argument("--parts-per-cu", type=int, default=0)
     ap.add_argument("--shape", default="",
                     help="fixed launch shape PPC,THREADS,GATHERS of the nonzero-ordered copies (no tuning)")
+    ap.add_argument("--wide-indices", action="store_true",
+                    help="serve-poisson: build every job's copies with 32-bit coordinates")
     ap.add_argument("--no-tune-shape", action="store_true",
                     help="time the library's default launch shape instead of the autotuned one")
     ap.add_argument("--kernel", choices=("steps", "nonzero"), default="nonzero",
@@ -821,7 +859,7 @@ def main(argv=None):
 
     flops = N * R * t.nnz * N
     gflops = flops / (ms_step / 1e3) / 1e9
-    bytes_mode = algorithmic_bytes(t.dims, t.nnz, R)
+    bytes_mode = algorithmic_bytes(t.dims, t.nnz, R, idx16_modes=capi.mttkrp_layout_info(h)["idx16_modes"])
     achieved = sum(bytes_mode) / (sum(mode_ms) / 1e3) / 1e9
     result = {
         "metric": METRIC,
@@ -927,7 +965,7 @@ def main(argv=None):
         # The second half of the metric: batched requests/s and served p50/p99
         # latency, on the batching and serving workloads, as sub-objects.
         result["batch"] = _sub(bench_batch(args), ("metric", "value", "unit", "ms_per_step", "config",
-                                                   "launch_shape", "plain_ms_per_step", "batched_speedup_vs_plain",
+                                                   "launch_shape", "plain_ms_per_step", "batched_speedup_vs_plain", "coords_16bit",
                                                    "eager_launch_ms_per_step", "gflops", "hbm_pct_peak",
                                                    "als_20_sweeps", "build_s"))
         torch.cuda.empty_cache()

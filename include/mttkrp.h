@@ -328,14 +328,16 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
  * partitions per SM, Sec. III-B; here the size is measured, not modelled):
  * for each candidate parts_per_cu, set it on every layout, build the batch and
  * time `reps` batched all-mode MTTKRP passes after one warm-up pass, with HIP
- * events on `stream`.  The fastest candidate stays set on the layouts (so
- * mttkrp_run, cpd_als_iter and later batches use it; results change by
+ * events on `stream`.  With more than 4 candidates the 4 fastest are timed
+ * again over 4 x reps passes.  The fastest candidate stays set on the layouts
+ * (so mttkrp_run, cpd_als_iter and later batches use it; results change by
  * rounding only) and is returned.  Synchronises the stream.
  *   candidates: n_candidates values in [1, 64]; NULL = {1, 2, 4, 8, 16}
  *   factors:    host array of count * N device pointers, as mttkrp_batch_run
  *   outs:       host array of count * N device pointers, tensor t's mode-n
  *               output (I_n x R fp32, overwritten) at [t * N + n]
  *   times_ms:   NULL or one float per candidate: time of one all-mode pass
+ *               (for the 4 finalists, from the second timing)
  *   best_ppc:   out: the chosen parts_per_cu */
 mttkrp_status mttkrp_batch_autotune(const mttkrp_handle* layouts, int count, int R, const int* candidates,
                                     int n_candidates, const float* const* factors, float* const* outs, int reps,

@@ -1351,7 +1351,8 @@ static std::vector<mttkrp_part_shape> default_shapes(int N)
 // change parts_per_cu only), mttkrp_batch_autotune_shape and (single: one
 // layout timed through mttkrp_run) mttkrp_autotune_shape.  Each candidate is
 // set on every layout, a batch is built unless single, and `reps` all-mode
-// passes are timed after a warm-up pass; the fastest candidate stays set.
+// passes are timed after a warm-up pass; the fastest four are timed again
+// over 4 x reps passes and the fastest of those stays set.
 static mttkrp_status autotune_impl(const mttkrp_handle* layouts, int count, int R,
                                    const std::vector<mttkrp_part_shape>& cands, bool set_shape,
                                    const float* const* factors, float* const* outs, int reps, hipStream_t stream,
@@ -1395,43 +1396,55 @@ static mttkrp_status autotune_impl(const mttkrp_handle* layouts, int count, int 
         return hip_fail(e, "autotune events");
     }
     std::vector<float*> mode_outs(count);
-    int best = -1;
-    float best_ms = 0.0f;
     mttkrp_status st = MTTKRP_OK;
-    for (size_t i = 0; i < cands.size() && st == MTTKRP_OK; ++i) {
+    // Average time of one all-mode pass of candidate i over r timed passes.
+    auto time_candidate = [&](size_t i, int r, float* ms) -> mttkrp_status {
         for (int t = 0; t < count; ++t) apply(t, cands[i]);
         mttkrp_batch_handle b = nullptr;
+        mttkrp_status s2 = MTTKRP_OK;
         if (!single) {
-            st = mttkrp_batch_create(layouts, count, R, nullptr, &b);
-            if (st) break;
+            s2 = mttkrp_batch_create(layouts, count, R, nullptr, &b);
+            if (s2) return s2;
         }
-        float ms = 0.0f;
-        for (int pass = 0; pass <= reps && st == MTTKRP_OK; ++pass) {
-            if (pass == 1) e = hipEventRecord(ev[0], stream);
-            for (int n = 0; n < N && st == MTTKRP_OK; ++n) {
+        hipError_t e2 = hipSuccess;
+        for (int pass = 0; pass <= r && s2 == MTTKRP_OK; ++pass) {
+            if (pass == 1) e2 = hipEventRecord(ev[0], stream);
+            for (int n = 0; n < N && s2 == MTTKRP_OK; ++n) {
                 if (single) {
-                    st = mttkrp_run(layouts[0], n, factors, outs[n], R, stream);
+                    s2 = mttkrp_run(layouts[0], n, factors, outs[n], R, stream);
                     continue;
                 }
                 for (int t = 0; t < count; ++t) mode_outs[t] = outs[(size_t)t * N + n];
-                st = mttkrp_batch_run(b, n, factors, mode_outs.data(), stream);
+                s2 = mttkrp_batch_run(b, n, factors, mode_outs.data(), stream);
             }
         }
-        if (st == MTTKRP_OK) {
-            e = hipEventRecord(ev[1], stream);
-            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-            if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+        if (s2 == MTTKRP_OK) {
+            if (e2 == hipSuccess) e2 = hipEventRecord(ev[1], stream);
+            if (e2 == hipSuccess) e2 = hipEventSynchronize(ev[1]);
+            if (e2 == hipSuccess) e2 = hipEventElapsedTime(ms, ev[0], ev[1]);
+            if (e2 != hipSuccess) s2 = hip_fail(e2, "autotune timing");
         }
         mttkrp_batch_free(b);
-        if (st) break;
-        ms /= (float)reps;
-        if (times_ms) times_ms[i] = ms;
-        if (best < 0 || ms < best_ms) {
-            best = (int)i;
-            best_ms = ms;
-        }
+        *ms /= (float)r;
+        return s2;
+    };
+    // Two stages: every candidate at `reps` passes, then (when there are
+    // more than kFinal) the kFinal fastest again at 4 x reps passes, so that
+    // candidates within timing noise of each other are told apart.
+    constexpr size_t kFinal = 4;
+    std::vector<float> ms(cands.size(), 0.0f);
+    for (size_t i = 0; i < cands.size() && st == MTTKRP_OK; ++i) st = time_candidate(i, reps, &ms[i]);
+    std::vector<size_t> order(cands.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return ms[x] < ms[y]; });
+    if (st == MTTKRP_OK && cands.size() > kFinal) {
+        order.resize(kFinal);
+        for (size_t k = 0; k < kFinal && st == MTTKRP_OK; ++k) st = time_candidate(order[k], 4 * reps, &ms[order[k]]);
     }
+    int best = -1;
+    for (size_t k = 0; k < order.size() && st == MTTKRP_OK; ++k)
+        if (best < 0 || ms[order[k]] < ms[best]) best = (int)order[k];
+    if (st == MTTKRP_OK && times_ms) std::copy(ms.begin(), ms.end(), times_ms);
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (st) {

@@ -317,22 +317,24 @@ class GpuExecutor(Executor):
     waits are on one stream: a retiring group's stream before its results are
     read back, and the build's own stream."""
 
-    def __init__(self, batched: bool = True):
+    def __init__(self, batched: bool = True, wide_indices: bool = False):
         import torch
 
         from . import capi
         self.torch = torch
         self.capi = capi
         self.batched = batched
+        # Layout options of every job (wide_indices: 32-bit coordinates in all copies).
+        self.opts = dict(wide_indices=int(wide_indices))
         self._batches: Dict[Tuple[int, int], Tuple[tuple, object]] = {}   # group -> (member ids, batch)
         self._groups: Dict[Tuple[int, int], dict] = {}    # group -> stream, event, fit buffers
 
     def footprint(self, job: ServeJob) -> int:
-        lib = self.capi.mttkrp_footprint(job.dims, job.nnz, opts=dict(max_R=job.R))
+        lib = self.capi.mttkrp_footprint(job.dims, job.nnz, opts=dict(max_R=job.R, **self.opts))
         return lib + sum(int(d) * job.R * 4 for d in job.dims) + 16 * job.R
 
     def build_bytes(self, job: ServeJob) -> int:
-        return self.capi.mttkrp_build_scratch_bytes(job.dims, job.nnz, opts=dict(max_R=job.R))
+        return self.capi.mttkrp_build_scratch_bytes(job.dims, job.nnz, opts=dict(max_R=job.R, **self.opts))
 
     def _bytes(self, n: int):
         # 256-byte aligned by torch's allocator
@@ -340,7 +342,7 @@ class GpuExecutor(Executor):
 
     def admit(self, job: ServeJob):
         torch = self.torch
-        opts = dict(max_R=job.R)
+        opts = dict(max_R=job.R, **self.opts)
         mem = self._bytes(self.capi.mttkrp_footprint(job.dims, job.nnz, opts=opts))
         nscr = self.capi.mttkrp_build_scratch_bytes(job.dims, job.nnz, opts=opts)
         scratch = self._bytes(nscr) if nscr else None

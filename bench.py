@@ -923,6 +923,8 @@ def main(argv=None):
             return [x / K for x in tot]
         stream_ms = probe_ms(0)
         gather_ms = probe_ms(1)
+        one_lane_ms = probe_ms(2)
+        l1_ms = probe_ms(3)
         gbytes = [t.nnz * (N - 1) * R * 4 for _ in range(N)]
         result["gather_ceiling"] = {
             "stream_only_ms_per_mode": [round(x, 4) for x in stream_ms],
@@ -931,8 +933,12 @@ def main(argv=None):
             "gathered_TBps_in_probe": round(sum(gbytes) / (sum(gather_ms) / 1e3) / 1e12, 2),
             "gathered_TBps_in_mttkrp": round(sum(gbytes) / (sum(mode_ms0) / 1e3) / 1e12, 2),
             "mttkrp_time_over_probe_time": round(sum(mode_ms0) / sum(gather_ms), 3),
-            "what": "mttkrp_gather_probe on the nonzero-ordered copies: their MTTKRP's stream loads and factor-row "
-                    "gathers on the same partitions and lanes, arithmetic and stores replaced by an XOR fold",
+            "same_gathers_one_lane_per_row_ms_per_mode": [round(x, 4) for x in one_lane_ms],
+            "same_gathers_l1_resident_rows_ms_per_mode": [round(x, 4) for x in l1_ms],
+            "what": "mttkrp_gather_probe on the nonzero-ordered copies (default launch shape): their MTTKRP's "
+                    "stream loads and factor-row gathers on the same partitions and lanes, arithmetic and stores "
+                    "replaced by an XOR fold; the same gather instructions with one lane of each row's group "
+                    "reading (1/L of the bytes), and with every row L1-resident (row index & 63)",
         }
 
     # CP-ALS sweeps (MTTKRP plus the FP64 update), timed separately.

@@ -229,7 +229,10 @@ mttkrp_status mttkrp_run_scheme2(mttkrp_handle h, int mode, const float* const* 
  * with the same partitions, lane groups and loads as mttkrp_run (fp32) or
  * mttkrp_run_bf16, but the products, row sums, stores and fix-up replaced by
  * an XOR fold of the loaded bits.  what = 0 streams the mode copy only;
- * what = 1 also gathers every factor row the nonzeros name.
+ * what = 1 also gathers every factor row the nonzeros name; what = 2 issues
+ * the same gather instructions with one lane of each row's lane group
+ * reading (1/L of the bytes); what = 3 gathers row (index & 63) in place of
+ * row index, so every gather hits rows resident in L1.
  *   factors:      host array of N device pointers (factors[mode] unused), rows
  *                 of R fp32 values (factor_dtype MTTKRP_FP32) or R bf16 bit
  *                 patterns (MTTKRP_BF16)

@@ -345,9 +345,11 @@ def mttkrp_run_bf16(h: Layout, mode: int, factors, out, R: Optional[int] = None,
 
 
 def mttkrp_gather_probe(h: Layout, mode: int, factors, R: int, what: int = 1, stream=None):
-    """Measurement aid: the stream (what=0) or stream and row gathers (what=1)
-    of the MTTKRP along ``mode`` without its arithmetic or stores.  ``factors``
-    are fp32 or bfloat16 device tensors (all the same dtype)."""
+    """Measurement aid: the stream (what=0), stream and row gathers (what=1),
+    the same gather instructions with one lane per row reading (what=2) or
+    with L1-resident rows (what=3), of the MTTKRP along ``mode`` without its
+    arithmetic or stores.  ``factors`` are fp32 or bfloat16 device tensors
+    (all the same dtype)."""
     import torch
     N = len(h.dims)
     if not 0 <= int(mode) < N:

@@ -841,7 +841,9 @@ mttkrp_status mttkrp_gather_probe(mttkrp_handle h, int mode, const void* const* 
     g_err.clear();
     if (factor_dtype != MTTKRP_FP32 && factor_dtype != MTTKRP_BF16)
         return fail(MTTKRP_EINVAL, "factor_dtype must be MTTKRP_FP32 or MTTKRP_BF16");
-    if (what != 0 && what != 1) return fail(MTTKRP_EINVAL, "what must be 0 (stream) or 1 (stream and gathers)");
+    if (what < 0 || what > 3)
+        return fail(MTTKRP_EINVAL, "what must be 0 (stream), 1 (stream and gathers), 2 (one lane per row "
+                                   "gathering) or 3 (L1-resident rows)");
     if (!h) return fail(MTTKRP_EINVAL, "NULL handle");
     if (h->opts.partitioner == MTTKRP_PART_ROWS_LPT || h->opts.hot_steps)
         return fail(MTTKRP_EUNSUPPORTED, "the gather probe runs the nonzero-balanced partitions only");

@@ -86,66 +86,154 @@ struct FixArgs {
     const uint2* winfo;
     const uint32_t* row_id;
     const uint32_t* empty_rows;
-    const float* carry;
+    float* carry;
     float* out;
     uint64_t wgc;          // nonzeros per workgroup partition
     uint32_t nparts;
-    uint32_t nbound;       // workgroups of this grid that handle partition boundaries
+    uint32_t nbound;       // partition boundaries (nparts - 1, or 0 when no row is cut)
     uint64_t nempty;
     int R;
+    int phase;             // 0: one pass; 1 then 2: chunk sums, then rows (see fixup_body)
 };
 
 constexpr int kEmptyPerBlock = 64;
+constexpr int kBoundsPerBlock = kWG / 64;   // one wave per partition boundary
+constexpr uint32_t kChunk = 64;              // partitions per chunk sum of a long cut row
 
-// Block `blk` of the fix-up of one mode copy.  Blocks below nbound handle
-// partition boundary q = blk + 1: if a row is cut there and was not already
-// cut at boundary q - 1, the partials of every partition holding part of it
-// are added in partition order in FP64 and the row is stored.  The other
-// blocks zero rows without nonzeros, kEmptyPerBlock rows each.
+// Fix-up blocks of a copy with nbound partition boundaries.
+__host__ __device__ inline uint32_t fixup_bound_blocks(uint32_t nbound)
+{
+    return (nbound + kBoundsPerBlock - 1) / kBoundsPerBlock;
+}
+
+// Adds, in FP64, the R-float partials carry[slot(j) of partition part(j)] for
+// j = 0 .. n-1, over 256 / R interleaved streams of 4 columns per lane, then
+// the streams in stream order; lanes of stream 0 return the 4 sums of their
+// columns (col = (lane % (R / 4)) * 4), the other lanes return garbage.
+template <typename PartOf>
+__device__ __forceinline__ double4 sum_partials(const FixArgs& a, uint32_t n, int lane, PartOf part_of)
+{
+    const int R = a.R;
+    const int C4 = R / 4;                         // lanes per partial
+    const int S = 64 / C4;                        // partial streams
+    const int col = (lane % C4) * 4;
+    const int st = lane / C4;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll 4
+    for (uint32_t j = (uint32_t)st; j < n; j += (uint32_t)S) {
+        const uint64_t slot_row = part_of(j);     // partition * 2 + slot
+        const float4 c = *reinterpret_cast<const float4*>(a.carry + slot_row * R + col);
+        t0 += (double)c.x;
+        t1 += (double)c.y;
+        t2 += (double)c.z;
+        t3 += (double)c.w;
+    }
+    double4 sum = make_double4(t0, t1, t2, t3);
+    for (int k = 1; k < S; ++k) {
+        const int src = (lane % C4) + k * C4;
+        sum.x += __shfl(t0, src, 64);
+        sum.y += __shfl(t1, src, 64);
+        sum.z += __shfl(t2, src, 64);
+        sum.w += __shfl(t3, src, 64);
+    }
+    return sum;
+}
+
+// Block `blk` of the fix-up of one mode copy.  A row r cut by partition
+// boundaries has one partial in `carry` for each partition holding part of
+// it: partition pa, where it starts (slot 0 if pa itself starts inside r,
+// else slot 1), and partitions qf .. pb, which start inside it (slot 0).
+// The first fixup_bound_blocks(nbound) blocks take the boundaries, one wave
+// each (boundary q = blk * kBoundsPerBlock + wave + 1, where partition q
+// starts); the other blocks zero rows without nonzeros, kEmptyPerBlock each.
+//  phase 0: the wave at the first boundary qf of each cut row adds all of its
+//           partials in partition order and stores the row;
+//  phase 1: every partition p of qf+1 .. pb with p % kChunk == 0 (a chunk
+//           leader) replaces its slot 0 with the sum of slot 0 over
+//           p .. min(p + kChunk - 1, pb);
+//  phase 2: the wave at qf adds pa's partial, slot 0 of qf up to the first
+//           chunk leader, and every chunk leader's sum, in partition order.
+// Every sum is formed in FP64 in a fixed order, so results repeat bit for bit.
 __device__ __forceinline__ void fixup_body(const FixArgs& a, uint32_t blk)
 {
-    __shared__ double s_part[kWG];
     const int tid = threadIdx.x;
     const int R = a.R;
-    if (blk < a.nbound) {
-        const uint32_t q = blk + 1;                   // partition q begins at q * wgc
-        const uint2 wq = a.winfo[(q * a.wgc) >> 5];
+    const uint32_t nbb = fixup_bound_blocks(a.nbound);
+    if (blk < nbb) {
+        const int lane = tid & 63;
+        const uint32_t bidx = blk * kBoundsPerBlock + (uint32_t)(tid >> 6);
+        if (bidx >= a.nbound) return;
+        const uint32_t q = bidx + 1;                  // partition q begins at q * wgc
+        const auto winfo_of = [&](uint32_t p) { return a.winfo[((uint64_t)p * a.wgc) >> 5]; };
+        const uint2 wq = winfo_of(q);
         if (wq.x & 1u) return;                        // a row starts at the boundary: nothing is cut
         const uint32_t r = wq.y;                      // ordinal of the cut row
-        if (q >= 2) {
-            const uint2 wp = a.winfo[((uint64_t)(q - 1) * a.wgc) >> 5];
-            if (!(wp.x & 1u) && wp.y == r) return;   // the row was already cut at boundary q-1
+        const uint2 wp = winfo_of(q - 1);
+        const bool interior = !(wp.x & 1u) && wp.y == r;   // the row was already cut at boundary q-1
+        const int C4 = R / 4;
+        const int col = (lane % C4) * 4;
+        const bool stream0 = lane < C4;
+        if (a.phase == 1) {
+            if (!interior || q % kChunk != 0) return;
+            // The chunk's partitions that start inside r form a prefix.
+            const uint32_t p = q + (uint32_t)lane;
+            const uint64_t out_m = __ballot(p >= a.nparts || winfo_of(p).y != r);
+            const uint32_t cnt = out_m ? (uint32_t)__ffsll((long long)out_m) - 1 : 64u;
+            const double4 sum = sum_partials(a, cnt, lane, [&](uint32_t j) { return ((uint64_t)q + j) * 2; });
+            if (stream0)
+                *reinterpret_cast<float4*>(a.carry + (uint64_t)q * 2 * R + col) =
+                    make_float4((float)sum.x, (float)sum.y, (float)sum.z, (float)sum.w);
+            return;
         }
+        if (interior) return;
         const uint32_t pa = q - 1;
-        const int slot_a = (a.winfo[((uint64_t)pa * a.wgc) >> 5].y == r) ? 0 : 1;
-        // Partitions q, q+1, ..., pb hold the rest of the row; each starts inside it.
-        uint32_t pb = q;
-        for (;;) {
-            const uint32_t p = pb + 1 + tid;
-            const int inside = (p < a.nparts) && (a.winfo[((uint64_t)p * a.wgc) >> 5].y == r);
-            const int cnt = __syncthreads_count(inside);
-            pb += cnt;
-            if (cnt < kWG) break;
+        const uint64_t slot_a = (wp.y == r) ? 0 : 1;  // pa starts inside r (slot 0) or r starts inside pa
+        // Partitions q, q+1, ..., pb start inside the row; they form a prefix
+        // of those after q (the row ordinal of a partition's first nonzero
+        // never decreases).  The 64 partitions after q are tested at once; a
+        // row reaching past them is ended by a 64-way search: with p = lo
+        // inside the row and p = hi past it (hi = nparts counts as past),
+        // lane l tests lo + (l+1) * step.
+        const auto past = [&](uint32_t p) { return p >= a.nparts || winfo_of(p).y != r; };
+        uint32_t pb;
+        {
+            const uint64_t m = __ballot(past(q + 1 + (uint32_t)lane));
+            if (m != 0) {
+                pb = q + (uint32_t)__ffsll((long long)m) - 1;
+            } else {
+                uint32_t lo = q + 64, hi = a.nparts;
+                while (hi - lo > 1) {
+                    const uint32_t step = (hi - lo + 63) / 64;
+                    const uint32_t pl = lo + ((uint32_t)lane + 1) * step;
+                    const uint64_t mm = __ballot(pl >= hi || past(pl));
+                    const uint32_t f = (uint32_t)__ffsll((long long)mm) - 1;   // lane 63 always tests >= hi
+                    hi = min(hi, lo + (f + 1) * step);
+                    lo = lo + f * step;
+                }
+                pb = lo;
+            }
         }
-        const int S = kWG / R;                        // partial streams
-        const int col = tid % R;
-        const int s = tid / R;
-        const uint32_t ncontrib = pb - q + 2;
-        double t = 0.0;
-        for (uint32_t j = s; j < ncontrib; j += S) {
-            const uint32_t p = (j == 0) ? pa : (q + j - 1);
-            const int slot = (j == 0) ? slot_a : 0;
-            t += (double)a.carry[((uint64_t)p * 2 + slot) * R + col];
+        // Contributions: j = 0 is pa; j = 1 .. n1 are partitions q .. q + n1 - 1;
+        // then (phase 2) the chunk leaders l0, l0 + kChunk, ... <= pb.
+        uint32_t n1 = pb - q + 1, n2 = 0, l0 = 0;
+        if (a.phase == 2) {
+            l0 = (q / kChunk + 1) * kChunk;
+            if (l0 <= pb) {
+                n1 = l0 - q;
+                n2 = (pb - l0) / kChunk + 1;
+            }
         }
-        s_part[tid] = t;
-        __syncthreads();
-        if (s == 0) {
-            double tot = 0.0;
-            for (int j = 0; j < S; ++j) tot += s_part[j * R + col];
-            a.out[(uint64_t)a.row_id[r] * R + col] = (float)tot;
-        }
+        const double4 sum = sum_partials(a, 1 + n1 + n2, lane, [&](uint32_t j) -> uint64_t {
+            if (j == 0) return (uint64_t)pa * 2 + slot_a;
+            if (j <= n1) return ((uint64_t)q + j - 1) * 2;
+            return ((uint64_t)l0 + (uint64_t)(j - 1 - n1) * kChunk) * 2;
+        });
+        if (stream0)
+            *reinterpret_cast<float4*>(a.out + (uint64_t)a.row_id[r] * R + col) =
+                make_float4((float)sum.x, (float)sum.y, (float)sum.z, (float)sum.w);
     } else {
-        const uint64_t e0 = (uint64_t)(blk - a.nbound) * kEmptyPerBlock;
+        if (a.phase == 1) return;
+        const uint64_t e0 = (uint64_t)(blk - nbb) * kEmptyPerBlock;
         const uint64_t e1 = min(e0 + kEmptyPerBlock, a.nempty);
         const uint64_t n = (e1 - e0) * (uint64_t)R;
         for (uint64_t t = tid; t < n; t += kWG) {
@@ -317,8 +405,18 @@ hipError_t launch_mttkrp(const DevMode& m, int R, int dtype, const void* const* 
     f.nbound = f.nparts > 1 && !m.prange ? f.nparts - 1 : 0;   // scheme-1 partitions cut no rows
     f.nempty = m.nempty;
     f.R = R;
+    f.phase = 0;
     const uint64_t eblocks = (m.nempty + kEmptyPerBlock - 1) / kEmptyPerBlock;
-    const uint64_t blocks = f.nbound + eblocks;
+    const uint32_t nbb = fixup_bound_blocks(f.nbound);
+    if (f.nbound > kChunk) {
+        // A row may span more than kChunk partitions: chunk sums first.
+        f.phase = 1;
+        hipLaunchKernelGGL(mttkrp_fixup_kernel, dim3(nbb), dim3(kWG), 0, s, f);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        f.phase = 2;
+    }
+    const uint64_t blocks = nbb + eblocks;
     if (blocks > 0) {
         hipLaunchKernelGGL(mttkrp_fixup_kernel, dim3((uint32_t)blocks), dim3(kWG), 0, s, f);
         e = hipGetLastError();
@@ -341,7 +439,8 @@ uint32_t fill_fix_desc(void* dst, const DevMode& m, const Geometry& g, float* ca
     f.nbound = f.nparts > 1 ? f.nparts - 1 : 0;
     f.nempty = m.nempty;
     f.R = R;
-    return f.nbound + (uint32_t)((m.nempty + kEmptyPerBlock - 1) / kEmptyPerBlock);
+    f.phase = 0;   // batches add each cut row in one pass
+    return fixup_bound_blocks(f.nbound) + (uint32_t)((m.nempty + kEmptyPerBlock - 1) / kEmptyPerBlock);
 }
 
 hipError_t launch_batch_fixup(const void* descs, const uint2* work, uint32_t nwork, uint32_t grid, hipStream_t s)

@@ -4,13 +4,17 @@
 // kernel; the products, row sums, stores and fix-up are replaced by an XOR
 // fold of the loaded bits.  Timing it beside the MTTKRP gives the on-chip
 // ceiling of a tensor's own index pattern (what = 1) and of the stream alone
-// (what = 0).
+// (what = 0).  Two variants split the gather cost: what = 2 issues the same
+// gather instructions with only the first lane of each lane group reading
+// (the others take the out-of-range offset, which reads zero), so it moves
+// 1/L of the bytes; what = 3 gathers row (index & 63) instead of row index,
+// which stays in L1 (index & 63 <= index, so every row read exists).
 #include "part_kernel.h"
 
 namespace mk {
 namespace part {
 
-template <int NIN, int R, int DT, bool GATHER, bool IDX16>
+template <int NIN, int R, int DT, int WHAT, bool IDX16>
 __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN> a)
 {
     constexpr int kWGT = part_wg(NIN);
@@ -36,7 +40,7 @@ __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN
             load_batch<NIN, V, IDX16>(a, b, gl, bt);
             const int nvalid = (int)min((uint64_t)32, g_end - b);
             x ^= bt.w.x ^ bt.w.y;
-            if constexpr (!GATHER) {
+            if constexpr (WHAT == 0) {
 #pragma unroll
                 for (int j = 0; j < V; ++j) {
                     x ^= bt.val[j];
@@ -54,9 +58,11 @@ __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN
                         x ^= group_bcast<L, k / V>(bt.val[k % V]);
                         static_for<0, NIN>([&](auto M) {
                             constexpr int m = decltype(M)::value;
-                            const uint32_t v = group_bcast<L, k / V>(bt.idx[m][k % V]);
+                            uint32_t v = group_bcast<L, k / V>(bt.idx[m][k % V]);
+                            if constexpr (WHAT == 3) v &= 63u;
+                            const bool use = valid && (WHAT != 2 || gl == 0);
                             const uint32_t off =
-                                valid ? (v * (uint32_t)R + (uint32_t)(gl * E)) * Slice<R, DT>::kElem : kSkipOffset;
+                                use ? (v * (uint32_t)R + (uint32_t)(gl * E)) * Slice<R, DT>::kElem : kSkipOffset;
                             r[u][m] = load_buffer<R, DT>(rsrc[m], off);
                         });
                     });
@@ -80,20 +86,24 @@ __global__ __launch_bounds__(part_wg(NIN)) void gather_probe_kernel(PartArgs<NIN
 template <int NIN, int R, int DT>
 hipError_t launch_probe_r(const PartArgs<NIN>& a, uint32_t grid, int what, hipStream_t s)
 {
-    if constexpr (NIN <= kMaxIn16) {
-        if (a.idx16) {
-            if (what == 0)
-                hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, false, true>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
-            else
-                hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, true, true>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
-            return hipGetLastError();
+    auto go = [&](auto what_c, auto idx16_c) {
+        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, decltype(what_c)::value, decltype(idx16_c)::value>),
+                           dim3(grid), dim3(part_wg(NIN)), 0, s, a);
+        return hipGetLastError();
+    };
+    auto by_what = [&](auto idx16_c) {
+        switch (what) {
+            case 0: return go(std::integral_constant<int, 0>{}, idx16_c);
+            case 1: return go(std::integral_constant<int, 1>{}, idx16_c);
+            case 2: return go(std::integral_constant<int, 2>{}, idx16_c);
+            case 3: return go(std::integral_constant<int, 3>{}, idx16_c);
+            default: return hipErrorInvalidValue;
         }
+    };
+    if constexpr (NIN <= kMaxIn16) {
+        if (a.idx16) return by_what(std::true_type{});
     }
-    if (what == 0)
-        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, false, false>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
-    else
-        hipLaunchKernelGGL((gather_probe_kernel<NIN, R, DT, true, false>), dim3(grid), dim3(part_wg(NIN)), 0, s, a);
-    return hipGetLastError();
+    return by_what(std::false_type{});
 }
 
 template <int NIN>

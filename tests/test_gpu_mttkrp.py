@@ -75,6 +75,38 @@ def test_single_row_holds_everything():
         check_all_modes(t, 32, parts_per_cu=ppc)
 
 
+@pytest.mark.parametrize("R,threads", [(16, 256), (32, 512), (64, 256)])
+def test_rows_spanning_hundreds_of_partitions(R, threads):
+    """Cut rows longer than the fix-up's 64-partition chunks: a row with 40 %
+    of the nonzeros first, ending exactly on a partition boundary, another
+    with 25 % in the middle, and many short rows, at 32 and 64 partitions
+    per CU (up to a few thousand partitions)."""
+    print("case long cut rows", R, threads, flush=True)
+    rng = np.random.default_rng(40 + R)
+    nnz = 2_000_000
+    dims = (3000, 2500, 1800)
+    # Row 5 ends at 391 * 2048, a multiple of every partition size used here.
+    rows = np.concatenate([np.full(800_768, 5), rng.integers(6, 1500, 399_232), np.full(500_000, 1500),
+                           rng.integers(1501, 3000, 300_000)])
+    rows.sort()
+    idx = np.stack([rows, rng.integers(0, dims[1], nnz), rng.integers(0, dims[2], nnz)], axis=1).astype(np.uint32)
+    t = workloads.SparseTensor(idx=idx, val=rng.random(nnz).astype(np.float32), dims=dims, nnz_requested=nnz)
+    F = workloads.random_factors(t.dims, R, seed=3)
+    dF = gu.dev_factors(F)
+    ref = gu.oracle_mttkrp(t.idx, t.val, t.dims, F, 0)
+    for ppc in (32, 64):
+        h = capi.mttkrp_layout_build(t.idx, t.val, t.dims,
+                                     opts=dict(max_R=R, parts_per_cu=ppc, part_threads=threads, build_on_host=1))
+        a = gu.gpu_mttkrp(h, 0, dF, R)
+        b = gu.gpu_mttkrp(h, 0, dF, R)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), f"ppc {ppc}: not repeatable"
+        e = gu.rel_fro(a, ref)
+        rn = np.linalg.norm(ref, axis=1)
+        per_row = np.linalg.norm(a - ref, axis=1) / np.maximum(rn, 1e-30)
+        assert e <= TOL and per_row[rn > 0].max() <= TOL, f"ppc {ppc}: rel err {e:.3e}, worst row {per_row.max():.3e}"
+        h.free()
+
+
 @pytest.mark.parametrize("nnz", [0, 1, 5, 31, 32, 33, 1000])
 def test_tiny_and_ragged(nnz):
     print("case tiny_and_ragged", nnz, flush=True)

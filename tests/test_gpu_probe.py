@@ -1,6 +1,6 @@
-"""The gather-ceiling probe (a measurement aid): it runs on every mode for
-fp32 and bf16 factor rows, leaves the caller's memory alone, and rejects bad
-arguments like mttkrp_run."""
+"""The gather-ceiling probe (a measurement aid): all four variants run on
+every mode for fp32 and bf16 factor rows (and on 16-bit coordinates), leave
+the caller's memory alone, and reject bad arguments like mttkrp_run."""
 
 import numpy as np
 import pytest
@@ -22,7 +22,7 @@ def test_probe_runs_and_writes_nothing_of_the_callers():
     Fb = [f.to(torch.bfloat16) for f in F]
     before = [f.clone() for f in F]
     for n in range(4):
-        for what in (0, 1):
+        for what in (0, 1, 2, 3):
             capi.mttkrp_gather_probe(h, n, F, R, what)
             capi.mttkrp_gather_probe(h, n, Fb, R, what)
     torch.cuda.synchronize()
@@ -34,7 +34,7 @@ def test_probe_runs_and_writes_nothing_of_the_callers():
     ref = gu.oracle_mttkrp(t.idx, t.val, t.dims, [f.cpu().numpy() for f in F], 1)
     assert gu.rel_fro(out.cpu().numpy(), ref) <= 1e-5
     with pytest.raises(capi.MttkrpError):
-        capi.mttkrp_gather_probe(h, 0, F, R, what=2)
+        capi.mttkrp_gather_probe(h, 0, F, R, what=4)
     with pytest.raises(capi.MttkrpError):
         capi.mttkrp_gather_probe(h, 4, F, R)
     h.free()

@@ -205,3 +205,21 @@ def test_single_layout_shape_autotuner():
     with pytest.raises(capi.MttkrpError):
         capi.mttkrp_autotune_shape(hs, R, dF, outs, candidates=cands, reps=1)
     hs.free()
+
+
+def test_autotuner_second_stage_with_more_than_four_candidates():
+    """With more than four candidates the four fastest are timed again; the
+    choice is one of the candidates, every time is positive and the layouts
+    end on the choice."""
+    print("case shape autotune two stages", flush=True)
+    R = 32
+    ts, hs, F, dF = tuned_batch((8, 0, 0), R, count=5, seed=95)
+    outs = [[torch.empty((d, R), device="cuda") for d in t.dims] for t in ts]
+    cands = [(1, 256, 2), (2, 512, 4), (4, 1024, 2), (8, 0, 0), (16, 256, 4), (32, 512, 2)]
+    best, times = capi.mttkrp_batch_autotune_shape(hs, R, dF, outs, candidates=cands, reps=2)
+    assert best in cands and len(times) == 6 and all(v > 0 for v in times.values())
+    for h in hs:
+        info = capi.mttkrp_layout_info(h)
+        assert (info["parts_per_cu"], info["wg_threads"]) == (best[0], best[1] or 512)
+    for h in hs:
+        h.free()

@@ -81,7 +81,7 @@ def algorithmic_bytes(dims, nnz, R, factor_bytes=4, idx16_modes=0):
 
 
 def sources_digest():
-    """SHA-256 over the sources that shape the MTTKRP launch pair (partition
+    """SHA-256 over the sources that shape the per-mode MTTKRP launches (partition
     and fix-up kernels, their launch geometry and the layout; the CP-ALS and
     probe kernels are left out), sorted by name, with comments and blank
     lines removed: HBM traffic counted for one build of that code is only
@@ -103,10 +103,11 @@ def sources_digest():
 
 
 def profiled_traffic(workload):
-    """HBM bytes per MTTKRP launch pair from the committed rocprofv3 counter
-    summary of this workload (FETCH_SIZE and WRITE_SIZE in KiB per dispatch,
-    scaled by the factors a plain copy of known size gives), or None when the
-    summary is missing or was taken from other sources."""
+    """HBM bytes per mode of the MTTKRP (the partition kernel and its fix-up
+    launches) from the committed rocprofv3 counter summary of this workload
+    (FETCH_SIZE and WRITE_SIZE in KiB, scaled by the factors a plain copy of
+    known size gives), or None when the summary is missing or was taken from
+    other sources."""
     path = os.path.join(ROOT, "profiles", f"mttkrp_{workload}.traffic.txt")
     if not os.path.exists(path):
         return None
@@ -884,10 +885,11 @@ def main(argv=None):
         "step_ms_min": round(float(np.min(step_ms)), 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(args.workload),
-                     "kernel": ("per-mode MTTKRP launch pair (mttkrp_step_kernel on hot-steps copies + "
+                     "kernel": ("per-mode MTTKRP launches (mttkrp_step_kernel on hot-steps copies + "
                                 "mttkrp_fixup_kernel)" if steps else
-                                "per-mode MTTKRP launch pair (mttkrp_part_kernel + mttkrp_fixup_kernel)") +
-                               ": algorithmic bytes per mode / HIP-event time of the pair, averaged over modes",
+                                "per-mode MTTKRP launches (mttkrp_part_kernel + its mttkrp_fixup_kernel launches)") +
+                               ": algorithmic bytes per mode / HIP-event time of the mode's launches, averaged over "
+                               "modes",
                      "algorithmic_bytes_per_launch": round(sum(bytes_mode) / N),
                      "bytes_per_mode": bytes_mode},
         "build_s": round(build_s, 2),

@@ -121,7 +121,7 @@ def profiled_traffic(workload):
         return None
     fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_factor"])
     write = float(kv["write_kib_per_launch"]) * float(kv["write_factor"])
-    return round((fetch + write) * 1024.0)
+    return round((fetch + write) * 1024.0), kv.get("launch_shape")
 
 
 def cpu_model() -> str:
@@ -861,6 +861,7 @@ def main(argv=None):
     flops = N * R * t.nnz * N
     gflops = flops / (ms_step / 1e3) / 1e9
     bytes_mode = algorithmic_bytes(t.dims, t.nnz, R, idx16_modes=capi.mttkrp_layout_info(h)["idx16_modes"])
+    traffic = profiled_traffic(args.workload)
     achieved = sum(bytes_mode) / (sum(mode_ms) / 1e3) / 1e9
     result = {
         "metric": METRIC,
@@ -884,7 +885,8 @@ def main(argv=None):
         "step_ms_median": round(float(np.median(step_ms)), 4),
         "step_ms_min": round(float(np.min(step_ms)), 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(args.workload),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic[0] if traffic else None,
+                     "traffic_launch_shape": traffic[1] if traffic else None,
                      "kernel": ("per-mode MTTKRP launches (mttkrp_step_kernel on hot-steps copies + "
                                 "mttkrp_fixup_kernel)" if steps else
                                 "per-mode MTTKRP launches (mttkrp_part_kernel + its mttkrp_fixup_kernel launches)") +

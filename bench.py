@@ -387,7 +387,7 @@ def bench_precision(args):
     log(f"generated {t.dims} nnz={t.nnz}")
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=64), stream=stream)
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=64, relabel=int(args.relabel)), stream=stream)
     build_s = time.perf_counter() - t0
     log(f"layout built in {build_s:.1f}s")
     K, W = args.steps, args.warmup
@@ -433,7 +433,8 @@ def bench_precision(args):
         "ms_per_step": main["ms_all_modes"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "precision-100M-4mode: 4-mode 50000x40000x30000x2000, 100M distinct nonzeros "
-                               "(Zipf(1.1)), lognormal(0,1) values, R in {32,64}, FP32 vs BF16 factor rows",
+                               "(Zipf(1.1)), lognormal(0,1) values, R in {32,64}, FP32 vs BF16 factor rows"
+                               + (", indices renumbered by degree" if args.relabel else ""),
                    "nnz": t.nnz, "dims": list(t.dims)},
         "by_dtype_and_R": by,
         "build_s": round(build_s, 2),
@@ -694,6 +695,9 @@ def main(argv=None):
     ap.add_argument("--parts-per-cu", type=int, default=0)
     ap.add_argument("--shape", default="",
                     help="fixed launch shape PPC,THREADS,GATHERS of the nonzero-ordered copies (no tuning)")
+    ap.add_argument("--relabel", action="store_true",
+                    help="renumber each mode's indices by decreasing nonzero count before building "
+                         "(the default and precision workloads' nonzero-ordered copies)")
     ap.add_argument("--wide-indices", action="store_true",
                     help="serve-poisson: build every job's copies with 32-bit coordinates")
     ap.add_argument("--no-tune-shape", action="store_true",
@@ -773,7 +777,7 @@ def main(argv=None):
     # nonzero-ordered copies.
     steps = args.kernel == "steps" and N in (3, 4)
     other = N in (3, 4) and not args.no_compare_layouts
-    opts0 = dict(max_R=R, hot_rows=args.hot_rows)
+    opts0 = dict(max_R=R, hot_rows=args.hot_rows, relabel=int(args.relabel))
     if args.parts_per_cu:
         opts0["parts_per_cu"] = args.parts_per_cu
     opts1 = dict(max_R=R, hot_steps=1, parts_per_cu=args.parts_per_cu or 2)
@@ -898,7 +902,7 @@ def main(argv=None):
         "launch": capi.mttkrp_layout_info(h),
         "launch_shape": launch_shape,
         "layout": ("hot-steps copies (rows ordered by hot/cold input rows, padded to wave steps; built on the host)"
-                   if steps else "nonzero-ordered copies"),
+                   if steps else "nonzero-ordered copies" + (", indices renumbered by degree" if args.relabel else "")),
     }
     if other:
         result["nonzero_order_copies" if steps else "hot_steps_copies"] = {

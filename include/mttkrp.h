@@ -100,6 +100,13 @@ typedef struct {
     int part_gathers;          /* nonzeros whose row gathers each lane group keeps in flight in those runs: 2
                                   or 4; 0 (default) = 2 at R = 16, else 4.  Ignored elsewhere.  Both change
                                   the partitioning, so results change by rounding only */
+    int relabel;               /* 1: renumber every mode's indices by decreasing nonzero count (ties: lower
+                                  index first) before building, so the most gathered factor rows lie
+                                  together (rows shorter than a cache line then share lines; the LDS hot
+                                  rows of hot_rows are picked by the same count).  Every row index the
+                                  handle then takes or produces is in the new numbering: factors passed to
+                                  runs and CP-ALS, MTTKRP outputs, hot-row tables.  mttkrp_layout_perm
+                                  gives the map.  0 (default): the caller's numbering */
 } mttkrp_opts;
 
 enum { MTTKRP_PART_NNZ = 0, MTTKRP_PART_ROWS_LPT = 1 };
@@ -256,6 +263,11 @@ typedef struct {
 } mttkrp_info;
 
 mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info);
+
+/* The renumbering of a layout built with opts.relabel = 1: new_of_old (host,
+ * I_mode entries, written) receives the new index of each original index of
+ * `mode`.  MTTKRP_EINVAL for a layout built without relabel. */
+mttkrp_status mttkrp_layout_perm(mttkrp_handle h, int mode, uint32_t* new_of_old);
 
 /* Launch plan of the per-mode MTTKRP for a tensor of nnz nonzeros and N modes
  * (host only, no device needed): the nonzero-balanced partitions of the

@@ -33,7 +33,8 @@ EXPORTED = ["mttkrp_opts_default", "mttkrp_footprint", "mttkrp_layout_build", "m
             "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
             "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes", "mttkrp_batch_create_in",
             "mttkrp_run_noalloc", "mttkrp_noalloc_scratch_bytes", "mttkrp_lpt_partition", "mttkrp_batch_run_bf16",
-            "mttkrp_batch_autotune_shape", "mttkrp_batch_autotune_default_shapes", "mttkrp_autotune_shape"]
+            "mttkrp_batch_autotune_shape", "mttkrp_batch_autotune_default_shapes", "mttkrp_autotune_shape",
+            "mttkrp_layout_perm"]
 
 
 class MttkrpError(RuntimeError):
@@ -47,7 +48,7 @@ class mttkrp_opts(ctypes.Structure):
                 ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int), ("hot_rows", ctypes.c_int),
                 ("build_on_host", ctypes.c_int), ("partitioner", ctypes.c_int), ("lpt_parts", ctypes.c_int),
                 ("hot_steps", ctypes.c_int), ("wide_indices", ctypes.c_int), ("part_threads", ctypes.c_int),
-                ("part_gathers", ctypes.c_int)]
+                ("part_gathers", ctypes.c_int), ("relabel", ctypes.c_int)]
 
 
 class mttkrp_mode_view(ctypes.Structure):
@@ -126,6 +127,7 @@ def _load():
     lib.mttkrp_autotune_shape.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mttkrp_part_shape), ctypes.c_int,
                                           ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
                                           ctypes.POINTER(mttkrp_part_shape), ctypes.POINTER(ctypes.c_float)]
+    lib.mttkrp_layout_perm.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32)]
     lib.mttkrp_batch_autotune_default_shapes.argtypes = [ctypes.c_int, ctypes.POINTER(mttkrp_part_shape)]
     lib.mttkrp_batch_autotune_default_shapes.restype = ctypes.c_int
     lib.mttkrp_gather_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
@@ -148,7 +150,7 @@ def _load():
                  "mttkrp_gather_probe", "mttkrp_batch_autotune", "mttkrp_run_scheme2", "mttkrp_launch_plan",
                  "mttkrp_build_scratch_bytes", "mttkrp_layout_build_in", "mttkrp_batch_bytes",
                  "mttkrp_batch_create_in", "mttkrp_run_noalloc", "mttkrp_lpt_partition", "mttkrp_batch_run_bf16",
-                 "mttkrp_batch_autotune_shape", "mttkrp_autotune_shape"):
+                 "mttkrp_batch_autotune_shape", "mttkrp_autotune_shape", "mttkrp_layout_perm"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -288,6 +290,16 @@ def mttkrp_layout_info(h: Layout) -> dict:
     i = mttkrp_info()
     _check(_lib.mttkrp_layout_info(ctypes.c_void_p(h.ptr), ctypes.byref(i)))
     return {k: int(getattr(i, k)) for k, _ in mttkrp_info._fields_}
+
+
+def mttkrp_layout_perm(h: Layout, mode: int) -> np.ndarray:
+    """For a layout built with relabel=1: the new index of each original index
+    of ``mode`` (uint32 array of length I_mode)."""
+    if not 0 <= int(mode) < len(h.dims):
+        raise MttkrpError(MTTKRP_EINVAL, f"mode {mode} out of range")
+    out = np.zeros(int(h.dims[mode]), dtype=np.uint32)
+    _check(_lib.mttkrp_layout_perm(ctypes.c_void_p(h.ptr), int(mode), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return out
 
 
 def mttkrp_launch_plan(nnz: int, N: int, R: int, factor_dtype: int = MTTKRP_FP32, parts_per_cu: int = 0,

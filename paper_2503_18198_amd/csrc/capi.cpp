@@ -147,7 +147,29 @@ struct mttkrp_layout {
     mk::InvJob inv_job_host{};                         // host source of als.job (kept alive for the copy)
     double normX2 = 0.0;
     int als_R = 0;
+    std::vector<std::vector<uint32_t>> new_of_old;     // relabel: per mode, the new index of each old one
 };
+
+// Degree relabelling: per mode, indices renumbered by decreasing nonzero
+// count (ties: the lower index first); `out` receives the COO tensor in the
+// new numbering and `perm[m][old] = new`.
+static void relabel_by_degree(const uint32_t* coo, uint64_t nnz, const uint32_t* dims, int N,
+                              std::vector<uint32_t>& out, std::vector<std::vector<uint32_t>>& perm)
+{
+    perm.assign(N, {});
+    for (int m = 0; m < N; ++m) {
+        std::vector<uint64_t> deg(dims[m], 0);
+        for (uint64_t k = 0; k < nnz; ++k) ++deg[coo[k * N + m]];
+        std::vector<uint32_t> order(dims[m]);
+        for (uint32_t i = 0; i < dims[m]; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return deg[a] > deg[b]; });
+        perm[m].resize(dims[m]);
+        for (uint32_t r = 0; r < dims[m]; ++r) perm[m][order[r]] = r;
+    }
+    out.resize((size_t)nnz * N);
+    for (uint64_t k = 0; k < nnz; ++k)
+        for (int m = 0; m < N; ++m) out[k * N + m] = perm[m][coo[k * N + m]];
+}
 
 extern "C" {
 
@@ -167,6 +189,7 @@ void mttkrp_opts_default(mttkrp_opts* o)
     o->wide_indices = 0;
     o->part_threads = 0;
     o->part_gathers = 0;
+    o->relabel = 0;
 }
 
 const char* mttkrp_last_error(void) { return g_err.c_str(); }
@@ -188,6 +211,7 @@ static mttkrp_status check_opts(const mttkrp_opts* in, mttkrp_opts* o)
         ((o->part_threads || o->part_gathers) &&
          !mk::tuned_shape_supported(o->part_threads ? o->part_threads : 512, o->part_gathers ? o->part_gathers : 4)))
         return fail(MTTKRP_EINVAL, "part_threads must be 0, 256, 512 or 1024 and part_gathers 0, 2 or 4");
+    if (o->relabel != 0 && o->relabel != 1) return fail(MTTKRP_EINVAL, "relabel must be 0 or 1");
     if (o->hot_steps) {
         o->partitioner = MTTKRP_PART_NNZ;   // step copies carry their own hot rows and partitions
         o->hot_rows = 0;
@@ -283,6 +307,13 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     bool range_err = false;
     std::string msg = mk::validate_coo(coo_idx, nnz, dims, N, &range_err);
     if (!msg.empty()) return fail(range_err ? MTTKRP_ERANGE : MTTKRP_EINVAL, msg);
+    // Degree relabelling: every later step sees the tensor in the new numbering.
+    std::vector<uint32_t> relabelled;
+    std::vector<std::vector<uint32_t>> new_of_old;
+    if (o.relabel) {
+        relabel_by_degree(coo_idx, nnz, dims, N, relabelled, new_of_old);
+        coo_idx = relabelled.data();
+    }
 
     // Admission first, before any device call (the hot tables are sized for the
     // largest LDS, an upper bound).
@@ -328,6 +359,7 @@ static mttkrp_status build_impl(const uint32_t* coo_idx, const float* vals, uint
     h->nhot = nhot;
     h->lds_limit = lds_limit;
     h->device = dev_id;
+    h->new_of_old = std::move(new_of_old);
 
     const int threads = mk::host_threads();
     std::vector<mk::HotSet> hot = mk::select_hot_rows(coo_idx, nnz, dims, N, nhot);
@@ -623,6 +655,16 @@ mttkrp_status mttkrp_layout_info(mttkrp_handle h, mttkrp_info* info)
     info->idx16_modes = 0u;
     for (int n = 0; n < h->N; ++n)
         if (h->host_only ? copy_idx16(h->dims, h->N, n, h->opts, h->nhot) : h->dev[n].idx16) info->idx16_modes |= 1u << n;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_layout_perm(mttkrp_handle h, int mode, uint32_t* new_of_old)
+{
+    g_err.clear();
+    if (!h || !new_of_old) return fail(MTTKRP_EINVAL, "NULL handle or output");
+    if (mode < 0 || mode >= h->N) return fail(MTTKRP_EINVAL, "mode out of range");
+    if (h->new_of_old.empty()) return fail(MTTKRP_EINVAL, "the layout was built without relabel");
+    std::copy(h->new_of_old[mode].begin(), h->new_of_old[mode].end(), new_of_old);
     return MTTKRP_OK;
 }
 

@@ -319,3 +319,36 @@ def test_tuned_shape_options():
     assert len(d3) == 36 and len(set(d3)) == 36
     assert {s[1] for s in d3} == {256, 512, 1024} and {s[2] for s in d3} == {2, 4}
     assert capi.mttkrp_batch_autotune_default_shapes(5) == [(p, 0, 0) for p in (1, 2, 4, 8, 16, 32)]
+
+
+def test_degree_relabelling_host():
+    """relabel=1 renumbers each mode by decreasing nonzero count (ties: lower
+    index first) and then builds exactly the copies of the renumbered tensor."""
+    rng = np.random.default_rng(12)
+    dims = (300, 200, 100)
+    base = np.stack([rng.zipf(1.5, 20000) % d for d in dims], axis=1).astype(np.uint32)
+    idx = np.concatenate([base, base[:500]])            # duplicates too
+    val = rng.random(idx.shape[0]).astype(np.float32)
+    h = capi.mttkrp_layout_build(idx, val, dims, opts=dict(host_only=1, relabel=1))
+    perms = [capi.mttkrp_layout_perm(h, m) for m in range(3)]
+    remapped = np.stack([perms[m][idx[:, m]] for m in range(3)], axis=1).astype(np.uint32)
+    for m, d in enumerate(dims):
+        p = perms[m]
+        assert np.array_equal(np.sort(p), np.arange(d, dtype=np.uint32))
+        deg = np.bincount(idx[:, m], minlength=d)
+        order = np.argsort(p)                            # old index at each new position
+        assert np.all(np.diff(deg[order]) <= 0)
+        ties = np.diff(deg[order]) == 0
+        assert np.all(np.diff(order)[ties] > 0)          # equal counts keep the original order
+    ref = capi.mttkrp_layout_build(remapped, val, dims, opts=dict(host_only=1))
+    for n in range(3):
+        a, b = capi.mttkrp_layout_view(h, n), capi.mttkrp_layout_view(ref, n)
+        for k in ("val", "winfo", "row_id", "empty_rows", "src_pos"):
+            assert np.array_equal(a[k], b[k]), (n, k)
+        for x, y in zip(a["idx"], b["idx"]):
+            assert np.array_equal(x, y)
+    plain = capi.mttkrp_layout_build(idx, val, dims, opts=dict(host_only=1))
+    with pytest.raises(capi.MttkrpError):
+        capi.mttkrp_layout_perm(plain, 0)
+    with pytest.raises(capi.MttkrpError):
+        capi.mttkrp_layout_build(idx, val, dims, opts=dict(host_only=1, relabel=2))

@@ -12,8 +12,8 @@ in a HIP graph) and `serve` (Poisson CP-ALS jobs at 0.95 and 2 x the plain
 method's capacity: jobs/s and p50/p99 latency, continuous batching vs one job
 at a time).
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one
-GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the library runs on one
+device.
 """
 
 from __future__ import annotations
@@ -447,12 +447,12 @@ def bench_paper_shapes(args, R=32):
     """The paper's load-balancing ablation (Sec. V-B, Fig. 4) on synthetic
     tensors with the shapes and nonzero counts of its evaluation set (Table
     III), at kappa = one partition per compute unit.  Per mode, three
-    partitioners on the same kernel: this build's nonzero split with the
-    deterministic carry fix-up; scheme 2 (equal nonzero chunks, global
+    partitioners on the same kernel: the library's nonzero split with the
+    deterministic carry fix-up ("nonzero_split"); scheme 2 (equal nonzero chunks, global
     atomics for rows cut by chunk boundaries); scheme 1 (whole rows dealt to
     kappa partitions by LPT).  All-mode totals for scheme 1 only, scheme 2
     only, the paper's adaptive choice (scheme 1 where I_n >= kappa, else
-    scheme 2) and this build.  Returns the result line as a dict."""
+    scheme 2) and the nonzero split.  Returns the result line as a dict."""
     import torch
 
     import workloads
@@ -510,7 +510,7 @@ def bench_paper_shapes(args, R=32):
                         tot[n] += ev[n][0].elapsed_time(ev[n][1])
             return [x / K for x in tot]
 
-        ms = {"this_build": per_mode(capi.mttkrp_run, h, out["nnz"]),
+        ms = {"nonzero_split": per_mode(capi.mttkrp_run, h, out["nnz"]),
               "scheme2_atomics": per_mode(capi.mttkrp_run_scheme2, h, out["s2"]),
               "scheme1_lpt": per_mode(capi.mttkrp_run, h1, out["s1"])}
         adaptive = [ms["scheme1_lpt"][n] if dims[n] >= kappa else ms["scheme2_atomics"][n] for n in range(N)]
@@ -530,9 +530,9 @@ def bench_paper_shapes(args, R=32):
             "adaptive_choice": ["scheme1" if dims[n] >= kappa else "scheme2" for n in range(N)],
             "ms_all_modes": {k: round(v, 4) for k, v in tot.items()},
             "speedup_vs_adaptive": {k: round(tot["adaptive_paper"] / v, 3) for k, v in tot.items()},
-            "gflops_this_build": round(flops / (tot["this_build"] / 1e3) / 1e9, 1),
-            "hbm_frac_this_build": round(byts / (tot["this_build"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "max_rel_diff_vs_this_build": {"scheme2_atomics": rel(out["s2"], out["nnz"]),
+            "gflops_nonzero_split": round(flops / (tot["nonzero_split"] / 1e3) / 1e9, 1),
+            "hbm_frac_nonzero_split": round(byts / (tot["nonzero_split"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "max_rel_diff_vs_nonzero_split": {"scheme2_atomics": rel(out["s2"], out["nnz"]),
                                            "scheme1_lpt": rel(out["s1"], out["nnz"])},
         }
         print(f"[bench] {name}: {json.dumps(rows[name])}", file=sys.stderr, flush=True)
@@ -547,14 +547,14 @@ def bench_paper_shapes(args, R=32):
 
     res = {
         "metric": "all-mode spMTTKRP GFLOP/s on tensors shaped like the paper's evaluation set",
-        "value": round(float(np.exp(np.mean([np.log(r["gflops_this_build"]) for r in rows.values()]))), 1),
+        "value": round(float(np.exp(np.mean([np.log(r["gflops_nonzero_split"]) for r in rows.values()]))), 1),
         "unit": "GFLOP/s (geometric mean)", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": round(sum(r["ms_all_modes"]["this_build"] for r in rows.values()), 4),
+        "ms_per_step": round(sum(r["ms_all_modes"]["nonzero_split"] for r in rows.values()), 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "paper-shapes: Zipf(1.2) stand-ins with the shapes and nnz of the paper's Table III "
                                f"tensors, R={R}, fp32, kappa = {kappa} partitions for scheme 1"},
         "tensors": rows,
-        "speedup_vs_adaptive_geomean": {k: gm(k) for k in ("this_build", "scheme2_atomics", "scheme1_lpt",
+        "speedup_vs_adaptive_geomean": {k: gm(k) for k in ("nonzero_split", "scheme2_atomics", "scheme1_lpt",
                                                            "adaptive_paper")},
     }
     return res
@@ -729,8 +729,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: sharding across GPUs is not part of this build "
-              "(see the design notes on how the path would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on one device "
+              "(the design notes describe how the path would shard).", file=sys.stderr)
         return 2
 
     import torch

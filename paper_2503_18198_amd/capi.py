@@ -83,8 +83,7 @@ class mttkrp_plan(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run paper_2503_18198_amd.build.build() "
-                          "(or __graft_entry__.build()) first")
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2503_18198_amd.build.build() first")
     lib = ctypes.CDLL(LIB_PATH)
     vp, u32p, f32p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)
     lib.mttkrp_opts_default.argtypes = [ctypes.POINTER(mttkrp_opts)]

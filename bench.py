@@ -91,7 +91,7 @@ def sources_digest():
     d = os.path.join(ROOT, "paper_2503_18198_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
-        if name.endswith((".h", ".hip", ".cpp")) and name not in ("als_kernels.hip", "probe_kernels.hip"):
+        if name.endswith((".h", ".hip", ".cpp")) and name != "als_kernels.hip" and not name.startswith("probe"):
             with open(os.path.join(d, name), encoding="utf-8") as f:
                 text = f.read()
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)

@@ -239,7 +239,9 @@ mttkrp_status mttkrp_run_scheme2(mttkrp_handle h, int mode, const float* const* 
  * what = 1 also gathers every factor row the nonzeros name; what = 2 issues
  * the same gather instructions with one lane of each row's lane group
  * reading (1/L of the bytes); what = 3 gathers row (index & 63) in place of
- * row index, so every gather hits rows resident in L1.
+ * row index, so every gather hits rows resident in L1.  Variants 2 and 3 are
+ * compiled for 3- and 4-mode tensors; for more modes they fail with
+ * MTTKRP_EHIP (invalid launch).
  *   factors:      host array of N device pointers (factors[mode] unused), rows
  *                 of R fp32 values (factor_dtype MTTKRP_FP32) or R bf16 bit
  *                 patterns (MTTKRP_BF16)

@@ -21,7 +21,7 @@ ARCH = "gfx950"
 
 SOURCES = ["capi.cpp", "layout.cpp", "layout_device.hip", "mttkrp_kernels.hip", "als_kernels.hip", "probe_kernels.hip",
            "noalloc.hip", "step_n3.hip", "step_n4.hip", "part_tuned_256.hip", "part_tuned_512.hip",
-           "part_tuned_1024.hip"] + [
+           "part_tuned_1024.hip", "probe_n3.hip", "probe_n4.hip", "probe_n5_8.hip"] + [
     f"part_n{n}.hip" for n in range(3, 9)
 ]
 

@@ -38,3 +38,24 @@ def test_probe_runs_and_writes_nothing_of_the_callers():
     with pytest.raises(capi.MttkrpError):
         capi.mttkrp_gather_probe(h, 4, F, R)
     h.free()
+
+
+def test_split_variants_refused_beyond_four_modes():
+    """Variants 2 and 3 are compiled for 3- and 4-mode tensors; a 5-mode
+    tensor gets an error from them and still runs variants 0 and 1."""
+    print("case probe 5 modes", flush=True)
+    R = 16
+    t = workloads.random_tensor((60, 50, 40, 30, 20), 5000, seed=9)
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R))
+    F = gu.dev_factors(workloads.random_factors(t.dims, R, seed=9))
+    for what in (0, 1):
+        capi.mttkrp_gather_probe(h, 0, F, R, what)
+    for what in (2, 3):
+        with pytest.raises(capi.MttkrpError):
+            capi.mttkrp_gather_probe(h, 0, F, R, what)
+    torch.cuda.synchronize()
+    out = torch.empty((t.dims[0], R), device="cuda")
+    capi.mttkrp_run(h, 0, F, out, R)
+    ref = gu.oracle_mttkrp(t.idx, t.val, t.dims, [f.cpu().numpy() for f in F], 0)
+    assert gu.rel_fro(out.cpu().numpy(), ref) <= 1e-5
+    h.free()

@@ -107,6 +107,10 @@ typedef struct {
                                   handle then takes or produces is in the new numbering: factors passed to
                                   runs and CP-ALS, MTTKRP outputs, hot-row tables.  mttkrp_layout_perm
                                   gives the map.  0 (default): the caller's numbering */
+    int als_solve;             /* CP-ALS normal equations A_n V = M (Sec. II-A): 0 (default) V^{-1} by the sweep
+                                  operator (FP64, one workgroup) and M V^{-1} on the FP64 matrix cores;
+                                  1: V = L L^T by Cholesky (FP64) and every row of M solved by forward and
+                                  back substitution (FP64).  Both reject the same non-SPD V; 1 is slower */
 } mttkrp_opts;
 
 enum { MTTKRP_PART_NNZ = 0, MTTKRP_PART_ROWS_LPT = 1 };

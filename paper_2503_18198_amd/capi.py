@@ -48,7 +48,7 @@ class mttkrp_opts(ctypes.Structure):
                 ("hbm_budget_bytes", ctypes.c_uint64), ("host_only", ctypes.c_int), ("hot_rows", ctypes.c_int),
                 ("build_on_host", ctypes.c_int), ("partitioner", ctypes.c_int), ("lpt_parts", ctypes.c_int),
                 ("hot_steps", ctypes.c_int), ("wide_indices", ctypes.c_int), ("part_threads", ctypes.c_int),
-                ("part_gathers", ctypes.c_int), ("relabel", ctypes.c_int)]
+                ("part_gathers", ctypes.c_int), ("relabel", ctypes.c_int), ("als_solve", ctypes.c_int)]
 
 
 class mttkrp_mode_view(ctypes.Structure):

@@ -3,10 +3,11 @@
 // The paper computes CPD by alternating least squares around the MTTKRP and
 // normalises the factors (Sec. II-A).  The least-squares step is the
 // textbook one: A_n = M V^{-1} with V the Hadamard product of the other
-// factors' Gram matrices.  R <= 64 here, so V is tiny: its inverse comes
-// from one workgroup (sweep operator, whose pivots are those of V's Cholesky
-// factorisation, so non-SPD V is caught), and the I_n x R products are
-// memory-bound row passes.  Every reduction writes per-block partials that a
+// factors' Gram matrices.  R <= 64 here, so V is tiny: by default its inverse
+// comes from one workgroup (sweep operator, whose pivots are those of V's
+// Cholesky factorisation, so non-SPD V is caught) and the I_n x R products
+// M V^{-1} are row passes on the FP64 matrix cores; opt-in, V is factored by
+// Cholesky and every row of M is solved by substitution.  Every reduction writes per-block partials that a
 // second kernel adds in block order, so results repeat bit for bit.
 
 #include <math.h>
@@ -199,6 +200,181 @@ __global__ __launch_bounds__(kWG) void normal_eq_inverse_kernel(const InvJob* __
     if (tid == 0) {
         if (reset_flag) *jb.flag = 0.0;
         if (bad) *jb.flag = 1.0;
+    }
+}
+
+// ---- The Cholesky solve (opt-in, mttkrp_opts.als_solve = 1) ----
+//
+// Cholesky factor of the symmetric positive definite R x R normal-equation
+// matrix V (the textbook CP-ALS solve): one workgroup per job forms V = the
+// Hadamard product of the Gram matrices of every mode but `skip` (kept in LDS
+// and stored to V), then factors V = L L^T in place, right-looking: at step k
+// the pivot d is the Schur complement's diagonal entry, L_kk = sqrt(d), the
+// column below is divided by L_kk and the trailing lower triangle loses
+// L_ik L_jk (all entries of a step in parallel, barriers between steps).  The
+// pivot test is the sweep operator's, on the same pivots: a failure sets
+// *flag = 1 and fills W with NaN.  Otherwise W holds L (lower triangle; zeros
+// above).  One launch serves one tensor or every tensor of a batch.
+template <int R>
+__global__ __launch_bounds__(kWG) void normal_eq_cholesky_kernel(const InvJob* __restrict__ jobs, int N, int skip,
+                                                                 int reset_flag)
+{
+    constexpr int RR = R * R;
+    __shared__ double A[RR];
+    __shared__ double diag0[R];
+    const InvJob jb = jobs[blockIdx.x];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < RR; e += kWG) {
+        double v = 1.0;
+        for (int m = 0; m < N; ++m)
+            if (m != skip) v *= jb.grams[(uint64_t)m * RR + e];
+        A[e] = v;
+        jb.V[e] = v;
+    }
+    __syncthreads();
+    if (tid < R) diag0[tid] = A[tid * R + tid];
+    __syncthreads();
+    bool bad = false;   // every thread tests the same pivots, so this is uniform
+    for (int k = 0; k < R; ++k) {
+        double d = A[k * R + k];
+        if (!(d > 64.0 * 2.220446049250313e-16 * fabs(diag0[k])) || !isfinite(d)) {
+            bad = true;
+            d = 1.0;
+        }
+        const double lkk = sqrt(d);
+        const double inv = 1.0 / lkk;
+        __syncthreads();                              // every thread has read the pivot
+        for (int i = k + 1 + tid; i < R; i += kWG) A[i * R + k] *= inv;
+        if (tid == 0) A[k * R + k] = lkk;
+        __syncthreads();
+        // Trailing lower triangle: entries (i, j) with k < j <= i < R.
+        for (int e = tid; e < RR; e += kWG) {
+            const int i = e / R, j = e % R;
+            if (j > k && j <= i) A[e] -= A[i * R + k] * A[j * R + k];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < RR; e += kWG) {
+        const int i = e / R, j = e % R;
+        jb.W[e] = bad ? __longlong_as_double(0x7ff8000000000000ll) : (j <= i ? A[e] : 0.0);
+    }
+    if (tid == 0) {
+        if (reset_flag) *jb.flag = 0.0;
+        if (bad) *jb.flag = 1.0;
+    }
+}
+
+// Rows of M V^{-1} (FP64) by substitution with the Cholesky factor L of V
+// (in W): forward L y = m, then backward L^T x = y, one row per thread,
+// both in column order (after x_k is final, the rows it enters are updated),
+// so the R - k updates of a step are independent.  L and 1/L_kk sit in LDS
+// and are read by every lane at the same address, one column of L per step
+// (compiler barriers keep the scheduler from holding all of L in registers).
+// op 0: per-block column sums of squares -> part[b][c]: for R <= 32 each
+// thread adds its rows in registers and the 64 lanes of a wave are then added
+// by a fixed butterfly; for R = 64 every row's squares go through the
+// butterfly at once into a per-wave LDS sum; the waves are added in order.
+// op 1: A[i][c] = x[c] / lam[c], stored as fp32.
+template <int R>
+__global__ __launch_bounds__(kWG) void chol_solve_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
+                                                         const uint2* __restrict__ work, int op)
+{
+    constexpr int kWaves = kWG / 64;
+    constexpr bool kRegSums = R <= 32;
+    __shared__ double sL[R * R];
+    __shared__ double sdinv[R];
+    __shared__ double sscale[R];
+    __shared__ double swave[kWaves][R];
+    uint32_t blk;
+    const DenseJob& jb = pick_job(single, jobs, work, blk);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < R * R; e += kWG) sL[e] = jb.W[e];
+    for (int e = tid; e < kWaves * R; e += kWG) swave[e / R][e % R] = 0.0;
+    __syncthreads();
+    if (tid < R) {
+        sdinv[tid] = 1.0 / sL[tid * R + tid];
+        sscale[tid] = op == 1 ? 1.0 / jb.lam[tid] : 0.0;
+    }
+    __syncthreads();
+    uint32_t r0, r1;
+    block_rows(jb.I, jb.rpb, blk, r0, r1);
+    double colsq[kRegSums ? R : 1];
+#pragma unroll
+    for (int c = 0; c < (kRegSums ? R : 1); ++c) colsq[c] = 0.0;
+    // Every wave runs the same number of row steps, so the butterflies below
+    // always have all 64 lanes (rows past the block's end contribute zero).
+    const uint32_t nsteps = (r1 - r0 + kWG - 1) / kWG;
+    for (uint32_t it = 0; it < nsteps; ++it) {
+        const uint32_t i = r0 + it * kWG + tid;
+        const bool live = i < r1;
+        double x[R];
+        if (live) {
+            const float4* mrow = reinterpret_cast<const float4*>(jb.M + (uint64_t)i * R);
+#pragma unroll
+            for (int q = 0; q < R / 4; ++q) {
+                const float4 v = mrow[q];
+                x[4 * q] = v.x;
+                x[4 * q + 1] = v.y;
+                x[4 * q + 2] = v.z;
+                x[4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < R; ++c) x[c] = 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            asm volatile("" ::: "memory");   // one column of L in registers at a time
+            x[k] *= sdinv[k];
+#pragma unroll
+            for (int j = k + 1; j < R; ++j) x[j] -= sL[j * R + k] * x[k];
+        }
+#pragma unroll
+        for (int k = R - 1; k >= 0; --k) {
+            asm volatile("" ::: "memory");
+            x[k] *= sdinv[k];
+#pragma unroll
+            for (int j = 0; j < k; ++j) x[j] -= sL[k * R + j] * x[k];
+        }
+        if (op == 0) {
+            if constexpr (kRegSums) {
+#pragma unroll
+                for (int c = 0; c < R; ++c) colsq[c] += x[c] * x[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    double t = x[c] * x[c];
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+                    if (lane == 0) swave[wave][c] += t;
+                }
+            }
+        } else if (live) {
+            float4* arow = reinterpret_cast<float4*>(jb.A + (uint64_t)i * R);
+#pragma unroll
+            for (int q = 0; q < R / 4; ++q)
+                arow[q] = make_float4((float)(x[4 * q] * sscale[4 * q]), (float)(x[4 * q + 1] * sscale[4 * q + 1]),
+                                      (float)(x[4 * q + 2] * sscale[4 * q + 2]),
+                                      (float)(x[4 * q + 3] * sscale[4 * q + 3]));
+        }
+    }
+    if (op == 0) {
+        if constexpr (kRegSums) {
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                double t = colsq[c];
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+                if (lane == 0) swave[wave][c] = t;
+            }
+        }
+        __syncthreads();
+        if (tid < R) {
+            double t = 0.0;
+            for (int w = 0; w < kWaves; ++w) t += swave[w][tid];
+            jb.part[(uint64_t)blk * R + tid] = t;
+        }
     }
 }
 
@@ -518,9 +694,19 @@ hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, 
     return hipGetLastError();
 }
 
-hipError_t als_normal_eq_inverse(const InvJob* jobs, int count, int N, int skip, int R, int reset_flag, hipStream_t s)
+hipError_t als_normal_eq_inverse(const InvJob* jobs, int count, int N, int skip, int R, int reset_flag, int solve,
+                                 hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
+    if (solve == 1) {
+        switch (R) {
+            case 16: hipLaunchKernelGGL(normal_eq_cholesky_kernel<16>, dim3(count), dim3(kWG), 0, s, jobs, N, skip, reset_flag); break;
+            case 32: hipLaunchKernelGGL(normal_eq_cholesky_kernel<32>, dim3(count), dim3(kWG), 0, s, jobs, N, skip, reset_flag); break;
+            case 64: hipLaunchKernelGGL(normal_eq_cholesky_kernel<64>, dim3(count), dim3(kWG), 0, s, jobs, N, skip, reset_flag); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (R) {
         case 16: hipLaunchKernelGGL(normal_eq_inverse_kernel<16>, dim3(count), dim3(kWG), 0, s, jobs, N, skip, reset_flag); break;
         case 32: hipLaunchKernelGGL(normal_eq_inverse_kernel<32>, dim3(count), dim3(kWG), 0, s, jobs, N, skip, reset_flag); break;
@@ -550,6 +736,12 @@ struct Launch {
 
 // R = 16 and 32 run on the FP64 matrix cores; R = 64 on the vector units.
 template <int R>
+void launch_solve(const Launch& L, int op, hipStream_t s)
+{
+    hipLaunchKernelGGL(chol_solve_kernel<R>, dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work, op);
+}
+
+template <int R>
 void launch_mw(const Launch& L, int op, hipStream_t s)
 {
     if constexpr (R <= 32)
@@ -576,15 +768,18 @@ void launch_reduce(const Launch& L, int K, int which, hipStream_t s)
 }  // namespace
 
 hipError_t als_solve_normalize_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork,
-                                    int count, int R, hipStream_t s)
+                                    int count, int R, int solve, hipStream_t s)
 {
     const Launch L{single, jobs, work, nwork, count};
     if (L.grid() == 0) return hipSuccess;
     for (int op = 0; op < 2; ++op) {
-        switch (R) {
-            case 16: launch_mw<16>(L, op, s); break;
-            case 32: launch_mw<32>(L, op, s); break;
-            case 64: launch_mw<64>(L, op, s); break;
+        switch (R * 2 + (solve == 1 ? 1 : 0)) {
+            case 32: launch_mw<16>(L, op, s); break;
+            case 64: launch_mw<32>(L, op, s); break;
+            case 128: launch_mw<64>(L, op, s); break;
+            case 33: launch_solve<16>(L, op, s); break;
+            case 65: launch_solve<32>(L, op, s); break;
+            case 129: launch_solve<64>(L, op, s); break;
             default: return hipErrorInvalidValue;
         }
         if (op == 0) launch_reduce(L, R, 0, s);

@@ -190,6 +190,7 @@ void mttkrp_opts_default(mttkrp_opts* o)
     o->part_threads = 0;
     o->part_gathers = 0;
     o->relabel = 0;
+    o->als_solve = 0;
 }
 
 const char* mttkrp_last_error(void) { return g_err.c_str(); }
@@ -212,6 +213,7 @@ static mttkrp_status check_opts(const mttkrp_opts* in, mttkrp_opts* o)
          !mk::tuned_shape_supported(o->part_threads ? o->part_threads : 512, o->part_gathers ? o->part_gathers : 4)))
         return fail(MTTKRP_EINVAL, "part_threads must be 0, 256, 512 or 1024 and part_gathers 0, 2 or 4");
     if (o->relabel != 0 && o->relabel != 1) return fail(MTTKRP_EINVAL, "relabel must be 0 or 1");
+    if (o->als_solve != 0 && o->als_solve != 1) return fail(MTTKRP_EINVAL, "als_solve must be 0 or 1");
     if (o->hot_steps) {
         o->partitioner = MTTKRP_PART_NNZ;   // step copies carry their own hot rows and partitions
         o->hot_rows = 0;
@@ -981,7 +983,7 @@ static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* l
     hipError_t e = hipSuccess;
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         const uint32_t I = h->dims[n];
-        e = mk::als_normal_eq_inverse(w.job, 1, N, n, R, reset_flag && n == 0, stream);
+        e = mk::als_normal_eq_inverse(w.job, 1, N, n, R, reset_flag && n == 0, h->opts.als_solve, stream);
         if (e == hipSuccess) {
             const void* fac[MTTKRP_MAX_MODES];
             for (int m = 0; m < N; ++m)
@@ -990,7 +992,7 @@ static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* l
             if (st) return st;
         }
         mk::DenseJob j = dense_job(h, factors[n], n, R);
-        if (e == hipSuccess) e = mk::als_solve_normalize_jobs(j, nullptr, nullptr, 0, 1, R, stream);
+        if (e == hipSuccess) e = mk::als_solve_normalize_jobs(j, nullptr, nullptr, 0, 1, R, h->opts.als_solve, stream);
         if (e == hipSuccess) e = mk::als_gram_jobs(j, nullptr, nullptr, 0, 1, R, stream);
         if (e == hipSuccess && bf16) e = mk::cast_bf16(factors[n], (uint64_t)I * R, w.bf16[n], stream);
     }
@@ -1063,6 +1065,7 @@ struct mttkrp_batch {
     uint32_t nfix_work[MTTKRP_MAX_MODES] = {};
     uint32_t grid_part = 0, grid_fix = 0;
     int threads = 0, gathers = 0;                         // tuned partition-kernel shape (0: the default)
+    int als_solve = 0;                                    // the layouts' opts.als_solve (all the same)
     std::vector<const void*> last_ptrs[MTTKRP_MAX_MODES]; // pointers of the uploaded descriptors
     mk::InvJob* inv_jobs = nullptr;                       // device: every tensor's normal-equation inverse job
     mk::DenseJob* dense_jobs[MTTKRP_MAX_MODES + 1] = {};  // device: per mode (and [N]: fit) one job per tensor
@@ -1138,6 +1141,12 @@ static mttkrp_status batch_impl(const mttkrp_handle* layouts, int count, int R, 
             const mttkrp_handle h = b->hs[t];
             b->geo[n][t] = plan_nnz(h, h->nnz, N - 1, R, b->dtype);
             max_parts[t] = std::max(max_parts[t], b->geo[n][t].nparts);
+        }
+    b->als_solve = b->hs[0]->opts.als_solve;
+    for (int t = 1; t < count; ++t)
+        if (b->hs[t]->opts.als_solve != b->als_solve) {
+            delete b;
+            return fail(MTTKRP_EINVAL, "the layouts of a batch must share opts.als_solve");
         }
     // One launch runs every tensor: they must share the partition kernel's shape.
     b->threads = b->geo[0][0].threads;
@@ -1617,7 +1626,7 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
     }
     const mk::DenseJob none{};
     for (int n = 0; n < N && e == hipSuccess; ++n) {
-        e = mk::als_normal_eq_inverse(b->inv_jobs, C, N, n, R, 0, stream);
+        e = mk::als_normal_eq_inverse(b->inv_jobs, C, N, n, R, 0, b->als_solve, stream);
         if (e != hipSuccess) break;
         // The MTTKRP gathers the fp32 factors, or the handles' bf16 copies.
         std::vector<const void*> gather((size_t)C * N);
@@ -1627,7 +1636,8 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
                                                                     : static_cast<const void*>(factors[(size_t)t * N + m]);
         mttkrp_status st = batch_run_impl(b, n, gather.data(), b->dtype, outs.data(), stream);
         if (st) return st;
-        e = mk::als_solve_normalize_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R, stream);
+        e = mk::als_solve_normalize_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R,
+                                         b->als_solve, stream);
         if (e == hipSuccess)
             e = mk::als_gram_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R, stream);
         if (e == hipSuccess && b->dtype == MTTKRP_BF16)

@@ -144,7 +144,9 @@ struct AlsWork {
 hipError_t als_gram(const float* A, uint32_t I, int R, double* G_out, AlsWork& w, hipStream_t s);
 hipError_t als_hadamard(const double* grams, int N, int skip, int R, double* V, double* flag, int reset_flag,
                         hipStream_t s);
-hipError_t als_normal_eq_inverse(const InvJob* jobs, int count, int N, int skip, int R, int reset_flag, hipStream_t s);
+// solve 0: W = V^{-1} (sweep operator); 1: W = V's Cholesky factor L.
+hipError_t als_normal_eq_inverse(const InvJob* jobs, int count, int N, int skip, int R, int reset_flag, int solve,
+                                 hipStream_t s);
 
 // The row passes of one mode update of one tensor (a "job"): A = M W with
 // column norms into lam and A normalised; the Gram matrix of A; the fit.
@@ -170,8 +172,9 @@ struct DenseJob {
     int N;
 };
 void plan_dense_blocks(uint32_t I, int max_blocks, DenseJob& j);
+// solve: as als_normal_eq_inverse, for the W the jobs hold (0: M W; 1: substitution with L).
 hipError_t als_solve_normalize_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork,
-                                    int count, int R, hipStream_t s);
+                                    int count, int R, int solve, hipStream_t s);
 hipError_t als_gram_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
                          int R, hipStream_t s);
 hipError_t als_fit_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,

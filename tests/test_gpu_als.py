@@ -32,9 +32,9 @@ def normal_eq_residual(A_new, V, M):
     return float(res), lam
 
 
-def run_sweeps(t, R, iters, dtype=capi.MTTKRP_FP32, seed=0, check=True, tol=2e-5):
+def run_sweeps(t, R, iters, dtype=capi.MTTKRP_FP32, seed=0, check=True, tol=2e-5, als_solve=0):
     F0 = workloads.random_factors(t.dims, R, seed=seed)
-    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, factor_dtype=dtype))
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, factor_dtype=dtype, als_solve=als_solve))
     dF = gu.dev_factors(F0)
     lam = torch.empty(R, dtype=torch.float64, device="cuda")
     fit = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -226,3 +226,106 @@ def test_ill_conditioned_normal_equations():
     print(f"  normal-equation residual {res:.2e}, |dA|/|A| vs Cholesky {err:.2e}", flush=True)
     assert res <= 2e-5
     assert err <= cond * 1e-14 + 1e-6
+
+
+# ---- the opt-in Cholesky solve (opts.als_solve = 1) ----
+
+@pytest.mark.parametrize("R", [16, 32, 64])
+def test_cholesky_solve_sweeps_teacher_forced(R):
+    """Cholesky factor and per-row substitution: every mode update satisfies
+    the oracle's normal equations, unit column norms, the fit formula."""
+    print("case als cholesky", R, flush=True)
+    t = workloads.random_tensor((400, 300, 200, 60), 40_000, dist="zipf", s=1.2, seed=41)
+    run_sweeps(t, R, iters=2, als_solve=1)
+
+
+def test_cholesky_solve_trajectory_matches_oracle_and_default():
+    print("case als cholesky trajectory", flush=True)
+    t = workloads.random_tensor((1000, 800, 600), 100_000, seed=1)
+    R = 16
+    chol = run_sweeps(t, R, iters=5, check=False, als_solve=1)
+    sweep = run_sweeps(t, R, iters=5, check=False, als_solve=0)
+    st = oracle.cp_als(t.idx, t.val, t.dims, workloads.random_factors(t.dims, R, seed=0), n_iter=5, threads=8)
+    assert np.max(np.abs(np.array(chol) - np.array(st.fits))) <= 1e-5
+    assert np.max(np.abs(np.array(chol) - np.array(sweep))) <= 1e-6
+
+
+def test_cholesky_solve_not_spd_reported():
+    print("case als cholesky not spd", flush=True)
+    t = workloads.random_tensor((300, 200, 100), 5000, seed=4)
+    R = 16
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, als_solve=1))
+    dF = [torch.rand((d, 1), device="cuda").repeat(1, R).contiguous() for d in t.dims]
+    lam = torch.empty(R, dtype=torch.float64, device="cuda")
+    capi.cpd_als_init(h, dF, R)
+    with pytest.raises(capi.MttkrpError) as e:
+        capi.cpd_als_iter(h, dF, lam, R)
+    assert e.value.status == capi.MTTKRP_ENOTSPD
+    h.free()
+
+
+def test_cholesky_solve_ill_conditioned_matches_oracle_solve():
+    """cond(V) ~ 6e6: the substitution solve of the GPU's own M agrees with the
+    oracle's Cholesky solve to cond(V) * 1e-14 + 1e-6."""
+    print("case als cholesky ill-conditioned", flush=True)
+    t = workloads.random_tensor((900, 700, 500), 50_000, seed=31)
+    R = 16
+    rng = np.random.default_rng(32)
+    F0 = []
+    for d in t.dims:
+        base = rng.uniform(0.5, 1.0, (d, 1))
+        F0.append((base + 1e-3 * rng.standard_normal((d, R))).astype(np.float32))
+    F64 = [f.astype(np.float64) for f in F0]
+    V = oracle.hadamard_of_grams([oracle.gram(f) for f in F64], skip=0)
+    cond = float(np.linalg.cond(V))
+    h = capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, als_solve=1))
+    dF = gu.dev_factors(F0)
+    M = gu.gpu_mttkrp(h, 0, dF, R).astype(np.float64)
+    A_ref, _ = oracle.normalize_columns(oracle.solve_mode(M, V))
+    lam = torch.empty(R, dtype=torch.float64, device="cuda")
+    capi.cpd_als_init(h, dF, R)
+    capi.cpd_als_iter(h, dF, lam, R)
+    torch.cuda.synchronize()
+    h.free()
+    A0 = dF[0].cpu().numpy().astype(np.float64)
+    res, _ = normal_eq_residual(A0, V, M)
+    err = float(np.linalg.norm(A0 - A_ref) / np.linalg.norm(A_ref))
+    print(f"  cond {cond:.2e}, residual {res:.2e}, |dA|/|A| vs oracle {err:.2e}", flush=True)
+    assert res <= 2e-5
+    assert err <= cond * 1e-14 + 1e-6
+
+
+def test_cholesky_solve_batch_bitwise_single():
+    """Batched CP-ALS sweeps with the Cholesky solve are bitwise the single
+    sweeps; a batch mixing the two solves is refused."""
+    print("case als cholesky batch", flush=True)
+    R = 32
+    ts = [workloads.random_tensor((300 + 50 * i, 200, 150), 8000 + 3000 * i, seed=60 + i) for i in range(4)]
+    F0 = [workloads.random_factors(t.dims, R, seed=70 + i) for i, t in enumerate(ts)]
+    hs = [capi.mttkrp_layout_build(t.idx, t.val, t.dims, opts=dict(max_R=R, als_solve=1)) for t in ts]
+    dF = [gu.dev_factors(f) for f in F0]
+    lam = [torch.empty(R, dtype=torch.float64, device="cuda") for _ in ts]
+    fit = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in ts]
+    for h, d in zip(hs, dF):
+        capi.cpd_als_init(h, d, R)
+    b = capi.mttkrp_batch_create(hs, R)
+    for _ in range(2):
+        capi.cpd_als_batch_iter_async(b, dF, lam, fit)
+    torch.cuda.synchronize()
+    b.free()
+    for i, (t, h) in enumerate(zip(ts, hs)):
+        d = gu.dev_factors(F0[i])
+        l1 = torch.empty(R, dtype=torch.float64, device="cuda")
+        f1 = torch.empty(1, dtype=torch.float64, device="cuda")
+        capi.cpd_als_init(h, d, R)
+        for _ in range(2):
+            capi.cpd_als_iter(h, d, l1, R, f1)
+        assert float(f1.item()) == float(fit[i].item()), i
+        for a, c in zip(d, dF[i]):
+            assert torch.equal(a, c), i
+    plain = capi.mttkrp_layout_build(ts[0].idx, ts[0].val, ts[0].dims, opts=dict(max_R=R))
+    with pytest.raises(capi.MttkrpError):
+        capi.mttkrp_batch_create([hs[0], plain], R)
+    plain.free()
+    for h in hs:
+        h.free()

@@ -560,6 +560,54 @@ def bench_paper_shapes(args, R=32):
     return res
 
 
+def fiber_stats(t, R, shapes=((32, 256), (8, 512)), cus=256, L=4):
+    """How much factor-row reuse over fibers the mode copies offer (an
+    analysis on the host; no GPU).  In the mode-n copy, sorted by i_n and then
+    cyclically by the other indices, a fiber is a run of nonzeros sharing
+    (i_n, i_(n+1)); every nonzero of a fiber gathers the same row of the
+    next factor.  Per mode:
+    * fibers, their mean length and their nonzero-weighted mean length;
+    * `whole_wave_skip`: on the partition kernel's layout (each lane group
+      takes a run of gsz consecutive nonzeros, 64 / lanes-per-row groups per
+      wave), the fraction of wave steps at which no group starts a fiber, so
+      that the wave could skip the (n+1) gather instruction; gsz follows the
+      library's partition geometry for the given (partitions per CU, workgroup
+      threads) shapes;
+    * `split_gathers_per_nnz`: row gathers per nonzero if each fiber's
+      nonzeros were dealt into segments of L sharing one (n+1) row, the
+      remainder kept as single nonzeros, against N - 1 today."""
+    idx = t.idx
+    nnz, N = idx.shape
+    lanes = max(1, R * 4 // 16)
+    G = 64 // lanes
+    out = {"groups_per_wave": G, "segment_nonzeros": L, "modes": []}
+    for n in range(N):
+        m = (n + 1) % N
+        key = np.sort(idx[:, n].astype(np.int64) * int(t.dims[m]) + idx[:, m])
+        start = np.ones(nnz, dtype=bool)
+        start[1:] = key[1:] != key[:-1]
+        lens = np.diff(np.append(np.flatnonzero(start), nnz))
+        segs = int((lens // L).sum())
+        gathers = (nnz - segs * L) * (N - 1) + segs * (1 + L * (N - 2))
+        skip = {}
+        for ppc, threads in shapes:
+            groups = threads // lanes
+            per = -(-nnz // (ppc * cus * groups))
+            gsz = max(32, -(-per // 32) * 32)
+            W = nnz // (G * gsz)       # whole waves
+            frac = None
+            if W:
+                f = start[: W * G * gsz].reshape(W, G, gsz).copy()
+                f[:, :, 0] = True
+                frac = round(float(1.0 - f.any(axis=1).mean()), 4)
+            skip[f"{ppc}/{threads}"] = {"gsz": gsz, "fraction": frac}
+        out["modes"].append({"fibers": int(len(lens)), "mean_len": round(nnz / len(lens), 2),
+                             "nnz_weighted_mean_len": round(float((lens.astype(np.float64) ** 2).sum() / nnz), 1),
+                             "whole_wave_skip": skip,
+                             "split_gathers_per_nnz": round(gathers / nnz, 3)})
+    return out
+
+
 def _serve_tensor(spec):
     t = spec.tensor()
     return t.idx, t.val, t.dims, t.nnz
@@ -723,6 +771,9 @@ def main(argv=None):
                     help="device memory the serving loop may admit jobs into (serve-poisson)")
     ap.add_argument("--serve-build-threads", type=int, default=4,
                     help="worker threads for layout builds in the continuous-batching server")
+    ap.add_argument("--fiber-stats", action="store_true",
+                    help="only print, for the workload's tensor, how much factor-row reuse over fibers its "
+                         "mode copies offer (host analysis, no GPU)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB, 5 times (to calibrate "
                          "the HBM byte counters against a kernel of known traffic)")
@@ -732,6 +783,16 @@ def main(argv=None):
         print("bench.py measures one GPU only: the library runs on one device "
               "(the design notes describe how the path would shard).", file=sys.stderr)
         return 2
+
+    if args.fiber_stats:
+        import workloads
+
+        wl = WORKLOADS[args.workload]
+        if not wl["tensor"]:
+            raise SystemExit("--fiber-stats needs a single-tensor workload")
+        t = workloads.named_tensor(wl["tensor"])
+        print(json.dumps({"workload": args.workload, "fiber_stats": fiber_stats(t, wl["R"])}))
+        return 0
 
     import torch
 

@@ -485,14 +485,19 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c)
 // M[row lr][16h + 4lq .. +3] as one 16-byte load; its j-th value is the
 // A operand of k-step 4h + j, whose k index lq stands for k = 16h + 4lq + j,
 // so the B operand of that step is W[16h + 4lq + j][16t + lr].
-template <int R>
+// GRAM (with op 1): the store pass also adds the Gram partials of the
+// stored rows.  Item q of a column tile's result is row tile + lq + 4q,
+// column 16t + lr of A: for each q that is exactly the operand a Gram
+// matrix-core step over those 4 rows takes (as in gram_mfma_kernel), so
+// A^T A needs no second pass over A.
+template <int R, bool GRAM = false>
 __global__ __launch_bounds__(kWG) void mw_mfma_kernel(DenseJob single, const DenseJob* __restrict__ jobs,
                                                       const uint2* __restrict__ work, int op)
 {
     static_assert(R == 16 || R == 32, "matrix-core row pass for R = 16 or 32");
     constexpr int CT = R / 16;   // column tiles
     constexpr int H = R / 16;    // 16-wide k chunks
-    __shared__ double sred[R * 16];
+    __shared__ double sred[GRAM ? 4 * R * R : R * 16];
     uint32_t blk;
     const DenseJob& jb = pick_job(single, jobs, work, blk);
     const float* __restrict__ M = jb.M;
@@ -513,6 +518,13 @@ __global__ __launch_bounds__(kWG) void mw_mfma_kernel(DenseJob single, const Den
         inv[t] = op == 1 ? 1.0 / jb.lam[16 * t + lr] : 0.0;
         colsq[t] = 0.0;
     }
+    f64x4 gacc[CT][CT];
+    if constexpr (GRAM) {
+#pragma unroll
+        for (int a = 0; a < CT; ++a)
+#pragma unroll
+            for (int b = 0; b < CT; ++b) gacc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
     uint32_t r0, r1;
     block_rows(jb.I, jb.rpb, blk, r0, r1);
     for (uint32_t tile = r0 + 16u * wave; tile < r1; tile += 64u) {
@@ -530,16 +542,52 @@ __global__ __launch_bounds__(kWG) void mw_mfma_kernel(DenseJob single, const Den
 #pragma unroll
                 for (int t = 0; t < CT; ++t) acc[t] = mfma_f64(a[j], wf[h][j][t], acc[t]);
         }
-#pragma unroll
-        for (int t = 0; t < CT; ++t)
+        if constexpr (GRAM) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t rr = tile + lq + 4 * q;
-                if (rr < r1) {
-                    if (op == 0) colsq[t] += acc[t][q] * acc[t][q];
-                    else jb.A[(uint64_t)rr * R + 16 * t + lr] = (float)(acc[t][q] * inv[t]);
+                double x[CT];
+#pragma unroll
+                for (int t = 0; t < CT; ++t) {
+                    x[t] = 0.0;
+                    if (rr < r1) {
+                        const float v = (float)(acc[t][q] * inv[t]);
+                        jb.A[(uint64_t)rr * R + 16 * t + lr] = v;
+                        x[t] = (double)v;
+                    }
                 }
+#pragma unroll
+                for (int a = 0; a < CT; ++a)
+#pragma unroll
+                    for (int b = 0; b < CT; ++b) gacc[a][b] = mfma_f64(x[a], x[b], gacc[a][b]);
             }
+        } else {
+#pragma unroll
+            for (int t = 0; t < CT; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t rr = tile + lq + 4 * q;
+                    if (rr < r1) {
+                        if (op == 0) colsq[t] += acc[t][q] * acc[t][q];
+                        else jb.A[(uint64_t)rr * R + 16 * t + lr] = (float)(acc[t][q] * inv[t]);
+                    }
+                }
+        }
+    }
+    if constexpr (GRAM) {
+        // The four waves' tiles, added in a fixed order.
+#pragma unroll
+        for (int a = 0; a < CT; ++a)
+#pragma unroll
+            for (int b = 0; b < CT; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    sred[wave * R * R + (16 * a + lq + 4 * q) * R + 16 * b + lr] = gacc[a][b][q];
+        __syncthreads();
+        for (int e = threadIdx.x; e < R * R; e += kWG)
+            jb.part[(uint64_t)blk * R * R + e] =
+                ((sred[e] + sred[R * R + e]) + sred[2 * R * R + e]) + sred[3 * R * R + e];
+        return;
     }
     if (op == 0) {
         // Column c = 16t + lr: 16 partials (4 waves x 4 lane quarters), added in a fixed order.
@@ -784,6 +832,30 @@ hipError_t als_solve_normalize_jobs(const DenseJob& single, const DenseJob* jobs
         }
         if (op == 0) launch_reduce(L, R, 0, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t als_solve_normalize_gram_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work,
+                                         uint32_t nwork, int count, int R, int solve, hipStream_t s)
+{
+    if (solve == 1 || R > 32) {
+        const hipError_t e = als_solve_normalize_jobs(single, jobs, work, nwork, count, R, solve, s);
+        return e != hipSuccess ? e : als_gram_jobs(single, jobs, work, nwork, count, R, s);
+    }
+    const Launch L{single, jobs, work, nwork, count};
+    if (L.grid() == 0) return hipSuccess;
+    if (R == 16) {
+        launch_mw<16>(L, 0, s);
+        launch_reduce(L, R, 0, s);
+        hipLaunchKernelGGL((mw_mfma_kernel<16, true>), dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work, 1);
+    } else if (R == 32) {
+        launch_mw<32>(L, 0, s);
+        launch_reduce(L, R, 0, s);
+        hipLaunchKernelGGL((mw_mfma_kernel<32, true>), dim3(L.grid()), dim3(kWG), 0, s, L.single, L.jobs, L.work, 1);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    launch_reduce(L, R * R, 1, s);
     return hipGetLastError();
 }
 

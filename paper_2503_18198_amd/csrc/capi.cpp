@@ -992,8 +992,8 @@ static mttkrp_status als_sweep(mttkrp_handle h, float* const* factors, double* l
             if (st) return st;
         }
         mk::DenseJob j = dense_job(h, factors[n], n, R);
-        if (e == hipSuccess) e = mk::als_solve_normalize_jobs(j, nullptr, nullptr, 0, 1, R, h->opts.als_solve, stream);
-        if (e == hipSuccess) e = mk::als_gram_jobs(j, nullptr, nullptr, 0, 1, R, stream);
+        if (e == hipSuccess)
+            e = mk::als_solve_normalize_gram_jobs(j, nullptr, nullptr, 0, 1, R, h->opts.als_solve, stream);
         if (e == hipSuccess && bf16) e = mk::cast_bf16(factors[n], (uint64_t)I * R, w.bf16[n], stream);
     }
     if (e == hipSuccess) {
@@ -1636,10 +1636,8 @@ mttkrp_status cpd_als_batch_iter_async(mttkrp_batch_handle b, float* const* fact
                                                                     : static_cast<const void*>(factors[(size_t)t * N + m]);
         mttkrp_status st = batch_run_impl(b, n, gather.data(), b->dtype, outs.data(), stream);
         if (st) return st;
-        e = mk::als_solve_normalize_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R,
-                                         b->als_solve, stream);
-        if (e == hipSuccess)
-            e = mk::als_gram_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R, stream);
+        e = mk::als_solve_normalize_gram_jobs(none, b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], C, R,
+                                              b->als_solve, stream);
         if (e == hipSuccess && b->dtype == MTTKRP_BF16)
             e = mk::cast_bf16_jobs(b->dense_jobs[n], b->dense_work[n], b->ndense_work[n], R, stream);
     }

@@ -177,6 +177,10 @@ hipError_t als_solve_normalize_jobs(const DenseJob& single, const DenseJob* jobs
                                     int count, int R, int solve, hipStream_t s);
 hipError_t als_gram_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
                          int R, hipStream_t s);
+// als_solve_normalize_jobs followed by als_gram_jobs; for R = 16 and 32 with
+// the V^{-1} solve the Gram partials come from the store pass itself.
+hipError_t als_solve_normalize_gram_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work,
+                                         uint32_t nwork, int count, int R, int solve, hipStream_t s);
 hipError_t als_fit_jobs(const DenseJob& single, const DenseJob* jobs, const uint2* work, uint32_t nwork, int count,
                         int R, hipStream_t s);
 hipError_t cast_bf16(const float* A, uint64_t n, uint16_t* out, hipStream_t s);

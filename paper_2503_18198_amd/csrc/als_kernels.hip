@@ -139,7 +139,8 @@ __global__ __launch_bounds__(kWG) void hadamard_kernel(const double* __restrict_
 // squared diagonal of V's Cholesky factor, so a pivot that is not positive
 // beyond rounding (relative to V_kk) means V is not SPD to working precision:
 // then *flag = 1 and W is filled with NaN.  Each sweep updates all R^2
-// entries in parallel (read, barrier, write, barrier).
+// entries in parallel from one LDS copy of A into the other, so one barrier
+// per sweep separates it from the next.
 //
 // One workgroup per job: job b first forms its V = Hadamard product of the
 // Gram matrices of every mode but `skip` (kept in LDS and stored to V), then
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(kWG) void normal_eq_inverse_kernel(const InvJob* __
 {
     constexpr int RR = R * R;
     constexpr int kPer = (RR + kWG - 1) / kWG;   // entries per thread
-    __shared__ double A[RR];
+    __shared__ double Abuf[2][RR];
     __shared__ double diag0[R];
     const InvJob jb = jobs[blockIdx.x];
     const int tid = threadIdx.x;
@@ -158,14 +159,16 @@ __global__ __launch_bounds__(kWG) void normal_eq_inverse_kernel(const InvJob* __
         double v = 1.0;
         for (int m = 0; m < N; ++m)
             if (m != skip) v *= jb.grams[(uint64_t)m * RR + e];
-        A[e] = v;
+        Abuf[0][e] = v;
         jb.V[e] = v;
     }
     __syncthreads();
-    if (tid < R) diag0[tid] = A[tid * R + tid];
+    if (tid < R) diag0[tid] = Abuf[0][tid * R + tid];
     __syncthreads();
     bool bad = false;   // every thread tests the same pivots, so this is uniform
     for (int k = 0; k < R; ++k) {
+        const double* A = Abuf[k & 1];
+        double* An = Abuf[(k + 1) & 1];
         double d = A[k * R + k];
         if (!(d > 64.0 * 2.220446049250313e-16 * fabs(diag0[k])) || !isfinite(d)) {
             bad = true;
@@ -188,14 +191,14 @@ __global__ __launch_bounds__(kWG) void normal_eq_inverse_kernel(const InvJob* __
                 else nv[q] = A[e] - aik * akj * inv;
             }
         }
-        __syncthreads();
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int e = tid + q * kWG;
-            if (e < RR) A[e] = nv[q];
+            if (e < RR) An[e] = nv[q];
         }
         __syncthreads();
     }
+    const double* A = Abuf[R & 1];
     for (int e = tid; e < RR; e += kWG) jb.W[e] = bad ? __longlong_as_double(0x7ff8000000000000ll) : -A[e];
     if (tid == 0) {
         if (reset_flag) *jb.flag = 0.0;
